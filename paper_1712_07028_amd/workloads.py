@@ -1,0 +1,175 @@
+"""Seeded synthetic workloads of the free-surface liquid-gas-solid runs.
+
+This module only generates inputs: box sizes, physical parameters and the
+seeded random particle beds.  It holds none of the method's arithmetic and is
+shared by the library tests, the oracle tests and the benchmark, so that both
+implementations start from the same description.
+
+The workloads follow the shapes of the paper's experiments: a liquid column
+with a flat free surface, one spherical gas bubble near the bottom and a random
+homogeneous bed of rigid spheres (Sec. 4.1 and 4.2: bubble in a particle bed,
+bubble-induced particle mixing), plus a fully liquid periodic window with
+moving spheres for the differentiation form.
+"""
+from __future__ import annotations
+
+import dataclasses
+from dataclasses import dataclass, field
+
+import numpy as np
+
+STORAGE_F32, STORAGE_F16S, STORAGE_BF16S = 0, 1, 2
+
+
+@dataclass
+class Particles:
+    x: np.ndarray  # (n,3) float64 centres in node coordinates
+    u: np.ndarray  # (n,3) velocities
+    omega: np.ndarray  # (n,3) angular velocities
+    R: np.ndarray  # (n,) radii
+    rho_p: np.ndarray  # (n,) specific densities
+
+    @property
+    def n(self) -> int:
+        return int(self.R.shape[0])
+
+
+@dataclass
+class Workload:
+    name: str
+    n: tuple
+    trt: bool
+    tau: float
+    g: tuple
+    zs: float
+    steps: int
+    periodic: tuple = (0, 0, 0)
+    magic: float = 3.0 / 16.0
+    rho_g0: float = 1.0
+    gas_spheres: list = field(default_factory=list)  # (cx, cy, cz, r, rho_g)
+    eps_c: float = 1e-6
+    integrate: bool = True
+    n_sub: int = 10
+    storage: int = STORAGE_F32
+    particles: Particles | None = None
+
+    @property
+    def cells(self) -> int:
+        return int(self.n[0]) * int(self.n[1]) * int(self.n[2])
+
+    def replace(self, **kw) -> "Workload":
+        return dataclasses.replace(self, **kw)
+
+
+def _draw_centres(rng, lo, hi, count):
+    """count candidate centres, uniform per axis in [lo, hi]."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    return lo + (hi - lo) * rng.random((count, 3))
+
+
+def rsa_spheres(n_target, R, box, zs, bubble=None, seed=0, gap=1.0, max_draws=None,
+                batch=4096):
+    """Random sequential addition of equal spheres.
+
+    Candidate centres are uniform in [R+1, n-R-2] horizontally and in
+    [R+1, top-R-2] vertically (top = zs, or the box height for a fully liquid box);
+    a candidate is rejected when its surface gap to an accepted sphere is below
+    ``gap`` or when it lies within R_b + R + 1 of the bubble centre.  Candidates
+    are tested in draw order against every sphere accepted before them, so the
+    result equals a one-by-one RSA with numpy.random.Generator(PCG64(seed)).
+    """
+    from scipy.spatial import cKDTree
+
+    rng = np.random.Generator(np.random.PCG64(seed))
+    top = zs if zs >= 0 else box[2]
+    lo = [R + 1, R + 1, R + 1]
+    hi = [box[0] - R - 2, box[1] - R - 2, top - R - 2]
+    dmin = 2 * R + gap
+    acc = np.empty((0, 3))
+    draws = 0
+    max_draws = max_draws or 200 * n_target + 10000
+    while acc.shape[0] < n_target and draws < max_draws:
+        cand = _draw_centres(rng, lo, hi, batch)
+        draws += batch
+        ok = np.ones(batch, dtype=bool)
+        if bubble is not None:
+            bc, bR = np.asarray(bubble[:3], dtype=np.float64), float(bubble[3])
+            ok &= np.linalg.norm(cand - bc, axis=1) >= bR + R + 1
+        if acc.shape[0]:
+            d, _ = cKDTree(acc).query(cand, k=1, distance_upper_bound=dmin)
+            ok &= ~(d < dmin)
+        idx = np.nonzero(ok)[0]
+        if idx.size == 0:
+            continue
+        sub = cand[idx]
+        pairs = cKDTree(sub).query_pairs(dmin, output_type="ndarray")
+        conflicts = [[] for _ in range(idx.size)]
+        for a, b in pairs:
+            if np.linalg.norm(sub[a] - sub[b]) < dmin:
+                lo_i, hi_i = (a, b) if a < b else (b, a)
+                conflicts[hi_i].append(lo_i)
+        keep = np.zeros(idx.size, dtype=bool)
+        room = n_target - acc.shape[0]
+        for i in range(idx.size):
+            if room == 0:
+                break
+            if any(keep[j] for j in conflicts[i]):
+                continue
+            keep[i] = True
+            room -= 1
+        acc = np.vstack([acc, sub[keep]])
+    return acc[:n_target]
+
+
+def particle_bed(n, R, box, zs, bubble, seed, rho_p=2.5, vel_range=0.0):
+    x = rsa_spheres(n, R, box, zs, bubble=bubble, seed=seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    u = (rng.uniform(-vel_range, vel_range, size=x.shape) if vel_range > 0
+         else np.zeros_like(x))
+    return Particles(x=x, u=u, omega=np.zeros_like(x), R=np.full(x.shape[0], float(R)),
+                     rho_p=np.full(x.shape[0], float(rho_p)))
+
+
+def bubble_column_small():
+    """32^3 pool to z=24, bubble R=6 at (16,16,10), SRT tau=0.6, g=1e-5, no particles."""
+    return Workload(name="pool32_bubble6_srt", n=(32, 32, 32), trt=False, tau=0.6,
+                    g=(0.0, 0.0, -1e-5), zs=24.0, steps=200,
+                    gas_spheres=[(16.0, 16.0, 10.0, 6.0, 1.0)])
+
+
+def bubble_bed_128(n_particles=1400, storage=STORAGE_F32):
+    """128^3 pool to z=110, bubble R=12 at (64,64,24), 1,400 spheres R=4 (rho 2.5)."""
+    bub = (64.0, 64.0, 24.0, 12.0, 1.0)
+    parts = particle_bed(n_particles, 4.0, (128, 128, 128), 110.0, bub, seed=2)
+    return Workload(name="bed128_bubble12_1400spheres", n=(128, 128, 128), trt=True,
+                    tau=0.55, g=(0.0, 0.0, -2e-5), zs=110.0, steps=1000,
+                    gas_spheres=[bub], particles=parts, storage=storage)
+
+
+def bubble_column_large(n_particles=100_000, nz=1024, zs=980.0):
+    """512x512x1024 pool to z=980, bubble R=40 at (256,256,64), 1e5 spheres R=5."""
+    bub = (256.0, 256.0, 64.0, 40.0, 1.0)
+    parts = particle_bed(n_particles, 5.0, (512, 512, nz), zs, bub, seed=3)
+    return Workload(name="column512x512x1024_bubble40_100k_spheres", n=(512, 512, nz),
+                    trt=True, tau=0.55, g=(0.0, 0.0, -2e-5), zs=zs, steps=500,
+                    gas_spheres=[bub], particles=parts)
+
+
+def adjoint_window(n=64, n_particles=20):
+    """Fully liquid periodic n^3 window, 20 spheres R=4 moving with U(-0.01,0.01)^3."""
+    parts = particle_bed(n_particles, 4.0, (n, n, n), -1.0, None, seed=5, vel_range=0.01)
+    return Workload(name=f"window{n}_periodic_{n_particles}spheres", n=(n, n, n), trt=True,
+                    tau=0.6, g=(0.0, 0.0, -1e-5), zs=-1.0, steps=200, periodic=(1, 1, 1),
+                    integrate=False, particles=parts)
+
+
+def slab_of(w: Workload, nz: int) -> Workload:
+    """Same column cut to its lowest nz layers (keeps spheres whose box fits)."""
+    p = w.particles
+    if p is not None:
+        keep = p.x[:, 2] + p.R + 2 < nz
+        p = Particles(x=p.x[keep], u=p.u[keep], omega=p.omega[keep], R=p.R[keep],
+                      rho_p=p.rho_p[keep])
+    zs = w.zs if w.zs < nz else -1.0
+    return w.replace(n=(w.n[0], w.n[1], nz), particles=p, zs=zs)
