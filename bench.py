@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Throughput of the free-surface LBM hot path on one MI355X.
+
+One step = one full lattice update of the 512x512x1024 bubble column with 1e5
+spheres (fused stream-collide with free-surface and particle boundaries, cell
+conversions, bubble model, particle update and coverage).  Prints one JSON line:
+box MLUPS (all box cells counted), the HBM roofline of the dominant kernel
+(timed with HIP events on the library's stream) and the FP64 oracle timed on a
+bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "FSLBM MLUPS + achieved HBM GB/s vs peak; FP16-storage and adjoint MLUPS"
+STORAGES = {"f32": 0, "f16s": 1, "bf16s": 2}
+DTYPE = {0: "f32", 1: "f16-shifted storage, f32 arithmetic", 2: "bf16-shifted storage, f32 arithmetic"}
+ELEM = {0: 4, 1: 2, 2: 2}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name, storage):
+    from paper_1712_07028_amd import workloads as W
+
+    if name == "column":
+        w = W.bubble_column_large()
+    elif name == "bed128":
+        w = W.bubble_bed_128()
+    elif name == "pool32":
+        w = W.bubble_column_small()
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return w.replace(storage=storage)
+
+
+def cpu_baseline(w, steps):
+    """The FP64 oracle on a bounded sample: the lowest 16 layers of the column."""
+    import oracle
+    from paper_1712_07028_amd import workloads as W
+
+    oracle.build(force=False)
+    threads = min(os.cpu_count() or 1, 16)
+    s = W.slab_of(w, 16) if w.n[2] > 16 else w
+    o = oracle.Oracle(s, n_threads=threads)
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    o.close()
+    return {"value": round(s.cells * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{s.n[0]}x{s.n[1]}x{s.n[2]} bottom slab of the column "
+                      f"({s.particles.n if s.particles is not None else 0} spheres), {steps} steps, FP64"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="column")
+    ap.add_argument("--storage", default="f32", choices=list(STORAGES))
+    ap.add_argument("--forms", action="store_true", help="also time f16s and bf16s storage")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--traffic", default=None,
+                    help="JSON file with measured HBM bytes per stream-collide launch")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the multi-GPU slab decomposition is design-only "
+              "in this build (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1712_07028_amd as fsl
+
+    if not torch.cuda.is_available():
+        print("no HIP device", file=sys.stderr)
+        sys.exit(1)
+    fsl.load_library()
+
+    st = STORAGES[args.storage]
+    t0 = time.perf_counter()
+    w = workload(args.workload, st)
+    log(f"workload {w.name}: {w.n}, {w.particles.n if w.particles is not None else 0} spheres "
+        f"(placement {time.perf_counter() - t0:.1f} s)")
+
+    def run(storage, steps, warmup, profile):
+        ww = w.replace(storage=storage)
+        sim = fsl.Sim(ww)
+        sim.step(warmup)
+        sim.sync()
+        flags = sim.get(fsl.FIELD_FLAGS)
+        n_active = int(((flags == fsl.LIQ) | (flags == fsl.IFC)).sum())
+        del flags
+        if profile:
+            sim.profile(True)
+            sim.profile_get()  # reset
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        sim.sync()
+        prof = sim.profile_get() if profile else None
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        return dt, n_active, prof
+
+    log(f"warmup {args.warmup}, timed {args.steps} steps, storage {args.storage}")
+    dt, n_active, prof = run(st, args.steps, args.warmup, True)
+    N = w.cells
+    mlups = N * args.steps / dt / 1e6
+    ms_sc, n_sc = prof["stream_collide"]
+    avg_s = ms_sc / max(n_sc, 1) / 1e3
+    alg_bytes = 2 * 19 * ELEM[st] * n_active + N  # populations in and out + cell types
+    achieved = alg_bytes / avg_s / 1e9
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "kernel": "k_stream_collide", "kernel_ms": round(avg_s * 1e3, 4),
+            "algorithmic_bytes_per_launch": int(alg_bytes), "active_cells": n_active}
+    breakdown = {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()}
+    log(f"{mlups:.0f} MLUPS, stream-collide {avg_s * 1e3:.3f} ms, {achieved:.0f} GB/s, "
+        f"breakdown ms/step {breakdown}")
+
+    forms = {}
+    if args.forms:
+        for name, s2 in (("f16s", 1), ("bf16s", 2)):
+            d2, na2, p2 = run(s2, args.steps, args.warmup, True)
+            ms2, n2 = p2["stream_collide"]
+            a2 = (2 * 19 * 2 * na2 + N) / (ms2 / max(n2, 1) / 1e3) / 1e9
+            forms[name] = {"mlups": round(N * args.steps / d2 / 1e6, 1),
+                           "speedup_vs_f32": round(dt / d2, 3), "stream_collide_GBs": round(a2, 1)}
+            log(name, forms[name])
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host")
+        cpu = cpu_baseline(w, args.cpu_steps)
+
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[st],
+        "data": "synthetic",
+        "config": {"workload": w.name, "box": list(w.n),
+                   "particles": w.particles.n if w.particles is not None else 0,
+                   "collision": "TRT" if w.trt else "SRT", "tau": w.tau,
+                   "storage": args.storage, "step_ms_breakdown": breakdown},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if forms:
+        out["forms"] = forms
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,186 @@
+/*
+ * fsl.h -- C ABI of the MI355X (gfx950) free-surface lattice Boltzmann library
+ * for liquid-gas-solid flow (Bogner, Harting & Ruede, "Direct simulation of
+ * liquid-gas-solid flow with a free surface lattice Boltzmann method").
+ *
+ * The library advances one simulation state on one GPU.  It never allocates
+ * device memory: the caller passes one device workspace of
+ * fsl_workspace_bytes(cfg) bytes and a HIP stream; every kernel runs on that
+ * stream.  The library allocates only its small host context (freed by
+ * fsl_destroy, which never frees the workspace).  Host arrays passed to the
+ * get/set calls are owned by the caller, row-major, FP64 unless stated.
+ *
+ * Problem statement (Sec. 2): the box is split into three disjoint regions
+ * (liquid, gas, solid).  Liquid is simulated by a D3Q19 lattice Boltzmann model
+ * (Sec. 2.1); the liquid-gas boundary is captured by fill levels and cell types
+ * (Sec. 2.2); every gas region (bubble) holds a constant gas mass that sets its
+ * pressure; spheres described by radius, density, position, velocity and
+ * angular velocity (Sec. 2.3) block the nodes they cover and couple through
+ * moving-wall bounce-back and momentum exchange.
+ *
+ * Conventions (shared with the oracle by specification):
+ *   cell index     i + nx*(j + ny*k); node (i,j,k) sits at (i,j,k); no-slip walls
+ *                  are half-way, at -1/2 and n-1/2 on non-periodic axes
+ *   directions     0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..18 = (+-1,+-1,0),
+ *                  (+-1,0,+-1), (0,+-1,+-1) in sign order (+,+),(+,-),(-,+),(-,-)
+ *   flag values    0 gas, 1 liquid, 2 interface, 3 particle-covered
+ *
+ * Error convention: every int-returning call returns FSL_OK (0) or a negative
+ * FSL_E_* code.  Errors raised inside kernels (list overflow, NaN, a liquid cell
+ * next to gas) are latched on the device and reported by the next synchronising
+ * call (fsl_sync, the get calls).  fsl_error_string gives the text of the last
+ * error.  No C++ exception crosses this boundary.
+ */
+#ifndef FSL_H
+#define FSL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FSL_OK 0
+#define FSL_E_ARG (-1)       /* invalid argument or configuration            */
+#define FSL_E_HIP (-2)       /* a HIP runtime call failed                     */
+#define FSL_E_CAPACITY (-3)  /* a conversion/event list or table overflowed   */
+#define FSL_E_NUMERIC (-4)   /* NaN/Inf density or a collapsed bubble volume  */
+#define FSL_E_INVARIANT (-5) /* a liquid cell has a gas neighbour             */
+
+#define FSL_NOSLIP 0
+#define FSL_PERIODIC 1
+
+#define FSL_SRT 0
+#define FSL_TRT 1
+
+/* population storage (form 1): FP32, or f - w_q stored as IEEE binary16 /
+ * bfloat16 (round to nearest even); the collision always runs in FP32 */
+#define FSL_STORE_F32 0
+#define FSL_STORE_F16S 1
+#define FSL_STORE_BF16S 2
+
+#define FSL_MAX_GAS_SPHERES 16
+
+typedef struct {
+    int n[3];                   /* box size in cells, each >= 1                       */
+    int boundary[3];            /* FSL_NOSLIP or FSL_PERIODIC per axis                */
+    int collision;              /* FSL_SRT or FSL_TRT                                 */
+    double tau;                 /* relaxation time, lambda_+ = -1/tau (Sec. 2.1)      */
+    double magic;               /* TRT constant Lambda (3/16 in the paper)            */
+    double g[3];                /* body-force acceleration, lattice units             */
+    double zs;                  /* pool height (node coordinates); < 0: fully liquid  */
+    double rho_g0;              /* gas density of the atmosphere above the pool      */
+    int n_gas_spheres;          /* spherical gas bubbles in the initial state         */
+    double gas_spheres[FSL_MAX_GAS_SPHERES][5]; /* cx, cy, cz, r, rho_g                */
+    int max_particles;          /* particle table capacity                            */
+    int n_sub;                  /* particle substeps per lattice step (10)            */
+    int integrate;              /* 1: particles move; 0: kinematic (fixed x, u, omega)*/
+    int storage;                /* FSL_STORE_*                                        */
+    double eps_c;               /* interface fills at phi >= 1-eps_c, empties at <= eps_c */
+    int list_capacity;          /* per-step conversion/event list capacity, 0 = auto  */
+    int max_bubbles;            /* bubble table capacity, 0 = auto (64)               */
+    int window_steps;           /* differentiation window length T (0 = no window)    */
+    int window_every;           /* checkpoint interval k of the window                */
+} fsl_config;
+
+typedef struct {
+    int id, alive;              /* alive: a root bubble (merged ones point to a root) */
+    double V, M, rho_g;         /* gas volume (cells), constant gas mass, M/V         */
+    double centroid[3];         /* gas-volume centroid                                */
+    double V0;                  /* volume at initialisation                           */
+    int64_t n_gas, n_iface;     /* gas and interface cells carrying the id            */
+} fsl_bubble;
+
+typedef struct fsl_ctx fsl_ctx;
+
+/* Bytes of device workspace needed for cfg; 0 if cfg is invalid. */
+size_t fsl_workspace_bytes(const fsl_config *cfg);
+
+/* Build the initial state (Sec. 2.2 cell types and fill levels of a flat pool
+ * with spherical gas bubbles, liquid at hydrostatic equilibrium) in the caller's
+ * workspace d_ws (device pointer, >= fsl_workspace_bytes(cfg) bytes, 256-byte
+ * aligned) and return a context bound to hip_stream (a hipStream_t, may be 0).
+ * The workspace must outlive the context.  FSL_E_ARG on a bad configuration. */
+int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, fsl_ctx **out);
+
+/* Enqueue n lattice steps on the stream (asynchronous).  One step: streaming with
+ * wall / moving-particle / free-surface reconstruction, moments, interface mass
+ * exchange, collision (Eqs. LBE1, LBE2, fsk, bbrule, massExchange, massExchangeb),
+ * momentum exchange (Eqs. netforce, torque), cell conversions, particle update
+ * (Eq. lubrication, substeps) and the bubble model. */
+int fsl_step(fsl_ctx *ctx, int n);
+
+/* Replace the particle table with n spheres (arrays n x 3: centres in node
+ * coordinates, velocities, angular velocities; n: radii, specific densities;
+ * u / omega may be NULL for zero) and recompute node coverage.  Newly covered
+ * cells hand their liquid mass to the ledger, uncovered cells are re-initialised.
+ * FSL_E_ARG if n > max_particles. */
+int fsl_particles_set(fsl_ctx *ctx, int n, const double *x, const double *u,
+                      const double *omega, const double *R, const double *rho_p);
+
+/* Copy the first n particles' state (any pointer may be NULL) to the host.
+ * F and T are the momentum-exchange force and torque of the last completed step
+ * (Eqs. netforce, torque).  Synchronises the stream. */
+int fsl_particles_get(fsl_ctx *ctx, int n, double *x, double *u, double *omega,
+                      double *F, double *T);
+
+/* Copy up to cap bubble records to out; *n receives the table size.  Synchronises. */
+int fsl_bubbles_get(fsl_ctx *ctx, fsl_bubble *out, int cap, int *n);
+
+/* Import the bubble table (gas masses, merge roots, alive flags) for n ids and
+ * recompute volumes and gas densities from the current fields. */
+int fsl_bubbles_set(fsl_ctx *ctx, int n, const double *M, const int *root, const int *alive);
+
+/* Field exchange for tests and checkpoints.  Host layouts:
+ *   FSL_FIELD_FLAGS u8[N]; FSL_FIELD_MASS f64[N] (interface mass m);
+ *   FSL_FIELD_PHI f64[N]; FSL_FIELD_F f64[19][N] post-collision populations,
+ *   unshifted; FSL_FIELD_BUBBLE_ID i32[N]; FSL_FIELD_PID i32[N] (-1 = none).
+ * fields_get synchronises; fields_set is stream-ordered and synchronises. */
+#define FSL_FIELD_FLAGS 0
+#define FSL_FIELD_MASS 1
+#define FSL_FIELD_PHI 2
+#define FSL_FIELD_F 3
+#define FSL_FIELD_BUBBLE_ID 4
+#define FSL_FIELD_PID 5
+int fsl_fields_get(fsl_ctx *ctx, int field, void *host);
+int fsl_fields_set(fsl_ctx *ctx, int field, const void *host);
+
+/* Total mass sum_liquid rho + sum_interface m + ledger (FP64) and the ledger alone
+ * (mass held by covered cells, by excess without recipients and paid by moving
+ * bounce-back).  Synchronises. */
+int fsl_mass_get(fsl_ctx *ctx, double *total, double *ledger);
+
+/* Wait for the stream and report a latched device error (FSL_E_*). */
+int fsl_sync(fsl_ctx *ctx);
+
+/* Text of the last error of ctx (never NULL). */
+const char *fsl_error_string(const fsl_ctx *ctx);
+
+/* Free the host context (not the workspace). */
+void fsl_destroy(fsl_ctx *ctx);
+
+/* Per-kernel timing with HIP events on the library's stream.  When enabled, each
+ * launch of the named kernels is bracketed by events; fsl_profile_get returns,
+ * for kernel k (0 = fused stream-collide, 1 = conversions, 2 = bubbles,
+ * 3 = particles), the summed milliseconds and launch counts since the last reset
+ * (synchronises).  Off by default. */
+int fsl_profile_enable(fsl_ctx *ctx, int on);
+int fsl_profile_get(fsl_ctx *ctx, double ms[4], long long count[4]);
+
+/* Differentiation form (flags frozen over a window, Sec. 2.1/2.3 operators):
+ * fsl_window_forward runs T steps from the current state with flags, particle
+ * positions and velocities frozen, storing a checkpoint every k steps in the
+ * workspace, and returns J = sum_{t=1..T} sum_P (-F_P(t) . u_P/|u_P|) (FP64).
+ * fsl_window_backward returns dJ/dtau and dJ/dg (times the seed dJ) by a reverse
+ * (adjoint) sweep that recomputes each segment from its checkpoint.  The state
+ * after forward is the state after T steps.  The checkpoint memory is part of the
+ * workspace when cfg.window_steps / cfg.window_every are set; FSL_E_ARG if T or k
+ * exceed them or the box holds gas or interface cells. */
+int fsl_window_forward(fsl_ctx *ctx, int T, int k, double *J);
+int fsl_window_backward(fsl_ctx *ctx, double dJ, double *dJ_dtau, double dJ_dg[3]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -79,7 +79,8 @@ struct orc_ctx {
     uint32_t err;
     /* particles */
     int np;
-    double *px, *pu, *pw, *pR, *prho, *pF, *pT;
+    double *px, *pu, *pw, *pR, *prho, *pF, *pT, *pFp, *pTp;
+    int have_prev;          /* a previous step's force exists */
     /* bubbles */
     int nb;
     double *bM, *bV, *bV0, *bcent, *brho;
@@ -223,7 +224,7 @@ void orc_destroy(orc_ctx *c)
     free(c->flag); free(c->f); free(c->fn); free(c->rho_new); free(c->u_new);
     free(c->m); free(c->phi); free(c->phi_new); free(c->bub); free(c->pid); free(c->claim);
     free(c->conv);
-    free(c->px); free(c->pu); free(c->pw); free(c->pR); free(c->prho); free(c->pF); free(c->pT);
+    free(c->px); free(c->pu); free(c->pw); free(c->pR); free(c->prho); free(c->pF); free(c->pT); free(c->pFp); free(c->pTp);
     free(c->bM); free(c->bV); free(c->bV0); free(c->bcent); free(c->brho); free(c->broot);
     free(c->balive); free(c->bngas); free(c->bnif);
     free(c);
@@ -274,6 +275,8 @@ orc_ctx *orc_create(const orc_config *cfg)
     c->pw = (double *)xcalloc(3 * mp, sizeof(double));
     c->pF = (double *)xcalloc(3 * mp, sizeof(double));
     c->pT = (double *)xcalloc(3 * mp, sizeof(double));
+    c->pFp = (double *)xcalloc(3 * mp, sizeof(double));
+    c->pTp = (double *)xcalloc(3 * mp, sizeof(double));
     c->pR = (double *)xcalloc(mp, sizeof(double));
     c->prho = (double *)xcalloc(mp, sizeof(double));
     int MB = c->cfg.max_bubbles;
@@ -558,6 +561,7 @@ int orc_particles_set(orc_ctx *c, int n, const double *x, const double *u,
 {
     if (n < 0 || n > c->cfg.max_particles) { c->err |= ERR_ARG; return -1; }
     c->np = n;
+    c->have_prev = 0;
     for (int P = 0; P < n; ++P) {
         for (int a = 0; a < 3; ++a) {
             c->px[3 * P + a] = x[3 * P + a];
@@ -610,11 +614,16 @@ int orc_lubrication(const double x1[3], const double x2[3], const double u1[3],
 }
 
 /* Semi-implicit Euler with n_sub substeps (Sec. 2.3, "up to 10" read as a fixed
- * count): the hydrodynamic force and torque of the lattice step are held
- * constant, the lubrication force is recomputed every substep, gravity m_P g
- * (buoyancy comes through the fluid pressure), m_P = rho_P 4/3 pi R^3,
- * I = 2/5 m_P R^2.  Velocity is updated before position.  A sphere closer than R
- * to a wall face while moving towards it has that velocity component reversed. */
+ * count; the paper does not give the scheme).  The hydrodynamic force and torque
+ * are held constant over the substeps and are the mean of the momentum-exchange
+ * values of this and the previous lattice step (the two-step average of Ladd's
+ * suspension method, which removes the period-two oscillation of the momentum
+ * exchange that otherwise drives explicit coupling unstable at density ratio
+ * 2.5); right after the particle table is set, this step's value alone.  The
+ * lubrication force is recomputed every substep, gravity m_P g (buoyancy comes
+ * through the fluid pressure), m_P = rho_P 4/3 pi R^3, I = 2/5 m_P R^2.
+ * Velocity is updated before position.  A sphere closer than R to a wall face
+ * while moving towards it has that velocity component reversed. */
 static void particles_integrate(orc_ctx *c)
 {
     const int np = c->np, ns = c->cfg.n_sub;
@@ -639,10 +648,15 @@ static void particles_integrate(orc_ctx *c)
             double mP = c->prho[P] * (4.0 / 3.0) * M_PI * R * R * R;
             double IP = 0.4 * mP * R * R;
             for (int d = 0; d < 3; ++d) {
-                double F = c->pF[3 * P + d] + mP * c->cfg.g[d] + Fl[3 * P + d];
+                double Fh = c->pF[3 * P + d], Th = c->pT[3 * P + d];
+                if (c->have_prev) {
+                    Fh = 0.5 * (Fh + c->pFp[3 * P + d]);
+                    Th = 0.5 * (Th + c->pTp[3 * P + d]);
+                }
+                double F = Fh + mP * c->cfg.g[d] + Fl[3 * P + d];
                 c->pu[3 * P + d] += dt * F / mP;
                 c->px[3 * P + d] += dt * c->pu[3 * P + d];
-                c->pw[3 * P + d] += dt * c->pT[3 * P + d] / IP;
+                c->pw[3 * P + d] += dt * Th / IP;
                 if (!c->cfg.periodic[d]) {
                     if (c->px[3 * P + d] < R - 0.5 && c->pu[3 * P + d] < 0)
                         c->pu[3 * P + d] = -c->pu[3 * P + d];
@@ -653,13 +667,19 @@ static void particles_integrate(orc_ctx *c)
         }
     }
     free(Fl);
+    for (int k = 0; k < 3 * np; ++k) {
+        c->pFp[k] = c->pF[k];
+        c->pTp[k] = c->pT[k];
+    }
+    c->have_prev = 1;
 }
 
 /* ---- one lattice step ----------------------------------------------------------- */
 
 /* momentum exchange over all particle links (Eqs. netforce, torque,
- * momentum_transfer) and the mass that moving bounce-back adds to the fluid, which
- * the ledger pays.  Reading: the momentum Delta j_q(x) = c_q f*_q(x,t) -
+ * momentum_transfer) and the mass that moving bounce-back adds to a liquid cell,
+ * which the ledger pays (an interface cell's mass is m, which only the exchange of
+ * Eq. massExchangeb changes, so its moving-wall term is not charged).  Reading: the momentum Delta j_q(x) = c_q f*_q(x,t) -
  * c_qbar f_qbar(x,t+1) with f_qbar(x,t+1) from Eq. (bbrule); the torque arm is the
  * node x.  A solid node of another particle P' with a link into P contributes
  * with equilibrium populations at rho = 1 and the rigid velocity of P' at that
@@ -698,7 +718,7 @@ static void force_pass(orc_ctx *c)
                 c->pT[3 * P] += r[1] * dj[2] - r[2] * dj[1];
                 c->pT[3 * P + 1] += r[2] * dj[0] - r[0] * dj[2];
                 c->pT[3 * P + 2] += r[0] * dj[1] - r[1] * dj[0];
-                c->ledger -= fin - fout;
+                if (fl == LIQ) c->ledger -= fin - fout; /* interface mass is m, not rho */
             }
         } else if (fl == SOL) {
             int Pp = c->pid[x];

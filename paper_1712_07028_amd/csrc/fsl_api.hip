@@ -1,0 +1,794 @@
+// fsl_api.hip -- host runtime and C ABI of the free-surface LBM library.
+//
+// The caller's workspace is carved into the state (two population lattices,
+// cell types, fill levels, interface mass, bubble ids, particle ids), the
+// per-step lists, the particle and bubble tables and a staging area for host
+// exchange.  Every kernel is enqueued on the caller's stream; a step never
+// returns control to the host, device-side errors are latched in one word and
+// read at the next synchronising call.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/fsl.h"
+#include "k_init.hpp"
+#include "k_particles.hpp"
+#include "k_stream_collide.hpp"
+#include "k_adjoint.hpp"
+
+using namespace fsl;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int LIST_BLOCKS = 128;
+constexpr int NPROF = 4;
+
+size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+    size_t fA, fB, flags, cv, phiA, phiB, m, bub, pid, claim;
+    size_t lF, lE0, lE, lNG, lNL, lCov, lUnc, uncRho, uncDec, merges, pairs;
+    size_t counters, ctl, ptab, pacc, pFT, pFTp, pFl, gStart, gCount, gIdx;
+    size_t btab, bacc, broot, balive, rhog, stage;
+    size_t win;  // differentiation window storage
+    size_t total;
+    long long S;
+    int cap, capEv, pcap, maxP, maxB, ncellMax;
+    size_t stageBytes, winBytes;
+};
+
+int esize(int storage) { return storage == FSL_STORE_F32 ? 4 : 2; }
+
+bool valid(const fsl_config *c) {
+    if (!c) return false;
+    for (int a = 0; a < 3; ++a)
+        if (c->n[a] < 1 || (c->boundary[a] != FSL_NOSLIP && c->boundary[a] != FSL_PERIODIC)) return false;
+    long long N = (long long)c->n[0] * c->n[1] * c->n[2];
+    if (N >= (1LL << 31) - 4096) return false;
+    if (!(c->tau > 0.5)) return false;
+    if (c->collision != FSL_SRT && c->collision != FSL_TRT) return false;
+    if (c->collision == FSL_TRT && !(c->magic > 0.0)) return false;
+    if (c->storage < 0 || c->storage > 2) return false;
+    if (c->n_gas_spheres < 0 || c->n_gas_spheres > FSL_MAX_GAS_SPHERES) return false;
+    if (c->max_particles < 0 || c->n_sub < 0) return false;
+    if (c->max_bubbles < 0 || c->max_bubbles > 64) return false;
+    if (c->n_gas_spheres + 1 > (c->max_bubbles ? c->max_bubbles : 64)) return false;
+    if (c->window_steps < 0 || c->window_every < 0) return false;
+    return true;
+}
+
+Layout layout_of(const fsl_config *c) {
+    Layout L{};
+    long long N = (long long)c->n[0] * c->n[1] * c->n[2];
+    L.S = (N + 255) / 256 * 256;
+    L.cap = c->list_capacity > 0 ? c->list_capacity : (int)std::max<long long>(65536, N / 16);
+    // coverage events: replacing a whole particle table covers up to the solid
+    // fraction of the box at once
+    L.capEv = c->max_particles > 0 ? (int)std::max<long long>(L.cap, N / 3 + 65536) : L.cap;
+    L.maxP = std::max(1, c->max_particles);
+    L.pcap = 16 * L.maxP;
+    L.maxB = c->max_bubbles > 0 ? c->max_bubbles : 64;
+    L.ncellMax = ((c->n[0] + 2) / 3) * ((c->n[1] + 2) / 3) * ((c->n[2] + 2) / 3) + 1;
+    L.stageBytes = std::min<size_t>((size_t)64 << 20, std::max<size_t>((size_t)L.S * 8, 1 << 20));
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o += up(bytes); return r; };
+    size_t lat = (size_t)Q * L.S * esize(c->storage);
+    L.fA = take(lat);
+    L.fB = take(lat);
+    L.flags = take(L.S);
+    L.cv = take(L.S);
+    L.phiA = take(L.S * 8);
+    L.phiB = take(L.S * 8);
+    L.m = take(L.S * 8);
+    L.bub = take(L.S * 2);
+    L.pid = take(L.S * 4);
+    L.claim = take(L.S * 4);
+    L.lF = take((size_t)L.cap * 4);
+    L.lE0 = take((size_t)L.cap * 4);
+    L.lE = take((size_t)L.cap * 4);
+    L.lNG = take((size_t)L.cap * 4);
+    L.lNL = take((size_t)L.cap * 4);
+    L.lCov = take((size_t)L.capEv * 8);
+    L.lUnc = take((size_t)L.capEv * 8);
+    L.uncRho = take((size_t)L.capEv * 8);
+    L.uncDec = take((size_t)L.capEv * 4);
+    L.merges = take((size_t)L.cap * 8);
+    L.pairs = take((size_t)L.pcap * 8);
+    L.counters = take(64 * 4);
+    L.ctl = take(64 * 8);  // [0] err word, [8] ledger, [16..] mass sums
+    L.ptab = take((size_t)L.maxP * P_STRIDE * 8);
+    L.pacc = take((size_t)L.maxP * ACC_STRIDE * 8);
+    L.pFT = take((size_t)L.maxP * 6 * 8);
+    L.pFTp = take((size_t)L.maxP * 6 * 8);
+    L.pFl = take((size_t)L.maxP * 3 * 8);
+    L.gStart = take((size_t)(L.ncellMax + 1) * 4);
+    L.gCount = take((size_t)L.ncellMax * 4);
+    L.gIdx = take((size_t)L.maxP * 4);
+    L.btab = take((size_t)L.maxB * B_STRIDE * 8);
+    L.bacc = take((size_t)L.maxB * BACC_STRIDE * 8);
+    L.broot = take((size_t)L.maxB * 4);
+    L.balive = take((size_t)L.maxB * 4);
+    L.rhog = take((size_t)L.maxB * 4);
+    L.stage = take(L.stageBytes);
+    L.winBytes = adjoint_window_bytes(c->window_steps, c->window_every, (size_t)L.S, c->max_particles);
+    L.win = take(L.winBytes);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct fsl_ctx {
+    fsl_config cfg;
+    Layout L;
+    Geom G;
+    Phys Ph;
+    Dev D;
+    hipStream_t st;
+    char *ws;
+    char err[256];
+    double Rmax;
+    PGrid PG;
+    int ncell;
+    int tilesX, tilesY, nTiles;
+    int profiling;
+    int have_prev;  // a previous step's hydrodynamic force exists (particle update)
+    std::vector<hipEvent_t> evpool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> evlog;
+    double prof_ms[NPROF];
+    long long prof_n[NPROF];
+    AdjointState adj;
+};
+
+namespace {
+
+int fail(fsl_ctx *c, int code, const char *msg) {
+    if (c) snprintf(c->err, sizeof(c->err), "%s", msg);
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                           \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess) {                                                     \
+            char b_[200];                                                           \
+            snprintf(b_, sizeof b_, "%s: %s", #call, hipGetErrorString(e_));       \
+            return fail(ctx, FSL_E_HIP, b_);                                        \
+        }                                                                           \
+    } while (0)
+
+#define LAUNCHCHK(ctx)                                                              \
+    do {                                                                            \
+        hipError_t e_ = hipGetLastError();                                          \
+        if (e_ != hipSuccess) return fail(ctx, FSL_E_HIP, hipGetErrorString(e_));  \
+    } while (0)
+
+hipEvent_t ev_get(fsl_ctx *c) {
+    if (!c->evpool.empty()) {
+        hipEvent_t e = c->evpool.back();
+        c->evpool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct ProfScope {
+    fsl_ctx *c;
+    int k;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(fsl_ctx *ctx, int kind) : c(ctx), k(kind) {
+        if (c->profiling) {
+            a = ev_get(c);
+            b = ev_get(c);
+            if (a) (void)hipEventRecord(a, c->st);
+        }
+    }
+    ~ProfScope() {
+        if (c->profiling && a && b) {
+            (void)hipEventRecord(b, c->st);
+            c->evlog.push_back({k, {a, b}});
+        }
+    }
+};
+
+int grid_for(long long n, int block = 256, int cap = 8192) {
+    long long g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+void set_phys(fsl_ctx *c) {
+    const fsl_config &f = c->cfg;
+    c->Ph.lp = (float)(-1.0 / f.tau);
+    double lp = -1.0 / f.tau;
+    double lm = lp;
+    if (f.collision == FSL_TRT) {
+        double a = 1.0 / lp + 0.5;
+        double b = f.magic / a;
+        lm = 1.0 / (b - 0.5);
+    }
+    c->Ph.lm = (float)lm;
+    for (int a = 0; a < 3; ++a) c->Ph.g[a] = (float)f.g[a];
+    c->Ph.eps = f.eps_c;
+    c->Ph.scale = f.storage == FSL_STORE_F16S ? 1024.0f : 1.0f;
+    c->Ph.inv = 1.0f / c->Ph.scale;
+}
+
+template <int ST> int enqueue_steps(fsl_ctx *c, int n);
+template <int ST> int enqueue_coverage_full(fsl_ctx *c);
+template <int ST> int enqueue_bubbles(fsl_ctx *c, double *phi, int init);
+
+template <int ST>
+int enqueue_bubbles(fsl_ctx *c, double *phi, int init) {
+    ProfScope ps(c, 2);
+    Dev &D = c->D;
+    hipLaunchKernelGGL(k_bubble_zero, dim3(1), dim3(256), 0, c->st, D);
+    hipLaunchKernelGGL(k_bubble_accum, dim3(grid_for((c->G.N + 15) / 16, 256, 2048)), dim3(256), 0,
+                       c->st, c->G, D, (const double *)phi);
+    hipLaunchKernelGGL(k_bubble_finalize, dim3(1), dim3(64), 0, c->st, D, init);
+    LAUNCHCHK(c);
+    return FSL_OK;
+}
+
+template <int ST>
+int enqueue_conversions(fsl_ctx *c) {
+    ProfScope ps(c, 1);
+    Dev &D = c->D;
+    dim3 g(LIST_BLOCKS), b(256);
+    hipLaunchKernelGGL(k_conv_mark, g, b, 0, c->st, D);
+    hipLaunchKernelGGL(k_conv_closure, g, b, 0, c->st, c->G, D);
+    hipLaunchKernelGGL(k_conv_init<ST>, g, b, 0, c->st, c->G, c->Ph, D);
+    hipLaunchKernelGGL(k_conv_finalize, g, b, 0, c->st, D);
+    hipLaunchKernelGGL(k_conv_excess<ST>, g, b, 0, c->st, c->G, c->Ph, D);
+    hipLaunchKernelGGL(k_conv_fill<ST>, g, b, 0, c->st, c->G, c->Ph, D);
+    hipLaunchKernelGGL(k_bubble_merge, dim3(1), dim3(64), 0, c->st, D);
+    LAUNCHCHK(c);
+    return FSL_OK;
+}
+
+// cover / uncover events with the lattice lat and fill levels phi as "current"
+template <int ST>
+int enqueue_cover_events(fsl_ctx *c, const Dev &Dv, double *phi) {
+    dim3 g(LIST_BLOCKS), b(256);
+    hipLaunchKernelGGL(k_cov_apply<ST>, g, b, 0, c->st, c->G, c->Ph, Dv, phi);
+    hipLaunchKernelGGL(k_unc_decide<ST>, g, b, 0, c->st, c->G, c->Ph, Dv);
+    hipLaunchKernelGGL(k_unc_apply<ST>, g, b, 0, c->st, c->G, c->Ph, Dv, phi);
+    hipLaunchKernelGGL(k_unc_closure, g, b, 0, c->st, c->G, Dv, phi);
+    LAUNCHCHK(c);
+    return FSL_OK;
+}
+
+template <int ST>
+int enqueue_particles(fsl_ctx *c) {
+    ProfScope ps(c, 3);
+    Dev &D = c->D;
+    const int np = D.np;
+    hipLaunchKernelGGL(k_part_forces, dim3((np + 255) / 256), dim3(256), 0, c->st, D, c->cfg.integrate);
+    if (!c->cfg.integrate) { LAUNCHCHK(c); return FSL_OK; }
+    hipLaunchKernelGGL(k_grid_zero, dim3(grid_for(c->ncell)), dim3(256), 0, c->st, D, c->ncell);
+    hipLaunchKernelGGL(k_grid_count, dim3(grid_for(np)), dim3(256), 0, c->st, D, c->PG);
+    hipLaunchKernelGGL(k_grid_scan, dim3(1), dim3(1024), 0, c->st, D, c->ncell);
+    hipLaunchKernelGGL(k_grid_fill, dim3(grid_for(np)), dim3(256), 0, c->st, D, c->PG);
+    hipLaunchKernelGGL(k_pairs, dim3(grid_for(np)), dim3(256), 0, c->st, D, c->PG, c->L.pcap);
+    const int ns = c->cfg.n_sub > 0 ? c->cfg.n_sub : 10;
+    const double mu = (c->cfg.tau - 0.5) / 3.0;
+    for (int s = 0; s < ns; ++s) {
+        hipLaunchKernelGGL(k_lub, dim3(grid_for(c->L.pcap, 256, 1024)), dim3(256), 0, c->st, D, mu, c->L.pcap);
+        hipLaunchKernelGGL(k_substep, dim3(grid_for(np)), dim3(256), 0, c->st, D, c->G, 1.0 / ns,
+                           c->cfg.g[0], c->cfg.g[1], c->cfg.g[2], c->have_prev);
+    }
+    c->have_prev = 1;
+    dim3 pw((np + 3) / 4);
+    hipLaunchKernelGGL(k_cov_claim, pw, dim3(256), 0, c->st, c->G, D);
+    hipLaunchKernelGGL(k_cov_scan, pw, dim3(256), 0, c->st, c->G, D);
+    int rc = enqueue_cover_events<ST>(c, D, D.phi_nxt);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_cov_reset, pw, dim3(256), 0, c->st, c->G, D);
+    LAUNCHCHK(c);
+    return FSL_OK;
+}
+
+template <int ST>
+int enqueue_steps(fsl_ctx *c, int n) {
+    for (int s = 0; s < n; ++s) {
+        Dev &D = c->D;
+        hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, c->st, D);
+        {
+            ProfScope ps(c, 0);
+            hipLaunchKernelGGL(k_stream_collide<ST>, dim3(c->nTiles), dim3(256), 0, c->st, c->G, c->Ph, D,
+                               c->tilesX, c->tilesY, c->nTiles);
+        }
+        LAUNCHCHK(c);
+        int rc = enqueue_conversions<ST>(c);
+        if (rc) return rc;
+        if (D.np > 0) {
+            rc = enqueue_particles<ST>(c);
+            if (rc) return rc;
+        }
+        rc = enqueue_bubbles<ST>(c, D.phi_nxt, 0);
+        if (rc) return rc;
+        std::swap(D.fA, D.fB);
+        std::swap(D.phi_cur, D.phi_nxt);
+    }
+    return FSL_OK;
+}
+
+// coverage of a whole new particle table (no previous positions): dense scan
+template <int ST>
+int enqueue_coverage_full(fsl_ctx *c) {
+    Dev Dv = c->D;
+    Dv.fB = c->D.fA;  // the current state is in lattice A between steps
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, c->st, Dv);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(c->G.N, 256, 4096)), dim3(256), 0, c->st, Dv.claim,
+                       c->G.N, CLAIM_NONE);
+    if (Dv.np > 0) hipLaunchKernelGGL(k_cov_claim, dim3((Dv.np + 3) / 4), dim3(256), 0, c->st, c->G, Dv);
+    hipLaunchKernelGGL(k_cov_scan_dense, dim3(grid_for(c->G.N, 256, 4096)), dim3(256), 0, c->st, c->G, Dv);
+    int rc = enqueue_cover_events<ST>(c, Dv, Dv.phi_cur);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(c->G.N, 256, 4096)), dim3(256), 0, c->st, Dv.claim,
+                       c->G.N, CLAIM_NONE);
+    LAUNCHCHK(c);
+    return enqueue_bubbles<ST>(c, Dv.phi_cur, 0);
+}
+
+template <int ST>
+int dispatch_init(fsl_ctx *c, const InitGeo &I) {
+    Dev &D = c->D;
+    long long N = c->G.N;
+    int g = grid_for(N, 256, 8192);
+    hipLaunchKernelGGL(k_init_geometry, dim3(g), dim3(256), 0, c->st, c->G, D, I);
+    hipLaunchKernelGGL(k_init_closure_mark, dim3(g), dim3(256), 0, c->st, c->G, D);
+    hipLaunchKernelGGL(k_init_pdf<ST>, dim3(g), dim3(256), 0, c->st, c->G, c->Ph, D, I);
+    LAUNCHCHK(c);
+    return enqueue_bubbles<ST>(c, D.phi_cur, 1);
+}
+
+template <typename Fn>
+int by_storage(fsl_ctx *c, Fn &&fn) {
+    switch (c->cfg.storage) {
+    case FSL_STORE_F32: return fn(std::integral_constant<int, ST_F32>{});
+    case FSL_STORE_F16S: return fn(std::integral_constant<int, ST_F16>{});
+    default: return fn(std::integral_constant<int, ST_BF16>{});
+    }
+}
+
+int read_error(fsl_ctx *c) {
+    unsigned e = 0;
+    HIPCHK(c, hipMemcpyAsync(&e, c->D.err, 4, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (!e) return FSL_OK;
+    if (e & ERR_CAP) return fail(c, FSL_E_CAPACITY, "a conversion, event or pair list overflowed");
+    if (e & ERR_NAN) return fail(c, FSL_E_NUMERIC, "NaN density or velocity");
+    if (e & ERR_VOL) return fail(c, FSL_E_NUMERIC, "a bubble volume collapsed to zero");
+    if (e & ERR_LG) return fail(c, FSL_E_INVARIANT, "a liquid cell has a gas neighbour");
+    return fail(c, FSL_E_NUMERIC, "device error");
+}
+
+}  // namespace
+
+// ==================================================================================
+extern "C" {
+
+size_t fsl_workspace_bytes(const fsl_config *cfg) {
+    if (!valid(cfg)) return 0;
+    return layout_of(cfg).total;
+}
+
+int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, fsl_ctx **out) {
+    if (!out) return FSL_E_ARG;
+    *out = nullptr;
+    if (!valid(cfg) || !d_ws || ((uintptr_t)d_ws % ALIGN)) return FSL_E_ARG;
+    Layout L = layout_of(cfg);
+    if (bytes < L.total) return FSL_E_ARG;
+    fsl_ctx *c = new (std::nothrow) fsl_ctx();
+    if (!c) return FSL_E_ARG;
+    c->cfg = *cfg;
+    if (c->cfg.n_sub <= 0) c->cfg.n_sub = 10;
+    c->L = L;
+    c->st = (hipStream_t)hip_stream;
+    c->ws = (char *)d_ws;
+    c->err[0] = 0;
+    Geom &G = c->G;
+    G.nx = cfg->n[0];
+    G.ny = cfg->n[1];
+    G.nz = cfg->n[2];
+    for (int a = 0; a < 3; ++a) G.per[a] = cfg->boundary[a] == FSL_PERIODIC;
+    G.N = (long long)G.nx * G.ny * G.nz;
+    G.S = L.S;
+    set_phys(c);
+    Dev &D = c->D;
+    char *w = c->ws;
+    D.fA = w + L.fA;
+    D.fB = w + L.fB;
+    D.flags = (uint8_t *)(w + L.flags);
+    D.cv = (uint8_t *)(w + L.cv);
+    D.phi_cur = (double *)(w + L.phiA);
+    D.phi_nxt = (double *)(w + L.phiB);
+    D.m = (double *)(w + L.m);
+    D.bub = (uint16_t *)(w + L.bub);
+    D.pid = (int *)(w + L.pid);
+    D.claim = (int *)(w + L.claim);
+    D.lF = (int *)(w + L.lF);
+    D.lE0 = (int *)(w + L.lE0);
+    D.lE = (int *)(w + L.lE);
+    D.lNG = (int *)(w + L.lNG);
+    D.lNL = (int *)(w + L.lNL);
+    D.lCov = (int *)(w + L.lCov);
+    D.lUnc = (int *)(w + L.lUnc);
+    D.uncRho = (double *)(w + L.uncRho);
+    D.uncDec = (int *)(w + L.uncDec);
+    D.merges = (int2 *)(w + L.merges);
+    D.pairs = (int2 *)(w + L.pairs);
+    D.counters = (int *)(w + L.counters);
+    D.err = (unsigned *)(w + L.ctl);
+    D.ledger = (double *)(w + L.ctl + 8);
+    D.ptab = (double *)(w + L.ptab);
+    D.pacc = (double *)(w + L.pacc);
+    D.pFT = (double *)(w + L.pFT);
+    D.pFTp = (double *)(w + L.pFTp);
+    D.pFl = (double *)(w + L.pFl);
+    D.gridStart = (int *)(w + L.gStart);
+    D.gridCount = (int *)(w + L.gCount);
+    D.gridIdx = (int *)(w + L.gIdx);
+    D.btab = (double *)(w + L.btab);
+    D.bacc = (double *)(w + L.bacc);
+    D.broot = (int *)(w + L.broot);
+    D.balive = (int *)(w + L.balive);
+    D.rhog = (float *)(w + L.rhog);
+    D.cap = L.cap;
+    D.capEv = L.capEv;
+    D.maxP = L.maxP;
+    D.maxB = L.maxB;
+    D.np = 0;
+    D.nb = cfg->n_gas_spheres + 1;
+    c->Rmax = 0;
+    c->ncell = 1;
+    c->PG = PGrid{{1, 1, 1}, {(double)G.nx, (double)G.ny, (double)G.nz}, 2.0 / 3.0 + 1.0};
+    c->tilesX = (G.nx + TX - 1) / TX;
+    c->tilesY = (G.ny + TY - 1) / TY;
+    c->nTiles = c->tilesX * c->tilesY * G.nz;
+    c->profiling = 0;
+    for (int k = 0; k < NPROF; ++k) { c->prof_ms[k] = 0; c->prof_n[k] = 0; }
+    adjoint_bind(c->adj, w + L.win, L.winBytes);
+
+    // control block, tables, accumulators
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, c->st, (double *)(w + L.ctl), 64LL, 0.0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->st, D.counters, 64LL, 0);
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)L.maxP * ACC_STRIDE)), dim3(256), 0, c->st,
+                       D.pacc, (long long)L.maxP * ACC_STRIDE, 0.0);
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)L.maxP * 6)), dim3(256), 0, c->st, D.pFT,
+                       (long long)L.maxP * 6, 0.0);
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)L.maxP * 6)), dim3(256), 0, c->st, D.pFTp,
+                       (long long)L.maxP * 6, 0.0);
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)L.maxP * 3)), dim3(256), 0, c->st, D.pFl,
+                       (long long)L.maxP * 3, 0.0);
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)L.maxB * B_STRIDE)), dim3(256), 0, c->st, D.btab,
+                       (long long)L.maxB * B_STRIDE, 0.0);
+    // lattice B starts cleared so that unused cells hold finite values
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for((long long)Q * L.S * esize(cfg->storage) / 4, 256, 8192)),
+                       dim3(256), 0, c->st, (int *)D.fB, (long long)Q * L.S * esize(cfg->storage) / 4, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for((long long)Q * L.S * esize(cfg->storage) / 4, 256, 8192)),
+                       dim3(256), 0, c->st, (int *)D.fA, (long long)Q * L.S * esize(cfg->storage) / 4, 0);
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(L.S, 256, 8192)), dim3(256), 0, c->st, D.phi_nxt, (long long)L.S, 0.0);
+    // bubble merge table: every id its own root, before any kernel follows it
+    {
+        std::vector<int> root(L.maxB), alive(L.maxB, 1);
+        for (int b = 0; b < L.maxB; ++b) root[b] = b;
+        hipError_t e1 = hipMemcpyAsync(D.broot, root.data(), L.maxB * 4, hipMemcpyHostToDevice, c->st);
+        hipError_t e2 = hipMemcpyAsync(D.balive, alive.data(), L.maxB * 4, hipMemcpyHostToDevice, c->st);
+        hipError_t e3 = hipStreamSynchronize(c->st);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) { delete c; return FSL_E_HIP; }
+    }
+    // bubble densities of the initial state in the density slot of the table
+    std::vector<double> rho0(D.nb);
+    rho0[0] = cfg->rho_g0;
+    for (int s = 0; s < cfg->n_gas_spheres; ++s) rho0[s + 1] = cfg->gas_spheres[s][4];
+    for (int b = 0; b < D.nb; ++b) {
+        hipError_t e = hipMemcpyAsync(D.btab + b * B_STRIDE + B_RHO, &rho0[b], 8, hipMemcpyHostToDevice, c->st);
+        if (e != hipSuccess) { delete c; return FSL_E_HIP; }
+    }
+    InitGeo I{};
+    I.zs = cfg->zs;
+    I.rho_g0 = cfg->rho_g0;
+    I.gz = cfg->g[2];
+    I.ns = cfg->n_gas_spheres;
+    for (int s = 0; s < I.ns; ++s)
+        for (int a = 0; a < 5; ++a) I.sph[s][a] = cfg->gas_spheres[s][a];
+    int rc = by_storage(c, [&](auto st) { return dispatch_init<decltype(st)::value>(c, I); });
+    if (rc == FSL_OK) rc = read_error(c);
+    if (rc != FSL_OK) {
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return FSL_OK;
+}
+
+int fsl_step(fsl_ctx *c, int n) {
+    if (!c || n < 0) return FSL_E_ARG;
+    return by_storage(c, [&](auto st) { return enqueue_steps<decltype(st)::value>(c, n); });
+}
+
+int fsl_particles_set(fsl_ctx *c, int n, const double *x, const double *u, const double *omega,
+                      const double *R, const double *rho_p) {
+    if (!c || n < 0 || n > c->cfg.max_particles || (n > 0 && (!x || !R || !rho_p)))
+        return fail(c, FSL_E_ARG, "particles_set: bad arguments");
+    std::vector<double> tab((size_t)std::max(n, 1) * P_STRIDE, 0.0);
+    double Rmax = 0;
+    for (int P = 0; P < n; ++P) {
+        double *t = &tab[(size_t)P * P_STRIDE];
+        for (int a = 0; a < 3; ++a) {
+            t[P_X + a] = x[3 * P + a];
+            t[P_XOLD + a] = x[3 * P + a];
+            t[P_U + a] = u ? u[3 * P + a] : 0.0;
+            t[P_W + a] = omega ? omega[3 * P + a] : 0.0;
+        }
+        if (!(R[P] > 0.0) || !(rho_p[P] > 0.0)) return fail(c, FSL_E_ARG, "particles_set: radius and density must be > 0");
+        t[P_R] = R[P];
+        t[P_RHO] = rho_p[P];
+        Rmax = std::max(Rmax, R[P]);
+    }
+    if (n > 0) HIPCHK(c, hipMemcpyAsync(c->D.ptab, tab.data(), (size_t)n * P_STRIDE * 8, hipMemcpyHostToDevice, c->st));
+    Dev &D = c->D;
+    D.np = n;
+    c->have_prev = 0;
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)c->L.maxP * ACC_STRIDE)), dim3(256), 0, c->st,
+                       D.pacc, (long long)c->L.maxP * ACC_STRIDE, 0.0);
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)c->L.maxP * 6)), dim3(256), 0, c->st, D.pFT,
+                       (long long)c->L.maxP * 6, 0.0);
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)c->L.maxP * 6)), dim3(256), 0, c->st, D.pFTp,
+                       (long long)c->L.maxP * 6, 0.0);
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)c->L.maxP * 3)), dim3(256), 0, c->st, D.pFl,
+                       (long long)c->L.maxP * 3, 0.0);
+    // lubrication candidate grid: cells no smaller than the largest pair reach
+    c->Rmax = Rmax;
+    const double reach = 2.0 / 3.0 + 1.0;
+    const double cell = std::max(2.0 * Rmax + reach, 3.0);
+    long long tot = 1;
+    for (int a = 0; a < 3; ++a) {
+        c->PG.g[a] = std::max(1, (int)floor(c->cfg.n[a] / cell));
+        c->PG.cs[a] = (double)c->cfg.n[a] / c->PG.g[a];
+        tot *= c->PG.g[a];
+    }
+    c->PG.reach = reach;
+    if (tot > c->L.ncellMax) return fail(c, FSL_E_ARG, "particles_set: radius too small for the pair grid");
+    c->ncell = (int)tot;
+    int rc = by_storage(c, [&](auto st) { return enqueue_coverage_full<decltype(st)::value>(c); });
+    if (rc) return rc;
+    return read_error(c);
+}
+
+int fsl_particles_get(fsl_ctx *c, int n, double *x, double *u, double *omega, double *F, double *T) {
+    if (!c || n < 0) return FSL_E_ARG;
+    if (n > c->D.np) n = c->D.np;
+    if (n == 0) return fsl_sync(c);
+    std::vector<double> tab((size_t)n * P_STRIDE), ft((size_t)n * 6);
+    HIPCHK(c, hipMemcpyAsync(tab.data(), c->D.ptab, tab.size() * 8, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(ft.data(), c->D.pFT, ft.size() * 8, hipMemcpyDeviceToHost, c->st));
+    int rc = read_error(c);
+    for (int P = 0; P < n; ++P)
+        for (int a = 0; a < 3; ++a) {
+            if (x) x[3 * P + a] = tab[(size_t)P * P_STRIDE + P_X + a];
+            if (u) u[3 * P + a] = tab[(size_t)P * P_STRIDE + P_U + a];
+            if (omega) omega[3 * P + a] = tab[(size_t)P * P_STRIDE + P_W + a];
+            if (F) F[3 * P + a] = ft[(size_t)P * 6 + a];
+            if (T) T[3 * P + a] = ft[(size_t)P * 6 + 3 + a];
+        }
+    return rc;
+}
+
+int fsl_bubbles_get(fsl_ctx *c, fsl_bubble *out, int cap, int *n) {
+    if (!c || (cap > 0 && !out)) return FSL_E_ARG;
+    const int nb = c->D.nb;
+    std::vector<double> tab((size_t)nb * B_STRIDE);
+    std::vector<int> root(nb), alive(nb);
+    HIPCHK(c, hipMemcpyAsync(tab.data(), c->D.btab, tab.size() * 8, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(root.data(), c->D.broot, nb * 4, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(alive.data(), c->D.balive, nb * 4, hipMemcpyDeviceToHost, c->st));
+    int rc = read_error(c);
+    if (n) *n = nb;
+    for (int b = 0; b < nb && b < cap; ++b) {
+        int r = b;
+        for (int it = 0; it < 64 && root[r] != r; ++it) r = root[r];
+        const double *t = &tab[(size_t)r * B_STRIDE];
+        fsl_bubble &o = out[b];
+        o.id = b;
+        o.alive = alive[b] && r == b;
+        o.V = t[B_V];
+        o.M = t[B_M];
+        o.rho_g = t[B_RHO];
+        for (int a = 0; a < 3; ++a) o.centroid[a] = t[B_C + a];
+        o.V0 = tab[(size_t)b * B_STRIDE + B_V0];
+        o.n_gas = (int64_t)llround(t[B_NGAS]);
+        o.n_iface = (int64_t)llround(t[B_NIF]);
+    }
+    return rc;
+}
+
+int fsl_bubbles_set(fsl_ctx *c, int n, const double *M, const int *root, const int *alive) {
+    if (!c || n < 1 || n > c->L.maxB || !M || !root || !alive) return fail(c, FSL_E_ARG, "bubbles_set: bad arguments");
+    for (int b = 0; b < n; ++b)
+        if (root[b] < 0 || root[b] >= n) return fail(c, FSL_E_ARG, "bubbles_set: bad root");
+    c->D.nb = n;
+    for (int b = 0; b < n; ++b)
+        HIPCHK(c, hipMemcpyAsync(c->D.btab + b * B_STRIDE + B_M, M + b, 8, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->D.broot, root, n * 4, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->D.balive, alive, n * 4, hipMemcpyHostToDevice, c->st));
+    int rc = by_storage(c, [&](auto st) { return enqueue_bubbles<decltype(st)::value>(c, c->D.phi_cur, 0); });
+    if (rc) return rc;
+    return read_error(c);
+}
+
+int fsl_fields_get(fsl_ctx *c, int field, void *host) {
+    if (!c || !host) return FSL_E_ARG;
+    const long long N = c->G.N;
+    Dev &D = c->D;
+    double *stage = (double *)(c->ws + c->L.stage);
+    const long long chunk = (long long)(c->L.stageBytes / 8);
+    switch (field) {
+    case FSL_FIELD_FLAGS: HIPCHK(c, hipMemcpyAsync(host, D.flags, N, hipMemcpyDeviceToHost, c->st)); break;
+    case FSL_FIELD_MASS: HIPCHK(c, hipMemcpyAsync(host, D.m, N * 8, hipMemcpyDeviceToHost, c->st)); break;
+    case FSL_FIELD_PHI: HIPCHK(c, hipMemcpyAsync(host, D.phi_cur, N * 8, hipMemcpyDeviceToHost, c->st)); break;
+    case FSL_FIELD_PID: HIPCHK(c, hipMemcpyAsync(host, D.pid, N * 4, hipMemcpyDeviceToHost, c->st)); break;
+    case FSL_FIELD_BUBBLE_ID:
+        for (long long c0 = 0; c0 < N; c0 += chunk / 2) {
+            long long n = std::min(chunk / 2, N - c0);
+            hipLaunchKernelGGL(k_u16_to_i32, dim3(grid_for(n)), dim3(256), 0, c->st, D.bub + c0, n, (int *)stage);
+            HIPCHK(c, hipMemcpyAsync((int *)host + c0, stage, n * 4, hipMemcpyDeviceToHost, c->st));
+            HIPCHK(c, hipStreamSynchronize(c->st));
+        }
+        break;
+    case FSL_FIELD_F: {
+        int rc = by_storage(c, [&](auto st) -> int {
+            constexpr int ST = decltype(st)::value;
+            for (int q = 0; q < Q; ++q)
+                for (long long c0 = 0; c0 < N; c0 += chunk) {
+                    long long n = std::min(chunk, N - c0);
+                    hipLaunchKernelGGL(k_pop_to_f64<ST>, dim3(grid_for(n)), dim3(256), 0, c->st, c->G, c->Ph,
+                                       (const void *)D.fA, q, c0, n, stage);
+                    HIPCHK(c, hipMemcpyAsync((double *)host + (long long)q * N + c0, stage, n * 8,
+                                             hipMemcpyDeviceToHost, c->st));
+                    HIPCHK(c, hipStreamSynchronize(c->st));
+                }
+            return FSL_OK;
+        });
+        if (rc) return rc;
+        break;
+    }
+    default: return fail(c, FSL_E_ARG, "fields_get: unknown field");
+    }
+    return read_error(c);
+}
+
+int fsl_fields_set(fsl_ctx *c, int field, const void *host) {
+    if (!c || !host) return FSL_E_ARG;
+    const long long N = c->G.N;
+    Dev &D = c->D;
+    double *stage = (double *)(c->ws + c->L.stage);
+    const long long chunk = (long long)(c->L.stageBytes / 8);
+    switch (field) {
+    case FSL_FIELD_FLAGS: HIPCHK(c, hipMemcpyAsync(D.flags, host, N, hipMemcpyHostToDevice, c->st)); break;
+    case FSL_FIELD_MASS: HIPCHK(c, hipMemcpyAsync(D.m, host, N * 8, hipMemcpyHostToDevice, c->st)); break;
+    case FSL_FIELD_PHI: HIPCHK(c, hipMemcpyAsync(D.phi_cur, host, N * 8, hipMemcpyHostToDevice, c->st)); break;
+    case FSL_FIELD_PID: HIPCHK(c, hipMemcpyAsync(D.pid, host, N * 4, hipMemcpyHostToDevice, c->st)); break;
+    case FSL_FIELD_BUBBLE_ID:
+        for (long long c0 = 0; c0 < N; c0 += chunk / 2) {
+            long long n = std::min(chunk / 2, N - c0);
+            HIPCHK(c, hipMemcpyAsync(stage, (const int *)host + c0, n * 4, hipMemcpyHostToDevice, c->st));
+            hipLaunchKernelGGL(k_i32_to_u16, dim3(grid_for(n)), dim3(256), 0, c->st, (const int *)stage, n, D.bub + c0);
+            HIPCHK(c, hipStreamSynchronize(c->st));
+        }
+        break;
+    case FSL_FIELD_F: {
+        int rc = by_storage(c, [&](auto st) -> int {
+            constexpr int ST = decltype(st)::value;
+            for (int q = 0; q < Q; ++q)
+                for (long long c0 = 0; c0 < N; c0 += chunk) {
+                    long long n = std::min(chunk, N - c0);
+                    HIPCHK(c, hipMemcpyAsync(stage, (const double *)host + (long long)q * N + c0, n * 8,
+                                             hipMemcpyHostToDevice, c->st));
+                    hipLaunchKernelGGL(k_pop_from_f64<ST>, dim3(grid_for(n)), dim3(256), 0, c->st, c->G, c->Ph,
+                                       D.fA, q, c0, n, (const double *)stage);
+                    HIPCHK(c, hipStreamSynchronize(c->st));
+                }
+            return FSL_OK;
+        });
+        if (rc) return rc;
+        break;
+    }
+    default: return fail(c, FSL_E_ARG, "fields_set: unknown field");
+    }
+    return read_error(c);
+}
+
+int fsl_mass_get(fsl_ctx *c, double *total, double *ledger) {
+    if (!c) return FSL_E_ARG;
+    double *out = (double *)(c->ws + c->L.ctl) + 2;
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, c->st, out, 2LL, 0.0);
+    int rc = by_storage(c, [&](auto st) -> int {
+        constexpr int ST = decltype(st)::value;
+        hipLaunchKernelGGL(k_mass<ST>, dim3(grid_for(c->G.N, 256, 2048)), dim3(256), 0, c->st, c->G, c->Ph, c->D, out);
+        LAUNCHCHK(c);
+        return FSL_OK;
+    });
+    if (rc) return rc;
+    double h[3];
+    HIPCHK(c, hipMemcpyAsync(h, (double *)(c->ws + c->L.ctl) + 1, 24, hipMemcpyDeviceToHost, c->st));
+    rc = read_error(c);
+    if (ledger) *ledger = h[0];
+    if (total) *total = h[2] + h[1] + h[0];
+    return rc;
+}
+
+int fsl_sync(fsl_ctx *c) {
+    if (!c) return FSL_E_ARG;
+    return read_error(c);
+}
+
+const char *fsl_error_string(const fsl_ctx *c) {
+    if (!c) return "null context";
+    return c->err;
+}
+
+void fsl_destroy(fsl_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->st);
+    for (auto &e : c->evlog) {
+        (void)hipEventDestroy(e.second.first);
+        (void)hipEventDestroy(e.second.second);
+    }
+    for (auto e : c->evpool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+int fsl_profile_enable(fsl_ctx *c, int on) {
+    if (!c) return FSL_E_ARG;
+    c->profiling = on ? 1 : 0;
+    return FSL_OK;
+}
+
+int fsl_profile_get(fsl_ctx *c, double ms[4], long long count[4]) {
+    if (!c) return FSL_E_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    for (auto &e : c->evlog) {
+        float t = 0;
+        if (hipEventElapsedTime(&t, e.second.first, e.second.second) == hipSuccess) {
+            c->prof_ms[e.first] += t;
+            c->prof_n[e.first] += 1;
+        }
+        c->evpool.push_back(e.second.first);
+        c->evpool.push_back(e.second.second);
+    }
+    c->evlog.clear();
+    for (int k = 0; k < NPROF; ++k) {
+        if (ms) ms[k] = c->prof_ms[k];
+        if (count) count[k] = c->prof_n[k];
+        c->prof_ms[k] = 0;
+        c->prof_n[k] = 0;
+    }
+    return FSL_OK;
+}
+
+int fsl_window_forward(fsl_ctx *c, int T, int k, double *J) {
+    if (!c) return FSL_E_ARG;
+    return by_storage(c, [&](auto st) { return adjoint_forward<decltype(st)::value>(c->adj, c->G, c->Ph, c->D, c->st, T, k, J, c->err); });
+}
+
+int fsl_window_backward(fsl_ctx *c, double dJ, double *dJ_dtau, double dJ_dg[3]) {
+    if (!c) return FSL_E_ARG;
+    return by_storage(c, [&](auto st) {
+        return adjoint_backward<decltype(st)::value>(c->adj, c->G, c->Ph, c->D, c->st, c->cfg, dJ, dJ_dtau, dJ_dg, c->err);
+    });
+}
+
+}  // extern "C"

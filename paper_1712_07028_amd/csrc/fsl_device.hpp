@@ -1,0 +1,168 @@
+// fsl_device.hpp -- device-side definitions of the free-surface LBM library:
+// D3Q19 velocity set, population storage formats, workspace pointers and the
+// wave-level helpers shared by the kernels.  gfx950 (CDNA4), wave64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fsl {
+
+// ---- D3Q19 (Sec. 2.1): rest, six axis directions, twelve diagonals -------------
+// Order: 0 rest; 1..6 +x,-x,+y,-y,+z,-z; 7..18 (+-1,+-1,0),(+-1,0,+-1),(0,+-1,+-1)
+// with sign pairs (+,+),(+,-),(-,+),(-,-).
+constexpr int Q = 19;
+__host__ __device__ constexpr int cx(int q) {
+    constexpr int v[Q] = {0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 0, 0, 0, 0};
+    return v[q];
+}
+__host__ __device__ constexpr int cy(int q) {
+    constexpr int v[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1};
+    return v[q];
+}
+__host__ __device__ constexpr int cz(int q) {
+    constexpr int v[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+    return v[q];
+}
+__host__ __device__ constexpr int opp(int q) {
+    constexpr int v[Q] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8, 7, 14, 13, 12, 11, 18, 17, 16, 15};
+    return v[q];
+}
+__host__ __device__ constexpr float wq(int q) {
+    return q == 0 ? 1.0f / 3.0f : (q <= 6 ? 1.0f / 18.0f : 1.0f / 36.0f);
+}
+__host__ __device__ constexpr double wqd(int q) {
+    return q == 0 ? 1.0 / 3.0 : (q <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// cell types
+constexpr uint8_t GAS = 0, LIQ = 1, IFC = 2, SOL = 3, WALL = 4;
+
+// device error bits (latched, reported by the host at the next sync)
+constexpr unsigned ERR_LG = 1u, ERR_NAN = 2u, ERR_CAP = 4u, ERR_VOL = 8u;
+
+// conversion marks (one byte per cell, zero outside the conversion phase)
+constexpr uint8_t CV_F = 1, CV_E0 = 2, CV_E = 4, CV_NEWG = 8, CV_NEWL = 16;
+
+// counters in the control block
+enum Counter {
+    C_NF = 0, C_NE0, C_NE, C_NNG, C_NNL, C_NMERGE, C_NCOVER, C_NUNCOVER, C_NPAIRS,
+    C_COUNT
+};
+
+// particle table: 16 doubles per particle
+enum PSlot { P_X = 0, P_U = 3, P_W = 6, P_R = 9, P_RHO = 10, P_XOLD = 11, P_STRIDE = 16 };
+// particle accumulators: F(3) T(3) dm(1) pad -> 8 doubles
+constexpr int ACC_STRIDE = 8;
+// bubble table: 16 doubles per id
+enum BSlot { B_M = 0, B_V = 1, B_RHO = 2, B_C = 3, B_V0 = 6, B_NGAS = 7, B_NIF = 8, B_STRIDE = 16 };
+// bubble accumulators: V, Vx, Vy, Vz, n_gas, n_iface
+constexpr int BACC_STRIDE = 6;
+
+// ---- population storage (form 1) ----------------------------------------------
+// Populations are always stored shifted, h_q = f_q - w_q, so that density
+// deviations of O(1e-3) never round at O(1).  FP32 stores h directly; the 16-bit
+// formats store h * scale (a power of two) with round-to-nearest-even.
+enum { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
+
+template <int S> struct Store;
+// enc() gives the stored word, dec() the value it represents, so that the
+// value a kernel will read back is known when it writes (rnd = dec(enc(v))).
+template <> struct Store<ST_F32> {
+    using T = float;
+    static __device__ __forceinline__ T enc(float v, float) { return v; }
+    static __device__ __forceinline__ float dec(T w, float) { return w; }
+    static __device__ __forceinline__ float ld(const T *p, float inv) { return dec(*p, inv); }
+    static __device__ __forceinline__ void st(T *p, float v, float sc) { *p = enc(v, sc); }
+};
+template <> struct Store<ST_F16> {
+    using T = _Float16;
+    static __device__ __forceinline__ T enc(float v, float sc) { return (_Float16)(v * sc); }
+    static __device__ __forceinline__ float dec(T w, float inv) { return (float)w * inv; }
+    static __device__ __forceinline__ float ld(const T *p, float inv) { return dec(*p, inv); }
+    static __device__ __forceinline__ void st(T *p, float v, float sc) { *p = enc(v, sc); }
+};
+template <> struct Store<ST_BF16> {
+    using T = uint16_t;
+    static __device__ __forceinline__ T enc(float v, float sc) {
+        uint32_t u = __float_as_uint(v * sc);
+        if ((u & 0x7f800000u) != 0x7f800000u) u += 0x7fffu + ((u >> 16) & 1u);  // RNE
+        return (uint16_t)(u >> 16);
+    }
+    static __device__ __forceinline__ float dec(T w, float inv) {
+        return __uint_as_float(((uint32_t)w) << 16) * inv;
+    }
+    static __device__ __forceinline__ float ld(const T *p, float inv) { return dec(*p, inv); }
+    static __device__ __forceinline__ void st(T *p, float v, float sc) { *p = enc(v, sc); }
+};
+
+// ---- geometry / parameters passed by value ------------------------------------
+struct Geom {
+    int nx, ny, nz;
+    int per[3];
+    long long N;  // cells
+    long long S;  // plane stride of one population (>= N, multiple of 256)
+};
+
+struct Phys {
+    float lp, lm;      // lambda_+, lambda_-
+    float g[3];
+    double eps;        // conversion threshold slack
+    float scale, inv;  // 16-bit storage scale and its inverse
+};
+
+struct Dev {
+    void *fA, *fB;            // post-collision populations at t (A), next (B)
+    uint8_t *flags, *cv;
+    double *phi_cur, *phi_nxt, *m;
+    uint16_t *bub;
+    int *pid, *claim;
+    int *lF, *lE0, *lE, *lNG, *lNL;  // conversion lists
+    int *lCov, *lUnc;                // coverage events (cell, particle) pairs
+    double *uncRho;                  // per uncover event: decided density
+    int *uncDec;                     // per uncover event: type | bubble << 8
+    int2 *merges, *pairs;
+    int *counters;
+    unsigned *err;
+    double *ledger;                  // [0] ledger
+    double *ptab, *pacc, *pFT, *pFTp, *pFl; // particles (pFTp: previous step's F, T)
+    int *gridStart, *gridCount, *gridIdx;
+    double *btab, *bacc;
+    int *broot, *balive;
+    float *rhog;                     // FP32 gas density per bubble id (through root)
+    int cap;                         // conversion list capacity
+    int capEv;                       // coverage event list capacity
+    int maxP, maxB;
+    int np, nb;
+};
+
+// ---- small helpers ---------------------------------------------------------------
+__device__ __forceinline__ int wrapc(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+
+// append the lanes with pred to a list: one atomic per wave
+__device__ __forceinline__ void wave_append(bool pred, int value, int *list, int *counter,
+                                            int cap, unsigned *err) {
+    unsigned long long mask = __ballot(pred);
+    if (!mask) return;
+    int n = __popcll(mask);
+    int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if ((int)lane_id() == leader) base = atomicAdd(counter, n);
+    base = __shfl(base, leader);
+    if (pred) {
+        int off = __popcll(mask & ((1ull << lane_id()) - 1ull));
+        int slot = base + off;
+        if (slot < cap) list[slot] = value;
+        else atomicOr(err, ERR_CAP);
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+}  // namespace fsl

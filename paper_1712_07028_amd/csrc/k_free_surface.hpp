@@ -1,0 +1,377 @@
+// k_free_surface.hpp -- list-driven cell conversions (Sec. 2.2, Fig.
+// cellConversions) and the bubble model (end of Sec. 2.2).
+//
+// The stream-collide kernel leaves two lists of interface cells: filled
+// (phi >= 1 - eps_c) and emptied (phi <= eps_c).  The kernels below, in order:
+//   mark     : conversion marks of the listed cells
+//   closure  : conflict rule (an emptied cell next to a filled one stays interface),
+//              gas neighbours of filled cells and liquid neighbours of emptied cells
+//              become new interface cells (one winner per cell by an atomic OR)
+//   init     : new interface cells from gas take the equilibrium at the mean density
+//              and velocity of their liquid/interface neighbours, m = 0; new
+//              interface cells from liquid keep m = rho and take the bubble id of
+//              their first emptied neighbour
+//   finalize : cell types
+//   excess   : excess mass (m - rho, or m) shared equally by the neighbours that are
+//              interface now (FP64 atomics), or paid into the ledger
+//   fill     : fill levels of the recipients, marks cleared, invariant checked,
+//              bubble merges recorded
+// Every step of this phase touches only the listed cells and their neighbours.
+#pragma once
+
+#include "fsl_device.hpp"
+
+namespace fsl {
+
+__device__ __forceinline__ void cell_xyz(const Geom &G, int c, int &x, int &y, int &z) {
+    x = c % G.nx;
+    int r = c / G.nx;
+    y = r % G.ny;
+    z = r / G.ny;
+}
+
+// neighbour index of c along q, -1 beyond a wall
+__device__ __forceinline__ int nbr_idx(const Geom &G, int x, int y, int z, int q, int sign) {
+    int a = x + sign * cx(q), b = y + sign * cy(q), d = z + sign * cz(q);
+    if (a < 0 || a >= G.nx) { if (!G.per[0]) return -1; a = wrapc(a, G.nx); }
+    if (b < 0 || b >= G.ny) { if (!G.per[1]) return -1; b = wrapc(b, G.ny); }
+    if (d < 0 || d >= G.nz) { if (!G.per[2]) return -1; d = wrapc(d, G.nz); }
+    return a + G.nx * (b + G.ny * d);
+}
+
+template <int ST>
+__device__ __forceinline__ double cell_rho(const Geom &G, const Dev &D, const Phys &Ph, const void *F, int c) {
+    using SS = Store<ST>;
+    const typename SS::T *p = (const typename SS::T *)F;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s += (double)SS::ld(p + q * G.S + c, Ph.inv);
+    return 1.0 + s;
+}
+
+// density deviation drho = rho - 1 and velocity of the post-collision populations
+// (first moment minus half the Guo force)
+template <int ST>
+__device__ __forceinline__ void cell_rho_u(const Geom &G, const Phys &Ph, const void *F, int c,
+                                           float &drho, float &u0, float &u1, float &u2) {
+    using SS = Store<ST>;
+    const typename SS::T *p = (const typename SS::T *)F;
+    float d = 0.f, j0 = 0.f, j1 = 0.f, j2 = 0.f;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        float h = SS::ld(p + q * G.S + c, Ph.inv);
+        d += h;
+        j0 += cx(q) * h;
+        j1 += cy(q) * h;
+        j2 += cz(q) * h;
+    }
+    drho = d;
+    const float rho = 1.0f + d;
+    u0 = j0 / rho - 0.5f * Ph.g[0];
+    u1 = j1 / rho - 0.5f * Ph.g[1];
+    u2 = j2 / rho - 0.5f * Ph.g[2];
+}
+
+// shifted equilibrium e_q(rho,u) - w_q written to cell c; drho = rho - 1 is passed
+// separately so that it keeps its own precision
+template <int ST>
+__device__ __forceinline__ void store_equilibrium(const Geom &G, const Phys &Ph, void *F, int c,
+                                                  float drho, float u0, float u1, float u2) {
+    using SS = Store<ST>;
+    typename SS::T *p = (typename SS::T *)F;
+    const float rho = 1.0f + drho;
+    float uu = u0 * u0 + u1 * u1 + u2 * u2;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        float cu = cx(q) * u0 + cy(q) * u1 + cz(q) * u2;
+        float h = wq(q) * (drho + rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
+        SS::st(p + q * G.S + c, h, Ph.scale);
+    }
+}
+
+__device__ __forceinline__ uint8_t cv_or(uint8_t *cv, int c, uint8_t bits) {
+    unsigned *w = (unsigned *)(cv + (c & ~3));
+    int sh = 8 * (c & 3);
+    unsigned old = atomicOr(w, (unsigned)bits << sh);
+    return (uint8_t)(old >> sh);
+}
+
+__device__ __forceinline__ int list_len(const Dev &D, int which) {
+    int n = D.counters[which];
+    return n < D.cap ? n : D.cap;
+}
+
+__device__ __forceinline__ void list_push(const Dev &D, int *list, int which, int v) {
+    int s = atomicAdd(D.counters + which, 1);
+    if (s < D.cap) list[s] = v;
+    else atomicOr(D.err, ERR_CAP);
+}
+
+#define GRID_STRIDE(i, n) for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += gridDim.x * blockDim.x)
+
+__global__ void k_conv_mark(Dev D) {
+    int nF = list_len(D, C_NF), nE = list_len(D, C_NE0);
+    GRID_STRIDE(i, nF) D.cv[D.lF[i]] = CV_F;
+    GRID_STRIDE(i, nE) D.cv[D.lE0[i]] = CV_E0;
+}
+
+__global__ void k_conv_closure(Geom G, Dev D) {
+    int nF = list_len(D, C_NF), nE = list_len(D, C_NE0);
+    GRID_STRIDE(i, nE) {
+        int c = D.lE0[i], x, y, z;
+        cell_xyz(G, c, x, y, z);
+        bool keep = true;
+        for (int q = 1; q < Q && keep; ++q) {
+            int n = nbr_idx(G, x, y, z, q, 1);
+            if (n >= 0 && D.cv[n] == CV_F) keep = false;
+        }
+        if (!keep) continue;
+        cv_or(D.cv, c, CV_E);
+        list_push(D, D.lE, C_NE, c);
+        for (int q = 1; q < Q; ++q) {
+            int n = nbr_idx(G, x, y, z, q, 1);
+            if (n < 0 || D.flags[n] != LIQ) continue;
+            if (!(cv_or(D.cv, n, CV_NEWL) & CV_NEWL)) list_push(D, D.lNL, C_NNL, n);
+        }
+    }
+    GRID_STRIDE(i, nF) {
+        int c = D.lF[i], x, y, z;
+        cell_xyz(G, c, x, y, z);
+        for (int q = 1; q < Q; ++q) {
+            int n = nbr_idx(G, x, y, z, q, 1);
+            if (n < 0 || D.flags[n] != GAS) continue;
+            if (!(cv_or(D.cv, n, CV_NEWG) & CV_NEWG)) list_push(D, D.lNG, C_NNG, n);
+        }
+    }
+}
+
+template <int ST>
+__global__ void k_conv_init(Geom G, Phys Ph, Dev D) {
+    int nG = list_len(D, C_NNG), nL = list_len(D, C_NNL);
+    GRID_STRIDE(i, nG) {
+        int c = D.lNG[i], x, y, z;
+        cell_xyz(G, c, x, y, z);
+        float rs = 0.f, s0 = 0.f, s1 = 0.f, s2 = 0.f;
+        int cnt = 0;
+        for (int q = 1; q < Q; ++q) {
+            int n = nbr_idx(G, x, y, z, q, 1);
+            if (n < 0) continue;
+            uint8_t f = D.flags[n];
+            if (f != LIQ && f != IFC) continue;
+            float r, a, b, e;
+            cell_rho_u<ST>(G, Ph, D.fB, n, r, a, b, e);
+            rs += r;
+            s0 += a;
+            s1 += b;
+            s2 += e;
+            ++cnt;
+        }
+        float inv = 1.0f / (float)cnt;
+        store_equilibrium<ST>(G, Ph, D.fB, c, rs * inv, s0 * inv, s1 * inv, s2 * inv);
+        D.m[c] = 0.0;
+    }
+    GRID_STRIDE(i, nL) {
+        int c = D.lNL[i], x, y, z;
+        cell_xyz(G, c, x, y, z);
+        D.m[c] = cell_rho<ST>(G, D, Ph, D.fB, c);
+        for (int q = 1; q < Q; ++q) {
+            int n = nbr_idx(G, x, y, z, q, 1);
+            if (n >= 0 && (D.cv[n] & CV_E)) { D.bub[c] = D.bub[n]; break; }
+        }
+    }
+}
+
+__global__ void k_conv_finalize(Dev D) {
+    int nF = list_len(D, C_NF), nE = list_len(D, C_NE), nG = list_len(D, C_NNG), nL = list_len(D, C_NNL);
+    GRID_STRIDE(i, nF) D.flags[D.lF[i]] = LIQ;
+    GRID_STRIDE(i, nE) D.flags[D.lE[i]] = GAS;
+    GRID_STRIDE(i, nG) D.flags[D.lNG[i]] = IFC;
+    GRID_STRIDE(i, nL) D.flags[D.lNL[i]] = IFC;
+}
+
+template <int ST>
+__device__ __forceinline__ void share_excess(const Geom &G, const Dev &D, int c, double ex) {
+    int x, y, z;
+    cell_xyz(G, c, x, y, z);
+    int k = 0;
+    for (int q = 1; q < Q; ++q) {
+        int n = nbr_idx(G, x, y, z, q, 1);
+        if (n >= 0 && D.flags[n] == IFC) ++k;
+    }
+    if (k == 0) {
+        unsafeAtomicAdd(D.ledger, ex);
+        return;
+    }
+    double part = ex / k;
+    for (int q = 1; q < Q; ++q) {
+        int n = nbr_idx(G, x, y, z, q, 1);
+        if (n >= 0 && D.flags[n] == IFC) unsafeAtomicAdd(D.m + n, part);
+    }
+}
+
+template <int ST>
+__global__ void k_conv_excess(Geom G, Phys Ph, Dev D) {
+    int nF = list_len(D, C_NF), nE = list_len(D, C_NE);
+    GRID_STRIDE(i, nF) {
+        int c = D.lF[i];
+        double ex = D.m[c] - cell_rho<ST>(G, D, Ph, D.fB, c);
+        D.m[c] = 0.0;
+        share_excess<ST>(G, D, c, ex);
+    }
+    GRID_STRIDE(i, nE) {
+        int c = D.lE[i];
+        double ex = D.m[c];
+        D.m[c] = 0.0;
+        share_excess<ST>(G, D, c, ex);
+    }
+}
+
+// root of a bubble id through the merge table; ids outside the table map to 0
+__device__ __forceinline__ int bubble_root(const Dev &D, int b) {
+    for (int it = 0; it < 64; ++it) {
+        if (b < 0 || b >= D.maxB) return 0;
+        int r = D.broot[b];
+        if (r == b) return b;
+        b = r;
+    }
+    return b < 0 || b >= D.maxB ? 0 : b;
+}
+
+template <int ST>
+__global__ void k_conv_fill(Geom G, Phys Ph, Dev D) {
+    int nF = list_len(D, C_NF), nE = list_len(D, C_NE);
+    int nE0 = list_len(D, C_NE0), nG = list_len(D, C_NNG), nL = list_len(D, C_NNL);
+    GRID_STRIDE(i, nF + nE) {
+        const bool filled = i < nF;
+        int c = filled ? D.lF[i] : D.lE[i - nF], x, y, z;
+        cell_xyz(G, c, x, y, z);
+        D.phi_nxt[c] = filled ? 1.0 : 0.0;
+        for (int q = 1; q < Q; ++q) {
+            int n = nbr_idx(G, x, y, z, q, 1);
+            if (n < 0) continue;
+            uint8_t f = D.flags[n];
+            if (f == IFC) {
+                D.phi_nxt[n] = D.m[n] / cell_rho<ST>(G, D, Ph, D.fB, n);
+            } else if (filled && f == GAS) {
+                atomicOr(D.err, ERR_LG);
+            } else if (!filled && f == LIQ) {
+                atomicOr(D.err, ERR_LG);
+            } else if (!filled && f == GAS) {
+                int a = bubble_root(D, D.bub[c]), b = bubble_root(D, D.bub[n]);
+                if (a != b) {
+                    int s = atomicAdd(D.counters + C_NMERGE, 1);
+                    if (s < D.cap) D.merges[s] = make_int2(a, b);
+                    else atomicOr(D.err, ERR_CAP);
+                }
+            }
+        }
+    }
+    GRID_STRIDE(i, nF) D.cv[D.lF[i]] = 0;
+    GRID_STRIDE(i, nE0) D.cv[D.lE0[i]] = 0;
+    GRID_STRIDE(i, nG) D.cv[D.lNG[i]] = 0;
+    GRID_STRIDE(i, nL) D.cv[D.lNL[i]] = 0;
+}
+
+// serial union of merged bubbles: the lower root id survives, gas masses add
+__global__ void k_bubble_merge(Dev D) {
+    if (blockIdx.x || threadIdx.x) return;
+    int n = list_len(D, C_NMERGE);
+    for (int i = 0; i < n; ++i) {
+        int a = bubble_root(D, D.merges[i].x), b = bubble_root(D, D.merges[i].y);
+        if (a == b) continue;
+        int lo = a < b ? a : b, hi = a < b ? b : a;
+        D.broot[hi] = lo;
+        D.btab[lo * B_STRIDE + B_M] += D.btab[hi * B_STRIDE + B_M];
+        D.balive[hi] = 0;
+    }
+}
+
+// ---- bubble volumes: dense pass over the cell types ------------------------------
+__global__ void k_bubble_zero(Dev D) {
+    GRID_STRIDE(i, D.nb * BACC_STRIDE) D.bacc[i] = 0.0;
+}
+
+// V_b = #gas cells + sum over interface cells of (1 - phi), with centroid moments;
+// per-block LDS accumulation (FP64), one global atomic per block and component
+__global__ __launch_bounds__(256) void k_bubble_accum(Geom G, Dev D, const double *phi) {
+    __shared__ double acc[64 * BACC_STRIDE];
+    __shared__ int root[64];
+    const int nb = D.nb;
+    for (int i = threadIdx.x; i < nb * BACC_STRIDE; i += blockDim.x) acc[i] = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) root[i] = bubble_root(D, i);
+    __syncthreads();
+    const long long N = G.N;
+    const long long nchunk = (N + 15) / 16;
+    for (long long ch = blockIdx.x * (long long)blockDim.x + threadIdx.x; ch < nchunk;
+         ch += (long long)gridDim.x * blockDim.x) {
+        long long c0 = ch * 16;
+        uint4 f4 = *(const uint4 *)(D.flags + c0);
+        uint32_t wds[4] = {f4.x, f4.y, f4.z, f4.w};
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            uint32_t v = wds[k];
+            // a byte is GAS (0) or IFC (2): test each byte
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) {
+                uint32_t f = (v >> (8 * bb)) & 0xffu;
+                any |= (f == GAS || f == IFC) && (c0 + 4 * k + bb < N);
+            }
+        }
+        if (!any) continue;
+        for (int k = 0; k < 16; ++k) {
+            long long c = c0 + k;
+            if (c >= N) break;
+            uint32_t f = (wds[k >> 2] >> (8 * (k & 3))) & 0xffu;
+            if (f != GAS && f != IFC) continue;
+            int id = D.bub[c];
+            int b = id < nb ? root[id] : 0;
+            double w = (f == GAS) ? 1.0 : 1.0 - phi[c];
+            int x = (int)(c % G.nx), y = (int)((c / G.nx) % G.ny), z = (int)(c / ((long long)G.nx * G.ny));
+            double *a = acc + b * BACC_STRIDE;
+            atomicAdd(a + 0, w);
+            atomicAdd(a + 1, w * x);
+            atomicAdd(a + 2, w * y);
+            atomicAdd(a + 3, w * z);
+            atomicAdd(a + (f == GAS ? 4 : 5), 1.0);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb * BACC_STRIDE; i += blockDim.x)
+        if (acc[i] != 0.0) unsafeAtomicAdd(D.bacc + i, acc[i]);
+}
+
+// rho_g = M / V for every root bubble; per-id FP32 mirror for the boundary condition
+// with init set, the gas densities of the initial state are read from the
+// table's density slot and the constant gas masses M = rho_g V(0) are fixed
+__global__ void k_bubble_finalize(Dev D, int init) {
+    if (blockIdx.x) return;
+    for (int b = threadIdx.x; b < D.nb; b += blockDim.x) {
+        double *t = D.btab + b * B_STRIDE;
+        const double *a = D.bacc + b * BACC_STRIDE;
+        if (init) {
+            t[B_M] = t[B_RHO] * a[0];
+            t[B_V0] = a[0];
+            D.balive[b] = a[0] > 0.0;
+            D.broot[b] = b;
+        }
+        if (D.broot[b] != b) continue;
+        t[B_V] = a[0];
+        t[B_NGAS] = a[4];
+        t[B_NIF] = a[5];
+        if (!D.balive[b]) continue;
+        if (a[0] > 0.0) {
+            t[B_RHO] = t[B_M] / a[0];
+            t[B_C] = a[1] / a[0];
+            t[B_C + 1] = a[2] / a[0];
+            t[B_C + 2] = a[3] / a[0];
+        } else if (t[B_M] > 0.0) {
+            atomicOr(D.err, ERR_VOL);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < D.nb; b += blockDim.x)
+        D.rhog[b] = (float)D.btab[bubble_root(D, b) * B_STRIDE + B_RHO];
+}
+
+}  // namespace fsl

@@ -1,0 +1,383 @@
+// k_particles.hpp -- rigid spheres (Sec. 2.3): force/torque hand-over from the
+// per-particle FP64 accumulators of the stream-collide kernel, lubrication
+// correction (Eq. lubrication) on a candidate-pair list from a uniform grid,
+// substep time integration, and the obstacle-coverage update (nodes inside a
+// sphere are obstacle nodes; covered / uncovered cells keep the mass ledger).
+#pragma once
+
+#include "k_free_surface.hpp"
+
+namespace fsl {
+
+constexpr int CLAIM_NONE = 0x7fffffff;
+
+// per particle: F, T of the step (reported), mass paid by moving bounce-back to the
+// ledger (block reduction then one atomic per block), accumulators cleared
+__global__ __launch_bounds__(256) void k_part_forces(Dev D, int integrate) {
+    __shared__ double red[256];
+    int P = blockIdx.x * blockDim.x + threadIdx.x;
+    double dm = 0.0;
+    if (P < D.np) {
+        double *a = D.pacc + (long long)P * ACC_STRIDE;
+        double *o = D.pFT + (long long)P * 6;
+        double *op = D.pFTp + (long long)P * 6;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            op[k] = o[k];
+            o[k] = a[k];
+        }
+        dm = a[6];
+#pragma unroll
+        for (int k = 0; k < ACC_STRIDE; ++k) a[k] = 0.0;
+        if (integrate) {
+            double *t = D.ptab + (long long)P * P_STRIDE;
+            t[P_XOLD] = t[P_X];
+            t[P_XOLD + 1] = t[P_X + 1];
+            t[P_XOLD + 2] = t[P_X + 2];
+            double *fl = D.pFl + (long long)P * 3;
+            fl[0] = fl[1] = fl[2] = 0.0;
+        }
+    }
+    red[threadIdx.x] = dm;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[0] != 0.0) unsafeAtomicAdd(D.ledger, -red[0]);
+}
+
+// ---- candidate pairs for lubrication: uniform grid ---------------------------------
+struct PGrid {
+    int g[3];
+    double cs[3];
+    double reach;  // pair candidate distance between surfaces
+};
+
+__device__ __forceinline__ int pgrid_cell(const PGrid &PG, const double *x, int a) {
+    int v = (int)floor(x[a] / PG.cs[a]);
+    return v < 0 ? 0 : (v >= PG.g[a] ? PG.g[a] - 1 : v);
+}
+
+__global__ void k_grid_zero(Dev D, int ncell) { GRID_STRIDE(i, ncell) D.gridCount[i] = 0; }
+
+__global__ void k_grid_count(Dev D, PGrid PG) {
+    GRID_STRIDE(P, D.np) {
+        const double *x = D.ptab + (long long)P * P_STRIDE;
+        int cell = pgrid_cell(PG, x, 0) + PG.g[0] * (pgrid_cell(PG, x, 1) + PG.g[1] * pgrid_cell(PG, x, 2));
+        atomicAdd(D.gridCount + cell, 1);
+    }
+}
+
+// exclusive scan of the grid counts by one block; gridCount becomes the fill cursor
+__global__ __launch_bounds__(1024) void k_grid_scan(Dev D, int ncell) {
+    __shared__ int part[1024];
+    const int T = blockDim.x, t = threadIdx.x;
+    int chunk = (ncell + T - 1) / T;
+    int lo = t * chunk, hi = min(ncell, lo + chunk);
+    int s = 0;
+    for (int i = lo; i < hi; ++i) s += D.gridCount[i];
+    part[t] = s;
+    __syncthreads();
+    for (int o = 1; o < T; o <<= 1) {
+        int v = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - s;
+    for (int i = lo; i < hi; ++i) {
+        int cnt = D.gridCount[i];
+        D.gridStart[i] = run;
+        D.gridCount[i] = run;
+        run += cnt;
+    }
+    if (t == T - 1) D.gridStart[ncell] = part[t];
+}
+
+__global__ void k_grid_fill(Dev D, PGrid PG) {
+    GRID_STRIDE(P, D.np) {
+        const double *x = D.ptab + (long long)P * P_STRIDE;
+        int cell = pgrid_cell(PG, x, 0) + PG.g[0] * (pgrid_cell(PG, x, 1) + PG.g[1] * pgrid_cell(PG, x, 2));
+        int s = atomicAdd(D.gridCount + cell, 1);
+        D.gridIdx[s] = P;
+    }
+}
+
+__global__ void k_pairs(Dev D, PGrid PG, int pcap) {
+    GRID_STRIDE(P, D.np) {
+        const double *x = D.ptab + (long long)P * P_STRIDE;
+        int c0 = pgrid_cell(PG, x, 0), c1 = pgrid_cell(PG, x, 1), c2 = pgrid_cell(PG, x, 2);
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int a = c0 + dx, b = c1 + dy, e = c2 + dz;
+                    if (a < 0 || b < 0 || e < 0 || a >= PG.g[0] || b >= PG.g[1] || e >= PG.g[2]) continue;
+                    int cell = a + PG.g[0] * (b + PG.g[1] * e);
+                    for (int s = D.gridStart[cell]; s < D.gridStart[cell + 1]; ++s) {
+                        int Qp = D.gridIdx[s];
+                        if (Qp <= P) continue;
+                        const double *y = D.ptab + (long long)Qp * P_STRIDE;
+                        double d0 = y[0] - x[0], d1 = y[1] - x[1], d2 = y[2] - x[2];
+                        double gap = sqrt(d0 * d0 + d1 * d1 + d2 * d2) - x[P_R] - y[P_R];
+                        if (gap < PG.reach) {
+                            int k = atomicAdd(D.counters + C_NPAIRS, 1);
+                            if (k < pcap) D.pairs[k] = make_int2(P, Qp);
+                            else atomicOr(D.err, ERR_CAP);
+                        }
+                    }
+                }
+    }
+}
+
+// Eq. (lubrication): only for gaps below Delta_c = 2/3, gap limited from below by
+// 0.2 Delta_c; equal and opposite on the pair
+__global__ void k_lub(Dev D, double mu, int pcap) {
+    int n = min(D.counters[C_NPAIRS], pcap);
+    GRID_STRIDE(k, n) {
+        int a = D.pairs[k].x, b = D.pairs[k].y;
+        const double *p1 = D.ptab + (long long)a * P_STRIDE, *p2 = D.ptab + (long long)b * P_STRIDE;
+        const double dc = 2.0 / 3.0;
+        double d0 = p2[0] - p1[0], d1 = p2[1] - p1[1], d2 = p2[2] - p1[2];
+        double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        double gap = dist - p1[P_R] - p2[P_R];
+        if (!(gap < dc) || dist <= 0.0) continue;
+        if (gap < 0.2 * dc) gap = 0.2 * dc;
+        double n0 = d0 / dist, n1 = d1 / dist, n2 = d2 / dist;
+        double rr = p1[P_R] * p2[P_R], sR = p1[P_R] + p2[P_R];
+        double coef = -6.0 * M_PI * mu * (rr * rr) / (sR * sR) * (1.0 / gap - 1.0 / dc);
+        double vn = n0 * (p1[P_U] - p2[P_U]) + n1 * (p1[P_U + 1] - p2[P_U + 1]) + n2 * (p1[P_U + 2] - p2[P_U + 2]);
+        double f0 = coef * vn * n0, f1 = coef * vn * n1, f2 = coef * vn * n2;
+        unsafeAtomicAdd(D.pFl + 3 * a, f0);
+        unsafeAtomicAdd(D.pFl + 3 * a + 1, f1);
+        unsafeAtomicAdd(D.pFl + 3 * a + 2, f2);
+        unsafeAtomicAdd(D.pFl + 3 * b, -f0);
+        unsafeAtomicAdd(D.pFl + 3 * b + 1, -f1);
+        unsafeAtomicAdd(D.pFl + 3 * b + 2, -f2);
+    }
+}
+
+// one semi-implicit Euler substep: velocity from F_hyd + m g + F_lub, then position;
+// angular velocity from T_hyd; normal velocity reversed when closer than R to a
+// wall face and moving towards it.  F_hyd, T_hyd are the mean of this and the
+// previous step's momentum exchange (two-step average that removes the period-two
+// oscillation of explicit coupling), or this step's alone after a table reset.
+__global__ void k_substep(Dev D, Geom G, double dt, double g0, double g1, double g2, int have_prev) {
+    GRID_STRIDE(P, D.np) {
+        double *t = D.ptab + (long long)P * P_STRIDE;
+        const double *FTn = D.pFT + (long long)P * 6, *FTp = D.pFTp + (long long)P * 6;
+        double FT[6];
+        for (int k = 0; k < 6; ++k) FT[k] = have_prev ? 0.5 * (FTn[k] + FTp[k]) : FTn[k];
+        double *fl = D.pFl + (long long)P * 3;
+        const double R = t[P_R];
+        const double mP = t[P_RHO] * (4.0 / 3.0) * M_PI * R * R * R;
+        const double IP = 0.4 * mP * R * R;
+        const double gg[3] = {g0, g1, g2};
+        const int n[3] = {G.nx, G.ny, G.nz};
+        for (int d = 0; d < 3; ++d) {
+            double F = FT[d] + mP * gg[d] + fl[d];
+            t[P_U + d] += dt * F / mP;
+            t[P_X + d] += dt * t[P_U + d];
+            t[P_W + d] += dt * FT[3 + d] / IP;
+            if (!G.per[d]) {
+                if (t[P_X + d] < R - 0.5 && t[P_U + d] < 0) t[P_U + d] = -t[P_U + d];
+                if (t[P_X + d] > n[d] - 0.5 - R && t[P_U + d] > 0) t[P_U + d] = -t[P_U + d];
+            }
+            fl[d] = 0.0;
+        }
+    }
+}
+
+// ---- coverage update --------------------------------------------------------------
+__device__ __forceinline__ void sphere_box(const Geom &G, const double *x, double R, int lo[3], int hi[3]) {
+    const int n[3] = {G.nx, G.ny, G.nz};
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = (int)floor(x[a] - R);
+        hi[a] = (int)ceil(x[a] + R);
+        if (lo[a] < 0) lo[a] = 0;
+        if (hi[a] > n[a] - 1) hi[a] = n[a] - 1;
+    }
+}
+
+__device__ __forceinline__ bool inside(double i, double j, double k, const double *x, double R) {
+    double d0 = i - x[0], d1 = j - x[1], d2 = k - x[2];
+    return __dadd_rn(__dadd_rn(__dmul_rn(d0, d0), __dmul_rn(d1, d1)), __dmul_rn(d2, d2)) <= __dmul_rn(R, R);
+}
+
+// one wave per particle walks its bounding box
+__global__ __launch_bounds__(256) void k_cov_claim(Geom G, Dev D) {
+    int P = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (P >= D.np) return;
+    const double *t = D.ptab + (long long)P * P_STRIDE;
+    int lo[3], hi[3];
+    sphere_box(G, t + P_X, t[P_R], lo, hi);
+    int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
+    int tot = ex * ey * ez;
+    for (int s = threadIdx.x & 63; s < tot; s += 64) {
+        int i = lo[0] + s % ex, j = lo[1] + (s / ex) % ey, k = lo[2] + s / (ex * ey);
+        if (inside(i, j, k, t + P_X, t[P_R])) atomicMin(D.claim + i + G.nx * (j + G.ny * k), P);
+    }
+}
+
+__device__ __forceinline__ int event_len(const Dev &D, int which) {
+    int n = D.counters[which];
+    return n < D.capEv ? n : D.capEv;
+}
+
+__device__ __forceinline__ void push_event(const Dev &D, int *list, int which, int cell, int P) {
+    int s = atomicAdd(D.counters + which, 1);
+    if (s < D.capEv) { list[2 * s] = cell; list[2 * s + 1] = P; }
+    else atomicOr(D.err, ERR_CAP);
+}
+
+__device__ __forceinline__ void classify_node(const Dev &D, int c, int P) {
+    int cl = D.claim[c];
+    uint8_t f = D.flags[c];
+    bool owned = (f == SOL) && D.pid[c] == P;
+    if (owned && cl == CLAIM_NONE) push_event(D, D.lUnc, C_NUNCOVER, c, P);
+    if (cl == P && !owned) {
+        if (f == SOL) D.pid[c] = P;  // owner changes to the lower index
+        else push_event(D, D.lCov, C_NCOVER, c, P);
+    }
+}
+
+// walks the union of the old and new bounding boxes
+__global__ __launch_bounds__(256) void k_cov_scan(Geom G, Dev D) {
+    int P = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (P >= D.np) return;
+    const double *t = D.ptab + (long long)P * P_STRIDE;
+    int lo[3], hi[3], lo2[3], hi2[3];
+    sphere_box(G, t + P_X, t[P_R], lo, hi);
+    sphere_box(G, t + P_XOLD, t[P_R], lo2, hi2);
+    for (int a = 0; a < 3; ++a) { lo[a] = min(lo[a], lo2[a]); hi[a] = max(hi[a], hi2[a]); }
+    int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
+    int tot = ex * ey * ez;
+    for (int s = threadIdx.x & 63; s < tot; s += 64) {
+        int i = lo[0] + s % ex, j = lo[1] + (s / ex) % ey, k = lo[2] + s / (ex * ey);
+        classify_node(D, i + G.nx * (j + G.ny * k), P);
+    }
+}
+
+// full-box variant used when the table is replaced (no previous positions)
+__global__ void k_cov_scan_dense(Geom G, Dev D) {
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < G.N;
+         c += (long long)gridDim.x * blockDim.x) {
+        int cl = D.claim[c];
+        uint8_t f = D.flags[c];
+        if (f == SOL) {
+            if (cl == CLAIM_NONE) push_event(D, D.lUnc, C_NUNCOVER, (int)c, D.pid[c]);
+            else D.pid[c] = cl;
+        } else if (cl != CLAIM_NONE) {
+            push_event(D, D.lCov, C_NCOVER, (int)c, cl);
+        }
+    }
+}
+
+template <int ST>
+__global__ void k_cov_apply(Geom G, Phys Ph, Dev D, double *phi) {
+    int n = event_len(D, C_NCOVER);
+    GRID_STRIDE(e, n) {
+        int c = D.lCov[2 * e], P = D.lCov[2 * e + 1];
+        uint8_t f = D.flags[c];
+        if (f == LIQ) unsafeAtomicAdd(D.ledger, cell_rho<ST>(G, D, Ph, D.fB, c));
+        else if (f == IFC) unsafeAtomicAdd(D.ledger, D.m[c]);
+        D.flags[c] = SOL;
+        D.pid[c] = P;
+        phi[c] = 0.0;
+    }
+}
+
+// decision with the flags after covering (uncovered nodes are still solid)
+template <int ST>
+__global__ void k_unc_decide(Geom G, Phys Ph, Dev D) {
+    int n = event_len(D, C_NUNCOVER);
+    GRID_STRIDE(e, n) {
+        int c = D.lUnc[2 * e], x, y, z;
+        cell_xyz(G, c, x, y, z);
+        int nli = 0, gfirst = -1;
+        double rs = 0.0;
+        for (int q = 1; q < Q; ++q) {
+            int nb = nbr_idx(G, x, y, z, q, 1);
+            if (nb < 0) continue;
+            uint8_t f = D.flags[nb];
+            if (f == LIQ || f == IFC) {
+                rs += cell_rho<ST>(G, D, Ph, D.fB, nb);
+                ++nli;
+            } else if (f == GAS && gfirst < 0) {
+                gfirst = nb;
+            }
+        }
+        int type = nli > 0 ? (gfirst >= 0 ? IFC : LIQ) : (gfirst >= 0 ? GAS : LIQ);
+        int bub = gfirst >= 0 ? D.bub[gfirst] : 0;
+        D.uncDec[e] = type | (bub << 8);
+        D.uncRho[e] = nli > 0 ? rs / nli : 1.0;
+    }
+}
+
+template <int ST>
+__global__ void k_unc_apply(Geom G, Phys Ph, Dev D, double *phi) {
+    int n = event_len(D, C_NUNCOVER);
+    GRID_STRIDE(e, n) {
+        int c = D.lUnc[2 * e], P = D.lUnc[2 * e + 1], x, y, z;
+        cell_xyz(G, c, x, y, z);
+        int type = D.uncDec[e] & 0xff, bub = D.uncDec[e] >> 8;
+        double rb = D.uncRho[e];
+        D.pid[c] = -1;
+        D.flags[c] = (uint8_t)type;
+        if (type == GAS) {
+            D.bub[c] = (uint16_t)bub;
+            phi[c] = 0.0;
+            continue;
+        }
+        float u0 = 0.f, u1 = 0.f, u2 = 0.f;
+        if ((unsigned)P < (unsigned)D.np) {
+            const double *t = D.ptab + (long long)P * P_STRIDE;
+            double rx = x - t[P_X], ry = y - t[P_X + 1], rz = z - t[P_X + 2];
+            u0 = (float)(t[P_U] + (t[P_W + 1] * rz - t[P_W + 2] * ry));
+            u1 = (float)(t[P_U + 1] + (t[P_W + 2] * rx - t[P_W] * rz));
+            u2 = (float)(t[P_U + 2] + (t[P_W] * ry - t[P_W + 1] * rx));
+        }
+        store_equilibrium<ST>(G, Ph, D.fB, c, (float)(rb - 1.0), u0, u1, u2);
+        unsafeAtomicAdd(D.ledger, -rb);
+        phi[c] = 1.0;
+        if (type == IFC) {
+            D.m[c] = rb;
+            D.bub[c] = (uint16_t)bub;
+        }
+    }
+}
+
+__global__ void k_unc_closure(Geom G, Dev D, double *phi) {
+    int n = event_len(D, C_NUNCOVER);
+    GRID_STRIDE(e, n) {
+        int c = D.lUnc[2 * e], x, y, z;
+        if ((D.uncDec[e] & 0xff) != LIQ) continue;
+        cell_xyz(G, c, x, y, z);
+        for (int q = 1; q < Q; ++q) {
+            int nb = nbr_idx(G, x, y, z, q, 1);
+            if (nb >= 0 && D.flags[nb] == GAS) {
+                D.flags[c] = IFC;
+                D.m[c] = D.uncRho[e];
+                phi[c] = 1.0;
+                D.bub[c] = D.bub[nb];
+                break;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cov_reset(Geom G, Dev D) {
+    int P = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (P >= D.np) return;
+    const double *t = D.ptab + (long long)P * P_STRIDE;
+    int lo[3], hi[3];
+    sphere_box(G, t + P_X, t[P_R], lo, hi);
+    int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
+    int tot = ex * ey * ez;
+    for (int s = threadIdx.x & 63; s < tot; s += 64) {
+        int i = lo[0] + s % ex, j = lo[1] + (s / ex) % ey, k = lo[2] + s / (ex * ey);
+        D.claim[i + G.nx * (j + G.ny * k)] = CLAIM_NONE;
+    }
+}
+
+}  // namespace fsl

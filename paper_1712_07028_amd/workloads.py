@@ -88,7 +88,7 @@ def rsa_spheres(n_target, R, box, zs, bubble=None, seed=0, gap=1.0, max_draws=No
     dmin = 2 * R + gap
     acc = np.empty((0, 3))
     draws = 0
-    max_draws = max_draws or 200 * n_target + 10000
+    max_draws = max_draws or 2000 * n_target + 100000
     while acc.shape[0] < n_target and draws < max_draws:
         cand = _draw_centres(rng, lo, hi, batch)
         draws += batch
