@@ -160,13 +160,14 @@ const char *fsl_error_string(const fsl_ctx *ctx);
 /* Free the host context (not the workspace). */
 void fsl_destroy(fsl_ctx *ctx);
 
-/* Per-kernel timing with HIP events on the library's stream.  When enabled, each
- * launch of the named kernels is bracketed by events; fsl_profile_get returns,
- * for kernel k (0 = fused stream-collide, 1 = conversions, 2 = bubbles,
- * 3 = particles), the summed milliseconds and launch counts since the last reset
- * (synchronises).  Off by default. */
+/* Per-phase timing with HIP events on the library's stream.  When enabled, each
+ * phase of a step is bracketed by events; fsl_profile_get writes, for phase k < n
+ * (0 = fused stream-collide kernel, 1 = cell conversions, 2 = bubble volumes,
+ * 3 = particle pairs and forces, 4 = particle substeps, 5 = coverage update), the
+ * summed milliseconds and counts since the last call, resets them, synchronises
+ * and returns the number of phases (6).  Off by default. */
 int fsl_profile_enable(fsl_ctx *ctx, int on);
-int fsl_profile_get(fsl_ctx *ctx, double ms[4], long long count[4]);
+int fsl_profile_get(fsl_ctx *ctx, double *ms, long long *count, int n);
 
 /* Differentiation form (flags frozen over a window, Sec. 2.1/2.3 operators):
  * fsl_window_forward runs T steps from the current state with flags, particle

@@ -83,7 +83,7 @@ def load_library(path=LIB_PATH):
     L.fsl_error_string.argtypes = [P]
     L.fsl_destroy.argtypes = [P]
     L.fsl_profile_enable.argtypes = [P, ctypes.c_int]
-    L.fsl_profile_get.argtypes = [P, dp, ctypes.POINTER(ctypes.c_longlong)]
+    L.fsl_profile_get.argtypes = [P, dp, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
     L.fsl_window_forward.argtypes = [P, ctypes.c_int, ctypes.c_int, dp]
     L.fsl_window_backward.argtypes = [P, ctypes.c_double, dp, dp]
     _lib = L
@@ -230,12 +230,17 @@ class Sim:
     def profile(self, on=True):
         self._check(self.L.fsl_profile_enable(self.ctx, int(on)), "fsl_profile_enable")
 
+    PHASES = ("stream_collide", "conversions", "bubbles", "particle_forces", "particle_substeps",
+              "coverage")
+
     def profile_get(self):
-        ms = np.zeros(4)
-        cnt = (ctypes.c_longlong * 4)()
-        self._check(self.L.fsl_profile_get(self.ctx, _dp(ms), cnt), "fsl_profile_get")
-        names = ("stream_collide", "conversions", "bubbles", "particles")
-        return {n: (ms[i], cnt[i]) for i, n in enumerate(names)}
+        n = len(self.PHASES)
+        ms = np.zeros(n)
+        cnt = (ctypes.c_longlong * n)()
+        rc = self.L.fsl_profile_get(self.ctx, _dp(ms), cnt, n)
+        if rc < 0:
+            self._check(rc, "fsl_profile_get")
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(self.PHASES)}
 
     def window_forward(self, T, k):
         J = ctypes.c_double(0)

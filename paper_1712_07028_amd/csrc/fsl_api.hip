@@ -28,14 +28,14 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 constexpr int LIST_BLOCKS = 128;
-constexpr int NPROF = 4;
+constexpr int NPROF = 6;
 
 size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
     size_t fA, fB, flags, cv, phiA, phiB, m, bub, pid, claim;
     size_t lF, lE0, lE, lNG, lNL, lCov, lUnc, uncRho, uncDec, merges, pairs;
-    size_t counters, ctl, ptab, pacc, pFT, pFTp, pFl, gStart, gCount, gIdx;
+    size_t counters, ctl, ptab, pacc, pFT, pFTp, pFl, pmir, gStart, gCount, gIdx;
     size_t btab, bacc, broot, balive, rhog, stage;
     size_t win;  // differentiation window storage
     size_t total;
@@ -108,6 +108,7 @@ Layout layout_of(const fsl_config *c) {
     L.pFT = take((size_t)L.maxP * 6 * 8);
     L.pFTp = take((size_t)L.maxP * 6 * 8);
     L.pFl = take((size_t)L.maxP * 3 * 8);
+    L.pmir = take((size_t)L.maxP * 64);
     L.gStart = take((size_t)(L.ncellMax + 1) * 4);
     L.gCount = take((size_t)L.ncellMax * 4);
     L.gIdx = take((size_t)L.maxP * 4);
@@ -225,6 +226,9 @@ void set_phys(fsl_ctx *c) {
 }
 
 template <int ST> int enqueue_steps(fsl_ctx *c, int n);
+template <int ST> int enqueue_integration(fsl_ctx *c);
+template <int ST> int enqueue_pair_forces(fsl_ctx *c);
+template <int ST> int enqueue_coverage_step(fsl_ctx *c);
 template <int ST> int enqueue_coverage_full(fsl_ctx *c);
 template <int ST> int enqueue_bubbles(fsl_ctx *c, double *phi, int init);
 
@@ -270,16 +274,35 @@ int enqueue_cover_events(fsl_ctx *c, const Dev &Dv, double *phi) {
 
 template <int ST>
 int enqueue_particles(fsl_ctx *c) {
-    ProfScope ps(c, 3);
+    int rc = enqueue_pair_forces<ST>(c);
+    if (rc || !c->cfg.integrate) return rc;
+    rc = enqueue_integration<ST>(c);
+    if (rc) return rc;
+    return enqueue_coverage_step<ST>(c);
+}
+
+template <int ST>
+int enqueue_pair_forces(fsl_ctx *c) {
     Dev &D = c->D;
     const int np = D.np;
-    hipLaunchKernelGGL(k_part_forces, dim3((np + 255) / 256), dim3(256), 0, c->st, D, c->cfg.integrate);
-    if (!c->cfg.integrate) { LAUNCHCHK(c); return FSL_OK; }
+    ProfScope ps(c, 3);
+    // candidate pairs (positions at t): particle-particle links and lubrication
     hipLaunchKernelGGL(k_grid_zero, dim3(grid_for(c->ncell)), dim3(256), 0, c->st, D, c->ncell);
     hipLaunchKernelGGL(k_grid_count, dim3(grid_for(np)), dim3(256), 0, c->st, D, c->PG);
     hipLaunchKernelGGL(k_grid_scan, dim3(1), dim3(1024), 0, c->st, D, c->ncell);
     hipLaunchKernelGGL(k_grid_fill, dim3(grid_for(np)), dim3(256), 0, c->st, D, c->PG);
     hipLaunchKernelGGL(k_pairs, dim3(grid_for(np)), dim3(256), 0, c->st, D, c->PG, c->L.pcap);
+    hipLaunchKernelGGL(k_solid_pairs, dim3(grid_for(c->L.pcap, 4, 8192)), dim3(256), 0, c->st, c->G, D, c->L.pcap);
+    hipLaunchKernelGGL(k_part_forces, dim3((np + 255) / 256), dim3(256), 0, c->st, D, c->cfg.integrate);
+    LAUNCHCHK(c);
+    return FSL_OK;
+}
+
+template <int ST>
+int enqueue_integration(fsl_ctx *c) {
+    Dev &D = c->D;
+    const int np = D.np;
+    ProfScope ps(c, 4);
     const int ns = c->cfg.n_sub > 0 ? c->cfg.n_sub : 10;
     const double mu = (c->cfg.tau - 0.5) / 3.0;
     for (int s = 0; s < ns; ++s) {
@@ -288,12 +311,22 @@ int enqueue_particles(fsl_ctx *c) {
                            c->cfg.g[0], c->cfg.g[1], c->cfg.g[2], c->have_prev);
     }
     c->have_prev = 1;
+    LAUNCHCHK(c);
+    return FSL_OK;
+}
+
+template <int ST>
+int enqueue_coverage_step(fsl_ctx *c) {
+    Dev &D = c->D;
+    const int np = D.np;
+    ProfScope ps(c, 5);
     dim3 pw((np + 3) / 4);
     hipLaunchKernelGGL(k_cov_claim, pw, dim3(256), 0, c->st, c->G, D);
     hipLaunchKernelGGL(k_cov_scan, pw, dim3(256), 0, c->st, c->G, D);
     int rc = enqueue_cover_events<ST>(c, D, D.phi_nxt);
     if (rc) return rc;
     hipLaunchKernelGGL(k_cov_reset, pw, dim3(256), 0, c->st, c->G, D);
+    hipLaunchKernelGGL(k_part_mirror, dim3(grid_for(np)), dim3(256), 0, c->st, D);
     LAUNCHCHK(c);
     return FSL_OK;
 }
@@ -437,6 +470,7 @@ int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, 
     D.pFT = (double *)(w + L.pFT);
     D.pFTp = (double *)(w + L.pFTp);
     D.pFl = (double *)(w + L.pFl);
+    D.pmir = (float4 *)(w + L.pmir);
     D.gridStart = (int *)(w + L.gStart);
     D.gridCount = (int *)(w + L.gCount);
     D.gridIdx = (int *)(w + L.gIdx);
@@ -563,6 +597,7 @@ int fsl_particles_set(fsl_ctx *c, int n, const double *x, const double *u, const
     c->PG.reach = reach;
     if (tot > c->L.ncellMax) return fail(c, FSL_E_ARG, "particles_set: radius too small for the pair grid");
     c->ncell = (int)tot;
+    if (n > 0) hipLaunchKernelGGL(k_part_mirror, dim3(grid_for(n)), dim3(256), 0, c->st, D);
     int rc = by_storage(c, [&](auto st) { return enqueue_coverage_full<decltype(st)::value>(c); });
     if (rc) return rc;
     return read_error(c);
@@ -757,8 +792,8 @@ int fsl_profile_enable(fsl_ctx *c, int on) {
     return FSL_OK;
 }
 
-int fsl_profile_get(fsl_ctx *c, double ms[4], long long count[4]) {
-    if (!c) return FSL_E_ARG;
+int fsl_profile_get(fsl_ctx *c, double *ms, long long *count, int n) {
+    if (!c || n < 0) return FSL_E_ARG;
     HIPCHK(c, hipStreamSynchronize(c->st));
     for (auto &e : c->evlog) {
         float t = 0;
@@ -771,12 +806,12 @@ int fsl_profile_get(fsl_ctx *c, double ms[4], long long count[4]) {
     }
     c->evlog.clear();
     for (int k = 0; k < NPROF; ++k) {
-        if (ms) ms[k] = c->prof_ms[k];
-        if (count) count[k] = c->prof_n[k];
+        if (ms && k < n) ms[k] = c->prof_ms[k];
+        if (count && k < n) count[k] = c->prof_n[k];
         c->prof_ms[k] = 0;
         c->prof_n[k] = 0;
     }
-    return FSL_OK;
+    return NPROF;
 }
 
 int fsl_window_forward(fsl_ctx *c, int T, int k, double *J) {

@@ -126,6 +126,7 @@ struct Dev {
     unsigned *err;
     double *ledger;                  // [0] ledger
     double *ptab, *pacc, *pFT, *pFTp, *pFl; // particles (pFTp: previous step's F, T)
+    float4 *pmir;                    // FP32 mirror per particle: anchor, fraction, u, omega
     int *gridStart, *gridCount, *gridIdx;
     double *btab, *bacc;
     int *broot, *balive;

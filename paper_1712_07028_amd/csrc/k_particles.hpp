@@ -47,6 +47,35 @@ __global__ __launch_bounds__(256) void k_part_forces(Dev D, int integrate) {
     if (threadIdx.x == 0 && red[0] != 0.0) unsafeAtomicAdd(D.ledger, -red[0]);
 }
 
+__device__ __forceinline__ void sphere_box(const Geom &G, const double *x, double R, int lo[3], int hi[3]) {
+    const int n[3] = {G.nx, G.ny, G.nz};
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = (int)floor(x[a] - R);
+        hi[a] = (int)ceil(x[a] + R);
+        if (lo[a] < 0) lo[a] = 0;
+        if (hi[a] > n[a] - 1) hi[a] = n[a] - 1;
+    }
+}
+
+__device__ __forceinline__ bool inside(double i, double j, double k, const double *x, double R) {
+    double d0 = i - x[0], d1 = j - x[1], d2 = k - x[2];
+    return __dadd_rn(__dadd_rn(__dmul_rn(d0, d0), __dmul_rn(d1, d1)), __dmul_rn(d2, d2)) <= __dmul_rn(R, R);
+}
+
+// FP32 mirror used by the stream-collide kernel: integer anchor floor(x_P), the
+// fraction x_P - anchor, velocity and angular velocity
+__global__ void k_part_mirror(Dev D) {
+    GRID_STRIDE(P, D.np) {
+        const double *t = D.ptab + (long long)P * P_STRIDE;
+        float4 *m = D.pmir + 4LL * P;
+        double a0 = floor(t[P_X]), a1 = floor(t[P_X + 1]), a2 = floor(t[P_X + 2]);
+        m[0] = make_float4((float)a0, (float)a1, (float)a2, 0.f);
+        m[1] = make_float4((float)(t[P_X] - a0), (float)(t[P_X + 1] - a1), (float)(t[P_X + 2] - a2), 0.f);
+        m[2] = make_float4((float)t[P_U], (float)t[P_U + 1], (float)t[P_U + 2], 0.f);
+        m[3] = make_float4((float)t[P_W], (float)t[P_W + 1], (float)t[P_W + 2], 0.f);
+    }
+}
+
 // ---- candidate pairs for lubrication: uniform grid ---------------------------------
 struct PGrid {
     int g[3];
@@ -130,6 +159,62 @@ __global__ void k_pairs(Dev D, PGrid PG, int pcap) {
     }
 }
 
+// Momentum exchange between two particles (Sec. 2.3): a node inside particle P'
+// with a link into particle P contributes with equilibrium populations at rho = 1
+// and the rigid velocity of P' at the node, Delta j = 2 c_q e^+_q(1, u_P'(x)), to
+// P's force and torque.  Such nodes exist only for pairs closer than sqrt(2), all
+// of which are in the candidate list; one wave per pair scans the nodes of each
+// particle that lie within one cell of the other's bounding box.
+__global__ __launch_bounds__(256) void k_solid_pairs(Geom G, Dev D, int pcap) {
+    const int n = min(D.counters[C_NPAIRS], pcap);
+    const int lane = threadIdx.x & 63;
+    for (int k = blockIdx.x * 4 + (threadIdx.x >> 6); k < n; k += gridDim.x * 4) {
+    const int pa = D.pairs[k].x, pb = D.pairs[k].y;
+    for (int side = 0; side < 2; ++side) {
+        const int Pp = side ? pb : pa, Po = side ? pa : pb;
+        const double *tp = D.ptab + (long long)Pp * P_STRIDE, *to = D.ptab + (long long)Po * P_STRIDE;
+        int lo[3], hi[3], lo2[3], hi2[3];
+        sphere_box(G, tp + P_X, tp[P_R], lo, hi);
+        sphere_box(G, to + P_X, to[P_R] + 1.0, lo2, hi2);
+        for (int a = 0; a < 3; ++a) { lo[a] = max(lo[a], lo2[a]); hi[a] = min(hi[a], hi2[a]); }
+        double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+        if (lo[0] <= hi[0] && lo[1] <= hi[1] && lo[2] <= hi[2]) {
+            const int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
+            const int tot = ex * ey * ez;
+            for (int s2 = lane; s2 < tot; s2 += 64) {
+                const int i = lo[0] + s2 % ex, j = lo[1] + (s2 / ex) % ey, kk = lo[2] + s2 / (ex * ey);
+                const int c = i + G.nx * (j + G.ny * kk);
+                if (D.flags[c] != SOL || D.pid[c] != Pp) continue;
+                const double rx = i - tp[P_X], ry = j - tp[P_X + 1], rz = kk - tp[P_X + 2];
+                const double ur0 = tp[P_U] + (tp[P_W + 1] * rz - tp[P_W + 2] * ry);
+                const double ur1 = tp[P_U + 1] + (tp[P_W + 2] * rx - tp[P_W] * rz);
+                const double ur2 = tp[P_U + 2] + (tp[P_W] * ry - tp[P_W + 1] * rx);
+                const double uu = ur0 * ur0 + ur1 * ur1 + ur2 * ur2;
+                const double ox = i - to[P_X], oy = j - to[P_X + 1], oz = kk - to[P_X + 2];
+                for (int q = 1; q < Q; ++q) {
+                    const int nb = nbr_idx(G, i, j, kk, q, 1);
+                    if (nb < 0 || D.flags[nb] != SOL || D.pid[nb] != Po) continue;
+                    const double cu = cx(q) * ur0 + cy(q) * ur1 + cz(q) * ur2;
+                    const double e2 = 2.0 * wqd(q) * (1.0 + 4.5 * cu * cu - 1.5 * uu);
+                    const double j0 = cx(q) * e2, j1 = cy(q) * e2, j2 = cz(q) * e2;
+                    acc[0] += j0;
+                    acc[1] += j1;
+                    acc[2] += j2;
+                    acc[3] += oy * j2 - oz * j1;
+                    acc[4] += oz * j0 - ox * j2;
+                    acc[5] += ox * j1 - oy * j0;
+                }
+            }
+        }
+        double *dst = D.pacc + (long long)Po * ACC_STRIDE;
+        for (int a = 0; a < 6; ++a) {
+            const double v = wave_sum(acc[a]);
+            if (lane == 0 && v != 0.0) unsafeAtomicAdd(dst + a, v);
+        }
+    }
+    }
+}
+
 // Eq. (lubrication): only for gaps below Delta_c = 2/3, gap limited from below by
 // 0.2 Delta_c; equal and opposite on the pair
 __global__ void k_lub(Dev D, double mu, int pcap) {
@@ -189,21 +274,6 @@ __global__ void k_substep(Dev D, Geom G, double dt, double g0, double g1, double
 }
 
 // ---- coverage update --------------------------------------------------------------
-__device__ __forceinline__ void sphere_box(const Geom &G, const double *x, double R, int lo[3], int hi[3]) {
-    const int n[3] = {G.nx, G.ny, G.nz};
-    for (int a = 0; a < 3; ++a) {
-        lo[a] = (int)floor(x[a] - R);
-        hi[a] = (int)ceil(x[a] + R);
-        if (lo[a] < 0) lo[a] = 0;
-        if (hi[a] > n[a] - 1) hi[a] = n[a] - 1;
-    }
-}
-
-__device__ __forceinline__ bool inside(double i, double j, double k, const double *x, double R) {
-    double d0 = i - x[0], d1 = j - x[1], d2 = k - x[2];
-    return __dadd_rn(__dadd_rn(__dmul_rn(d0, d0), __dmul_rn(d1, d1)), __dmul_rn(d2, d2)) <= __dmul_rn(R, R);
-}
-
 // one wave per particle walks its bounding box
 __global__ __launch_bounds__(256) void k_cov_claim(Geom G, Dev D) {
     int P = blockIdx.x * 4 + (threadIdx.x >> 6);

@@ -21,40 +21,58 @@ namespace fsl {
 
 constexpr int TX = 64, TY = 4;
 
+// Per-lane momentum-exchange accumulator for the links of one particle.
+// Delta j of a link (Eq. momentum_transfer) is -c_q (h*_qbar + h_q + 2 w_q) in
+// shifted populations; the small shifted parts are summed in FP32 and the
+// constant parts 2 w_q c_q are counted exactly as integer direction sums
+// (axis links 2w = 1/9, diagonal links 2w = 1/18).  All links of a lane share
+// the node x, so the torque (x - x_P) x F is formed once per lane in FP64.
 struct LinkAcc {
     int P;
-    double a[7];  // F(3), T(3), mass added by moving bounce-back
+    float fs[3];   // sum of -c_q (h*_qbar + h_q)
+    int ca[3];     // sum of -c_q over axis links
+    int cd[3];     // sum of -c_q over diagonal links
+    float dm;      // mass added by moving bounce-back at a liquid cell
 };
 
-__device__ __forceinline__ void acc_flush(const Dev &D, LinkAcc &L) {
+__device__ __forceinline__ void acc_zero(LinkAcc &L) {
+    L.fs[0] = L.fs[1] = L.fs[2] = 0.f;
+    L.ca[0] = L.ca[1] = L.ca[2] = 0;
+    L.cd[0] = L.cd[1] = L.cd[2] = 0;
+    L.dm = 0.f;
+}
+
+// FP64 force, torque and mass of the lane's links (a[0..6])
+__device__ __forceinline__ void acc_expand(const Dev &D, const LinkAcc &L, int x, int y, int z, double a[7]) {
+    double F[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) F[k] = (double)L.fs[k] + (L.ca[k] * (1.0 / 9.0) + L.cd[k] * (1.0 / 18.0));
+    const double *pt = D.ptab + (long long)L.P * P_STRIDE;
+    const double rx = x - pt[P_X], ry = y - pt[P_X + 1], rz = z - pt[P_X + 2];
+    a[0] = F[0];
+    a[1] = F[1];
+    a[2] = F[2];
+    a[3] = ry * F[2] - rz * F[1];
+    a[4] = rz * F[0] - rx * F[2];
+    a[5] = rx * F[1] - ry * F[0];
+    a[6] = (double)L.dm;
+}
+
+__device__ __noinline__ void acc_flush(const Dev &D, const LinkAcc &L, int x, int y, int z) {
     if (L.P < 0) return;
+    double a[7];
+    acc_expand(D, L, x, y, z, a);
     double *dst = D.pacc + (long long)L.P * ACC_STRIDE;
 #pragma unroll
-    for (int k = 0; k < 7; ++k) unsafeAtomicAdd(dst + k, L.a[k]);
+    for (int k = 0; k < 7; ++k) unsafeAtomicAdd(dst + k, a[k]);
 }
 
-__device__ __forceinline__ void acc_add(const Dev &D, LinkAcc &L, int P, double djx, double djy,
-                                        double djz, double rx, double ry, double rz, double dm) {
-    if (P != L.P) {
-        acc_flush(D, L);
-        L.P = P;
-#pragma unroll
-        for (int k = 0; k < 7; ++k) L.a[k] = 0.0;
-    }
-    double jx = djx, jy = djy, jz = djz;
-    L.a[0] += jx;
-    L.a[1] += jy;
-    L.a[2] += jz;
-    L.a[3] += ry * jz - rz * jy;
-    L.a[4] += rz * jx - rx * jz;
-    L.a[5] += rx * jy - ry * jx;
-    L.a[6] += dm;
-}
-
-// wave-level reduction of the per-lane accumulators, segmented by particle id:
+// wave-level reduction of the lanes' accumulators, segmented by particle id:
 // one FP64 atomic per (wave, particle, component)
-__device__ __forceinline__ void acc_reduce_wave(const Dev &D, LinkAcc &L) {
+__device__ __forceinline__ void acc_reduce_wave(const Dev &D, const LinkAcc &L, int x, int y, int z) {
     int key = L.P;
+    double a[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (key >= 0) acc_expand(D, L, x, y, z, a);
     while (true) {
         unsigned long long act = __ballot(key >= 0);
         if (!act) break;
@@ -64,81 +82,78 @@ __device__ __forceinline__ void acc_reduce_wave(const Dev &D, LinkAcc &L) {
         double *dst = D.pacc + (long long)k0 * ACC_STRIDE;
 #pragma unroll
         for (int k = 0; k < 7; ++k) {
-            double v = wave_sum(mine ? L.a[k] : 0.0);
+            double v = wave_sum(mine ? a[k] : 0.0);
             if ((int)lane_id() == leader) unsafeAtomicAdd(dst + k, v);
         }
         if (mine) key = -1;
     }
 }
 
-template <int ST>
-__global__ __launch_bounds__(256) void k_stream_collide(Geom G, Phys Ph, Dev D, int tilesX,
-                                                        int tilesY, int nTiles) {
+// One cell of the fused step.  INTERIOR: the tile and its halo lie inside the box,
+// so a source is the cell index minus a uniform offset (no wrap, no wall).
+template <int ST, bool INTERIOR>
+__device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev &D,
+                                        const uint8_t (&tile)[3][TY + 2][TX + 2], int lx, int ly,
+                                        int x, int y, int z) {
     using SS = Store<ST>;
     using T = typename SS::T;
-    __shared__ uint8_t tile[3][TY + 2][TX + 2];
-
-    const int nx = G.nx, ny = G.ny, nz = G.nz;
-    int b = blockIdx.x;
-    int t = (nTiles % 8 == 0) ? (b % 8) * (nTiles / 8) + b / 8 : b;
-    const int x0 = (t % tilesX) * TX;
-    const int rest = t / tilesX;
-    const int y0 = (rest % tilesY) * TY;
-    const int z = rest / tilesY;
-
-    for (int i = threadIdx.x; i < 3 * (TY + 2) * (TX + 2); i += 256) {
-        int lx = i % (TX + 2), ly = (i / (TX + 2)) % (TY + 2), lz = i / ((TX + 2) * (TY + 2));
-        int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z + lz - 1;
-        bool ok = true;
-        if (gx < 0 || gx >= nx) { if (G.per[0]) gx = wrapc(gx, nx); else ok = false; }
-        if (gy < 0 || gy >= ny) { if (G.per[1]) gy = wrapc(gy, ny); else ok = false; }
-        if (gz < 0 || gz >= nz) { if (G.per[2]) gz = wrapc(gz, nz); else ok = false; }
-        uint8_t v = WALL;
-        if (ok) v = D.flags[gx + (long long)nx * (gy + (long long)ny * gz)];
-        tile[lz][ly][lx] = v;
-    }
-    __syncthreads();
-
-    const int lx = threadIdx.x & (TX - 1), ly = threadIdx.x >> 6;
-    const int x = x0 + lx, y = y0 + ly;
-    if (x >= nx || y >= ny) return;
-    const int c = x + nx * (y + ny * z);
+    const int nx = G.nx, ny = G.ny, nz = G.nz, nxy = nx * ny;
+    const int c = x + nx * y + nxy * z;
     const uint8_t fl = tile[1][ly + 1][lx + 1];
-
-    LinkAcc acc;
-    acc.P = -1;
-#pragma unroll
-    for (int k = 0; k < 7; ++k) acc.a[k] = 0.0;
-    bool isF = false, isE = false;
-
     const T *A = (const T *)D.fA;
     T *B = (T *)D.fB;
     const long long S = G.S;
     const float inv = Ph.inv, sc = Ph.scale;
+    auto src = [&](int q) -> int {
+        if (INTERIOR) return c - (cx(q) + cy(q) * nx + cz(q) * nxy);
+        const int sx = wrapc(x - cx(q), nx), sy = wrapc(y - cy(q), ny), sz = wrapc(z - cz(q), nz);
+        return sx + nx * sy + nxy * sz;
+    };
+    auto nbr = [&](int q) -> int {
+        if (INTERIOR) return c + (cx(q) + cy(q) * nx + cz(q) * nxy);
+        const int sx = wrapc(x + cx(q), nx), sy = wrapc(y + cy(q), ny), sz = wrapc(z + cz(q), nz);
+        return sx + nx * sy + nxy * sz;
+    };
+
+    LinkAcc acc;
+    acc.P = -1;
+    acc_zero(acc);
+    bool isF = false, isE = false;
 
     if (fl == LIQ || fl == IFC) {
         uint32_t gm = 0, sm = 0, wm = 0;
 #pragma unroll
         for (int q = 1; q < Q; ++q) {
-            uint8_t sf = tile[1 - cz(q)][ly + 1 - cy(q)][lx + 1 - cx(q)];
+            const uint8_t sf = tile[1 - cz(q)][ly + 1 - cy(q)][lx + 1 - cx(q)];
             gm |= (uint32_t)(sf == GAS) << q;
             sm |= (uint32_t)(sf == SOL) << q;
-            wm |= (uint32_t)(sf == WALL) << q;
+            if (!INTERIOR) wm |= (uint32_t)(sf == WALL) << q;
         }
+        const uint32_t miss = gm | sm | wm;
         const bool needOwn = (fl == IFC) || gm || sm;
         float fo[Q], fi[Q];
+        // all independent loads first: own populations, pulled populations, ids
         if (needOwn) {
 #pragma unroll
             for (int q = 0; q < Q; ++q) fo[q] = SS::ld(A + q * S + c, inv);
         }
         fi[0] = needOwn ? fo[0] : SS::ld(A + c, inv);
-        const uint32_t miss = gm | sm | wm;
 #pragma unroll
-        for (int q = 1; q < Q; ++q) {
-            if (!((miss >> q) & 1u)) {
-                int sx = wrapc(x - cx(q), nx), sy = wrapc(y - cy(q), ny), sz = wrapc(z - cz(q), nz);
-                fi[q] = SS::ld(A + q * S + (sx + nx * (sy + ny * sz)), inv);
-            }
+        for (int q = 1; q < Q; ++q)
+            if (!((miss >> q) & 1u)) fi[q] = SS::ld(A + q * S + src(q), inv);
+        // particle ids of the solid sources: one batch of loads, reduced to the first
+        // id P0 and the mask of links whose particle is P0
+        int P0 = -1;
+        uint32_t same = 0;
+        if (sm) {
+            int pq[Q];
+#pragma unroll
+            for (int q = 1; q < Q; ++q) pq[q] = ((sm >> q) & 1u) ? D.pid[src(q)] : -1;
+#pragma unroll
+            for (int q = Q - 1; q >= 1; --q)
+                if ((sm >> q) & 1u) P0 = pq[q];
+#pragma unroll
+            for (int q = 1; q < Q; ++q) same |= (uint32_t)(((sm >> q) & 1u) && pq[q] == P0) << q;
         }
         float rho_t = 1.0f, ut0 = 0.f, ut1 = 0.f, ut2 = 0.f;
         if (needOwn) {
@@ -156,42 +171,66 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geom G, Phys Ph, Dev D, 
             ut2 = j2 / rho_t - 0.5f * Ph.g[2];
         }
         if (miss) {
+            // rigid-body velocity of the lane's particle at the node: c_q . u_w at
+            // the link midpoint x - c_q/2 equals c_q . (u_P + omega x (x - x_P))
+            // because c_q . (omega x c_q) = 0, so one velocity serves all links
+            float un0 = 0.f, un1 = 0.f, un2 = 0.f;
+            auto node_velocity = [&](int P) {
+                const float4 *pm = D.pmir + 4LL * P;
+                const float4 an = pm[0], fr = pm[1], up = pm[2], wp = pm[3];
+                const float rx = ((float)x - an.x) - fr.x;
+                const float ry = ((float)y - an.y) - fr.y;
+                const float rz = ((float)z - an.z) - fr.z;
+                un0 = up.x + (wp.y * rz - wp.z * ry);
+                un1 = up.y + (wp.z * rx - wp.x * rz);
+                un2 = up.z + (wp.x * ry - wp.y * rx);
+            };
+            if ((unsigned)P0 < (unsigned)D.np) {
+                acc.P = P0;
+                node_velocity(P0);
+            }
 #pragma unroll
             for (int q = 1; q < Q; ++q) {
                 const int o = opp(q);
-                if ((wm >> q) & 1u) {
+                if (!INTERIOR && ((wm >> q) & 1u)) {
                     fi[q] = needOwn ? fo[o] : SS::ld(A + o * S + c, inv);
                 } else if ((sm >> q) & 1u) {
-                    int sx = wrapc(x - cx(q), nx), sy = wrapc(y - cy(q), ny), sz = wrapc(z - cz(q), nz);
-                    int P = D.pid[sx + nx * (sy + ny * sz)];
-                    if ((unsigned)P >= (unsigned)D.np) {  // inconsistent state: plain wall
-                        fi[q] = fo[o];
-                        atomicOr(D.err, ERR_LG);
-                        continue;
+                    if (!((same >> q) & 1u) || acc.P != P0) {  // another particle (rare)
+                        const int P = D.pid[src(q)];
+                        if ((unsigned)P >= (unsigned)D.np) {  // inconsistent state: plain wall
+                            fi[q] = fo[o];
+                            atomicOr(D.err, ERR_LG);
+                            continue;
+                        }
+                        if (P != acc.P) {
+                            acc_flush(D, acc, x, y, z);
+                            acc.P = P;
+                            acc_zero(acc);
+                            node_velocity(P);
+                        }
                     }
-                    const double *pt = D.ptab + (long long)P * P_STRIDE;
-                    double rx = (x - 0.5 * cx(q)) - pt[P_X], ry = (y - 0.5 * cy(q)) - pt[P_X + 1],
-                           rz = (z - 0.5 * cz(q)) - pt[P_X + 2];
-                    double uw0 = pt[P_U] + (pt[P_W + 1] * rz - pt[P_W + 2] * ry);
-                    double uw1 = pt[P_U + 1] + (pt[P_W + 2] * rx - pt[P_W] * rz);
-                    double uw2 = pt[P_U + 2] + (pt[P_W] * ry - pt[P_W + 1] * rx);
-                    float cu = (float)(cx(q) * uw0 + cy(q) * uw1 + cz(q) * uw2);
-                    float fin = fo[o] + 6.0f * wq(q) * rho_t * cu;
+                    const float cu = cx(q) * un0 + cy(q) * un1 + cz(q) * un2;
+                    const float fin = fo[o] + 6.0f * wq(q) * rho_t * cu;  // Eq. (bbrule)
                     fi[q] = fin;
-                    // f*_qbar(x) + f_q(x,t+1) in FP64: shifted parts plus 2 w_q
-                    const double s = ((double)fo[o] + (double)fin) + 2.0 * wqd(q);
+                    const float s2 = fo[o] + fin;
+                    acc.fs[0] -= cx(q) * s2;
+                    acc.fs[1] -= cy(q) * s2;
+                    acc.fs[2] -= cz(q) * s2;
+                    if (q <= 6) {
+                        acc.ca[0] -= cx(q); acc.ca[1] -= cy(q); acc.ca[2] -= cz(q);
+                    } else {
+                        acc.cd[0] -= cx(q); acc.cd[1] -= cy(q); acc.cd[2] -= cz(q);
+                    }
                     // the ledger pays the moving-wall mass of liquid cells only: an
                     // interface cell's mass is m, which the link does not change
-                    acc_add(D, acc, P, -cx(q) * s, -cy(q) * s, -cz(q) * s, x - pt[P_X],
-                            y - pt[P_X + 1], z - pt[P_X + 2],
-                            fl == LIQ ? (double)fin - (double)fo[o] : 0.0);
+                    if (fl == LIQ) acc.dm += fin - fo[o];
                 } else if ((gm >> q) & 1u) {
                     if (fl == LIQ) atomicOr(D.err, ERR_LG);
-                    int sx = wrapc(x - cx(q), nx), sy = wrapc(y - cy(q), ny), sz = wrapc(z - cz(q), nz);
-                    int bid = D.bub[sx + nx * (sy + ny * sz)];
-                    float rg = D.rhog[bid < D.maxB ? bid : 0];
-                    float cu = cx(q) * ut0 + cy(q) * ut1 + cz(q) * ut2;
-                    float uu = ut0 * ut0 + ut1 * ut1 + ut2 * ut2;
+                    const int bid = D.bub[src(q)];
+                    const float rg = D.rhog[bid < D.maxB ? bid : 0];
+                    const float cu = cx(q) * ut0 + cy(q) * ut1 + cz(q) * ut2;
+                    const float uu = ut0 * ut0 + ut1 * ut1 + ut2 * ut2;
+                    // Eq. (fsk) in shifted form: -h*_qbar + 2 (e+_q(rho_g, u) - w_q)
                     fi[q] = -fo[o] + 2.0f * wq(q) * ((rg - 1.0f) + rg * (4.5f * cu * cu - 1.5f * uu));
                 }
             }
@@ -214,17 +253,15 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geom G, Phys Ph, Dev D, 
         if (!(rho == rho) || !(u0 == u0) || !(u1 == u1) || !(u2 == u2)) atomicOr(D.err, ERR_NAN);
 
         if (fl == IFC) {
+            // Eqs. (massExchange, massExchangeb), mass form, FP64
             const double phx = D.phi_cur[c];
             double dm = 0.0;
 #pragma unroll
             for (int q = 1; q < Q; ++q) {
-                uint8_t nf = tile[1 + cz(q)][ly + 1 + cy(q)][lx + 1 + cx(q)];
+                const uint8_t nf = tile[1 + cz(q)][ly + 1 + cy(q)][lx + 1 + cx(q)];
                 if (nf == LIQ || nf == IFC) {
                     double d = (double)fi[opp(q)] - (double)fo[q];
-                    if (nf == IFC) {
-                        int nxp = wrapc(x + cx(q), nx), nyp = wrapc(y + cy(q), ny), nzp = wrapc(z + cz(q), nz);
-                        d *= 0.5 * (D.phi_cur[nxp + nx * (nyp + ny * nzp)] + phx);
-                    }
+                    if (nf == IFC) d *= 0.5 * (D.phi_cur[nbr(q)] + phx);
                     dm += d;
                 }
             }
@@ -236,7 +273,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geom G, Phys Ph, Dev D, 
             isE = !isF && phin <= Ph.eps;
         }
 
-        // TRT collision with Guo forcing, shifted form: e - w and f - w
+        // TRT collision with Guo forcing (Eq. LBE2), shifted form: e - w and f - w
         const float F0 = rho * Ph.g[0], F1 = rho * Ph.g[1], F2 = rho * Ph.g[2];
         const float uu = u0 * u0 + u1 * u1 + u2 * u2;
         const float uF = u0 * F0 + u1 * F1 + u2 * F2;
@@ -267,39 +304,46 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geom G, Phys Ph, Dev D, 
             B[o * S + c] = vo;
         }
         SS::st(B + c, (float)(drho_d - sout), sc);
-    } else if (fl == SOL && D.np > 0) {
-        // solid node of particle P' with links into another particle P: equilibrium
-        // populations at rho = 1 and the rigid velocity of P' (Sec. 2.3)
-        uint32_t nm = 0;
-#pragma unroll
-        for (int q = 1; q < Q; ++q)
-            nm |= (uint32_t)(tile[1 + cz(q)][ly + 1 + cy(q)][lx + 1 + cx(q)] == SOL) << q;
-        const int Pp = D.pid[c];
-        if (nm && (unsigned)Pp < (unsigned)D.np) {
-            const double *pp = D.ptab + (long long)Pp * P_STRIDE;
-            double rx = x - pp[P_X], ry = y - pp[P_X + 1], rz = z - pp[P_X + 2];
-            double ur0 = pp[P_U] + (pp[P_W + 1] * rz - pp[P_W + 2] * ry);
-            double ur1 = pp[P_U + 1] + (pp[P_W + 2] * rx - pp[P_W] * rz);
-            double ur2 = pp[P_U + 2] + (pp[P_W] * ry - pp[P_W + 1] * rx);
-            double uu = ur0 * ur0 + ur1 * ur1 + ur2 * ur2;
-#pragma unroll
-            for (int q = 1; q < Q; ++q) {
-                if (!((nm >> q) & 1u)) continue;
-                int nxp = wrapc(x + cx(q), nx), nyp = wrapc(y + cy(q), ny), nzp = wrapc(z + cz(q), nz);
-                int P = D.pid[nxp + nx * (nyp + ny * nzp)];
-                if (P == Pp || (unsigned)P >= (unsigned)D.np) continue;
-                const double *pt = D.ptab + (long long)P * P_STRIDE;
-                double cu = cx(q) * ur0 + cy(q) * ur1 + cz(q) * ur2;
-                double e2 = 2.0 * wqd(q) * (1.0 + 4.5 * cu * cu - 1.5 * uu);
-                acc_add(D, acc, P, cx(q) * e2, cy(q) * e2, cz(q) * e2, x - pt[P_X], y - pt[P_X + 1],
-                        z - pt[P_X + 2], 0.0);
-            }
-        }
     }
 
     wave_append(isF, c, D.lF, D.counters + C_NF, D.cap, D.err);
     wave_append(isE, c, D.lE0, D.counters + C_NE0, D.cap, D.err);
-    if (D.np > 0) acc_reduce_wave(D, acc);
+    if (D.np > 0) acc_reduce_wave(D, acc, x, y, z);
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_stream_collide(Geom G, Phys Ph, Dev D, int tilesX,
+                                                        int tilesY, int nTiles) {
+    __shared__ uint8_t tile[3][TY + 2][TX + 2];
+
+    const int nx = G.nx, ny = G.ny, nz = G.nz;
+    const int b = blockIdx.x;
+    const int t = (nTiles % 8 == 0) ? (b % 8) * (nTiles / 8) + b / 8 : b;
+    const int x0 = (t % tilesX) * TX;
+    const int rest = t / tilesX;
+    const int y0 = (rest % tilesY) * TY;
+    const int z = rest / tilesY;
+    const bool interior = x0 >= 1 && x0 + TX + 1 <= nx && y0 >= 1 && y0 + TY + 1 <= ny && z >= 1 &&
+                          z + 2 <= nz;
+
+    for (int i = threadIdx.x; i < 3 * (TY + 2) * (TX + 2); i += 256) {
+        int lx = i % (TX + 2), ly = (i / (TX + 2)) % (TY + 2), lz = i / ((TX + 2) * (TY + 2));
+        int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z + lz - 1;
+        bool ok = true;
+        if (gx < 0 || gx >= nx) { if (G.per[0]) gx = wrapc(gx, nx); else ok = false; }
+        if (gy < 0 || gy >= ny) { if (G.per[1]) gy = wrapc(gy, ny); else ok = false; }
+        if (gz < 0 || gz >= nz) { if (G.per[2]) gz = wrapc(gz, nz); else ok = false; }
+        uint8_t v = WALL;
+        if (ok) v = D.flags[gx + (long long)nx * (gy + (long long)ny * gz)];
+        tile[lz][ly][lx] = v;
+    }
+    __syncthreads();
+
+    const int lx = threadIdx.x & (TX - 1), ly = threadIdx.x >> 6;
+    const int x = x0 + lx, y = y0 + ly;
+    if (x >= nx || y >= ny) return;
+    if (interior) sc_cell<ST, true>(G, Ph, D, tile, lx, ly, x, y, z);
+    else sc_cell<ST, false>(G, Ph, D, tile, lx, ly, x, y, z);
 }
 
 }  // namespace fsl

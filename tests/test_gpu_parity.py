@@ -100,6 +100,28 @@ def test_single_step_particle_bed(warm):
     say(compare_step(o, s, w))
 
 
+@pytest.mark.parametrize("integrate", [False, True])
+def test_single_step_touching_spheres(integrate):
+    """Three spheres with surface gaps below one cell: nodes of one sphere have links
+    into another, so the particle-particle momentum exchange (equilibrium at the
+    solid node) and lubrication are both active."""
+    x = np.array([[10.2, 12.1, 11.4], [17.9, 12.6, 11.9], [14.1, 18.8, 11.2]])
+    p = W.Particles(x=x, u=np.array([[0.01, 0, 0], [-0.01, 0.002, 0], [0, -0.005, 0.003]]),
+                    omega=np.array([[0, 0, 0.004], [0.002, 0, 0], [0, 0, -0.003]]),
+                    R=np.array([3.6, 3.8, 3.3]), rho_p=np.full(3, 2.5))
+    w = W.Workload(name="touch", n=(28, 28, 24), trt=True, tau=0.6, g=(0, 0, -1e-5), zs=20.0,
+                   steps=0, particles=p, integrate=integrate)
+    say("single step, touching spheres, integrate", integrate)
+    o = O.Oracle(w)
+    o.step(6)
+    s = fsl.Sim(w)
+    transfer(o, s, w)
+    o.step(1)
+    s.step(1)
+    s.sync()
+    say(compare_step(o, s, w))
+
+
 def test_single_step_periodic_window():
     w = W.adjoint_window(n=32, n_particles=6)
     say("single step, periodic window")
