@@ -77,6 +77,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--traffic", default=None,
                     help="JSON file with measured HBM bytes per stream-collide launch")
+    ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
+                    help="after the run, copy a buffer of this many GiB three times (plain "
+                         "device copy of known size, for scaling hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -149,6 +152,17 @@ def main():
             forms[name] = {"mlups": round(N * args.steps / d2 / 1e6, 1),
                            "speedup_vs_f32": round(dt / d2, 3), "stream_collide_GBs": round(a2, 1)}
             log(name, forms[name])
+
+    if args.calibrate_copy_gib > 0:
+        nbytes = int(args.calibrate_copy_gib * (1 << 30))
+        a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        b2 = torch.empty_like(a)
+        for _ in range(3):
+            b2.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {nbytes} bytes")
+        del a, b2
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:

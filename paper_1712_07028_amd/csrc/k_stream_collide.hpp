@@ -24,15 +24,19 @@ constexpr int TX = 64, TY = 4;
 // Per-lane momentum-exchange accumulator for the links of one particle.
 // Delta j of a link (Eq. momentum_transfer) is -c_q (h*_qbar + h_q + 2 w_q) in
 // shifted populations; the small shifted parts are summed in FP32 and the
-// constant parts 2 w_q c_q are counted exactly as integer direction sums
-// (axis links 2w = 1/9, diagonal links 2w = 1/18).  All links of a lane share
-// the node x, so the torque (x - x_P) x F is formed once per lane in FP64.
+// constant parts 2 w_q c_q are counted exactly as integer direction sums (axis
+// links 2w = 1/9, diagonal links 2w = 1/18).  All links of a lane share the node
+// x; the lever arm x - x_P is split into the integer part x - a (a = floor x_P)
+// and the fraction f = x_P - a, so torque sums stay exact integers or small FP32
+// values until the wave total is formed in FP64.
 struct LinkAcc {
     int P;
     float fs[3];   // sum of -c_q (h*_qbar + h_q)
     int ca[3];     // sum of -c_q over axis links
     int cd[3];     // sum of -c_q over diagonal links
     float dm;      // mass added by moving bounce-back at a liquid cell
+    float an[3];   // anchor a of particle P (integers stored exactly)
+    float fr[3];   // fraction x_P - a
 };
 
 __device__ __forceinline__ void acc_zero(LinkAcc &L) {
@@ -42,64 +46,123 @@ __device__ __forceinline__ void acc_zero(LinkAcc &L) {
     L.dm = 0.f;
 }
 
-// FP64 force, torque and mass of the lane's links (a[0..6])
-__device__ __forceinline__ void acc_expand(const Dev &D, const LinkAcc &L, int x, int y, int z, double a[7]) {
-    double F[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) F[k] = (double)L.fs[k] + (L.ca[k] * (1.0 / 9.0) + L.cd[k] * (1.0 / 18.0));
-    const double *pt = D.ptab + (long long)L.P * P_STRIDE;
-    const double rx = x - pt[P_X], ry = y - pt[P_X + 1], rz = z - pt[P_X + 2];
-    a[0] = F[0];
-    a[1] = F[1];
-    a[2] = F[2];
-    a[3] = ry * F[2] - rz * F[1];
-    a[4] = rz * F[0] - rx * F[2];
-    a[5] = rx * F[1] - ry * F[0];
-    a[6] = (double)L.dm;
-}
-
+// rare path: one lane's links of a particle straight to the accumulators
 __device__ __noinline__ void acc_flush(const Dev &D, const LinkAcc &L, int x, int y, int z) {
     if (L.P < 0) return;
-    double a[7];
-    acc_expand(D, L, x, y, z, a);
+    double F[3];
+    for (int k = 0; k < 3; ++k) F[k] = (double)L.fs[k] + (L.ca[k] * (1.0 / 9.0) + L.cd[k] * (1.0 / 18.0));
+    const double rx = ((double)x - L.an[0]) - L.fr[0], ry = ((double)y - L.an[1]) - L.fr[1],
+                 rz = ((double)z - L.an[2]) - L.fr[2];
+    const double a[7] = {F[0], F[1], F[2], ry * F[2] - rz * F[1], rz * F[0] - rx * F[2],
+                         rx * F[1] - ry * F[0], (double)L.dm};
     double *dst = D.pacc + (long long)L.P * ACC_STRIDE;
-#pragma unroll
     for (int k = 0; k < 7; ++k) unsafeAtomicAdd(dst + k, a[k]);
 }
 
+// wave64 sum of a 32-bit value, the same in every lane: DPP within rows of 16 lanes
+// (pairs, quads, half-row and row mirrors), then the four row sums via readlane
+__device__ __forceinline__ int row_sum_i(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);  // row_mirror
+    return v;
+}
+__device__ __forceinline__ float row_sum_f(float f) {
+    int v = __float_as_int(f);
+    v = __float_as_int(__int_as_float(v) + __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false)));
+    v = __float_as_int(__int_as_float(v) + __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false)));
+    v = __float_as_int(__int_as_float(v) + __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false)));
+    v = __float_as_int(__int_as_float(v) + __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false)));
+    return __int_as_float(v);
+}
+__device__ __forceinline__ int wave_total_i(int v) {
+    v = row_sum_i(v);
+    return __builtin_amdgcn_readlane(v, 15) + __builtin_amdgcn_readlane(v, 31) +
+           __builtin_amdgcn_readlane(v, 47) + __builtin_amdgcn_readlane(v, 63);
+}
+__device__ __forceinline__ double wave_total_f(float f) {
+    int v = __float_as_int(row_sum_f(f));
+    return ((double)__int_as_float(__builtin_amdgcn_readlane(v, 15)) +
+            (double)__int_as_float(__builtin_amdgcn_readlane(v, 31))) +
+           ((double)__int_as_float(__builtin_amdgcn_readlane(v, 47)) +
+            (double)__int_as_float(__builtin_amdgcn_readlane(v, 63)));
+}
+// two small integers (|value| < 2^15 after the wave sum) in one 32-bit word
+__device__ __forceinline__ int pack2(int hi, int lo) { return hi * 65536 + lo; }
+__device__ __forceinline__ void unpack2(int p, int &hi, int &lo) {
+    lo = (int)(short)(p & 0xffff);
+    hi = (p - lo) / 65536;
+}
+
 // wave-level reduction of the lanes' accumulators, segmented by particle id:
-// one FP64 atomic per (wave, particle, component)
+// one FP64 atomic per (wave, particle, component).  Lanes must be converged.
 __device__ __forceinline__ void acc_reduce_wave(const Dev &D, const LinkAcc &L, int x, int y, int z) {
     int key = L.P;
-    double a[7] = {0, 0, 0, 0, 0, 0, 0};
-    if (key >= 0) acc_expand(D, L, x, y, z, a);
+    if (!__ballot(key >= 0)) return;
+    // lane parts: forces, torques about the anchor, mass
+    const int dx = x - (int)L.an[0], dy = y - (int)L.an[1], dz = z - (int)L.an[2];
+    const float ts0 = dy * L.fs[2] - dz * L.fs[1], ts1 = dz * L.fs[0] - dx * L.fs[2], ts2 = dx * L.fs[1] - dy * L.fs[0];
+    const int ta0 = dy * L.ca[2] - dz * L.ca[1], ta1 = dz * L.ca[0] - dx * L.ca[2], ta2 = dx * L.ca[1] - dy * L.ca[0];
+    const int td0 = dy * L.cd[2] - dz * L.cd[1], td1 = dz * L.cd[0] - dx * L.cd[2], td2 = dx * L.cd[1] - dy * L.cd[0];
+    // direction counts are at most 6 (axis) and 12 (diagonal) per lane, so their wave
+    // sums fit 16 bits; the torque counts scale with the sphere size and stay 32-bit
+    const int p0 = pack2(L.ca[0], L.cd[0]), p1 = pack2(L.ca[1], L.cd[1]), p2 = pack2(L.ca[2], L.cd[2]);
     while (true) {
-        unsigned long long act = __ballot(key >= 0);
+        const unsigned long long act = __ballot(key >= 0);
         if (!act) break;
-        int leader = __ffsll((long long)act) - 1;
-        int k0 = __shfl(key, leader);
-        bool mine = key == k0;
-        double *dst = D.pacc + (long long)k0 * ACC_STRIDE;
-#pragma unroll
-        for (int k = 0; k < 7; ++k) {
-            double v = wave_sum(mine ? a[k] : 0.0);
-            if ((int)lane_id() == leader) unsafeAtomicAdd(dst + k, v);
+        const int leader = __ffsll((long long)act) - 1;
+        const int k0 = __builtin_amdgcn_readlane(key, leader);
+        const bool mine = key == k0;
+        const double F0s = wave_total_f(mine ? L.fs[0] : 0.f), F1s = wave_total_f(mine ? L.fs[1] : 0.f),
+                     F2s = wave_total_f(mine ? L.fs[2] : 0.f);
+        const double T0s = wave_total_f(mine ? ts0 : 0.f), T1s = wave_total_f(mine ? ts1 : 0.f),
+                     T2s = wave_total_f(mine ? ts2 : 0.f);
+        const double dms = wave_total_f(mine ? L.dm : 0.f);
+        const int q0 = wave_total_i(mine ? p0 : 0), q1 = wave_total_i(mine ? p1 : 0), q2 = wave_total_i(mine ? p2 : 0);
+        const int ta = wave_total_i(mine ? ta0 : 0), tc = wave_total_i(mine ? ta1 : 0), tf = wave_total_i(mine ? ta2 : 0);
+        const int tb = wave_total_i(mine ? td0 : 0), te = wave_total_i(mine ? td1 : 0), tg = wave_total_i(mine ? td2 : 0);
+        if ((int)lane_id() == leader) {
+            int a0, d0, a1, d1, a2, d2;
+            unpack2(q0, a0, d0);
+            unpack2(q1, a1, d1);
+            unpack2(q2, a2, d2);
+            const double F[3] = {F0s + (a0 * (1.0 / 9.0) + d0 * (1.0 / 18.0)),
+                                 F1s + (a1 * (1.0 / 9.0) + d1 * (1.0 / 18.0)),
+                                 F2s + (a2 * (1.0 / 9.0) + d2 * (1.0 / 18.0))};
+            // sum over lanes of (x - a) x F_lane, then shift the arm by the fraction
+            const double Ta[3] = {T0s + (ta * (1.0 / 9.0) + tb * (1.0 / 18.0)),
+                                  T1s + (tc * (1.0 / 9.0) + te * (1.0 / 18.0)),
+                                  T2s + (tf * (1.0 / 9.0) + tg * (1.0 / 18.0))};
+            const double f0 = L.fr[0], f1 = L.fr[1], f2 = L.fr[2];
+            const double T[3] = {Ta[0] - (f1 * F[2] - f2 * F[1]), Ta[1] - (f2 * F[0] - f0 * F[2]),
+                                 Ta[2] - (f0 * F[1] - f1 * F[0])};
+            double *dst = D.pacc + (long long)k0 * ACC_STRIDE;
+            unsafeAtomicAdd(dst + 0, F[0]);
+            unsafeAtomicAdd(dst + 1, F[1]);
+            unsafeAtomicAdd(dst + 2, F[2]);
+            unsafeAtomicAdd(dst + 3, T[0]);
+            unsafeAtomicAdd(dst + 4, T[1]);
+            unsafeAtomicAdd(dst + 5, T[2]);
+            unsafeAtomicAdd(dst + 6, dms);
         }
         if (mine) key = -1;
     }
 }
 
 // One cell of the fused step.  INTERIOR: the tile and its halo lie inside the box,
-// so a source is the cell index minus a uniform offset (no wrap, no wall).
+// so a source is the cell index minus a uniform offset (no wrap, no wall).  Lanes
+// past the box edge (inb false) stay in the wave with nothing to do, because the
+// wave-level sums below read every lane.
 template <int ST, bool INTERIOR>
 __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev &D,
                                         const uint8_t (&tile)[3][TY + 2][TX + 2], int lx, int ly,
-                                        int x, int y, int z) {
+                                        int x, int y, int z, bool inb) {
     using SS = Store<ST>;
     using T = typename SS::T;
     const int nx = G.nx, ny = G.ny, nz = G.nz, nxy = nx * ny;
-    const int c = x + nx * y + nxy * z;
-    const uint8_t fl = tile[1][ly + 1][lx + 1];
+    const int c = inb ? x + nx * y + nxy * z : 0;
+    const uint8_t fl = inb ? tile[1][ly + 1][lx + 1] : WALL;
     const T *A = (const T *)D.fA;
     T *B = (T *)D.fB;
     const long long S = G.S;
@@ -118,6 +181,8 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
     LinkAcc acc;
     acc.P = -1;
     acc_zero(acc);
+    acc.an[0] = acc.an[1] = acc.an[2] = 0.f;
+    acc.fr[0] = acc.fr[1] = acc.fr[2] = 0.f;
     bool isF = false, isE = false;
 
     if (fl == LIQ || fl == IFC) {
@@ -166,9 +231,10 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
                 j2 += cz(q) * fo[q];
             }
             rho_t = 1.0f + d;
-            ut0 = j0 / rho_t - 0.5f * Ph.g[0];
-            ut1 = j1 / rho_t - 0.5f * Ph.g[1];
-            ut2 = j2 / rho_t - 0.5f * Ph.g[2];
+            const float ir = 1.0f / rho_t;
+            ut0 = j0 * ir - 0.5f * Ph.g[0];
+            ut1 = j1 * ir - 0.5f * Ph.g[1];
+            ut2 = j2 * ir - 0.5f * Ph.g[2];
         }
         if (miss) {
             // rigid-body velocity of the lane's particle at the node: c_q . u_w at
@@ -178,6 +244,8 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
             auto node_velocity = [&](int P) {
                 const float4 *pm = D.pmir + 4LL * P;
                 const float4 an = pm[0], fr = pm[1], up = pm[2], wp = pm[3];
+                acc.an[0] = an.x; acc.an[1] = an.y; acc.an[2] = an.z;
+                acc.fr[0] = fr.x; acc.fr[1] = fr.y; acc.fr[2] = fr.z;
                 const float rx = ((float)x - an.x) - fr.x;
                 const float ry = ((float)y - an.y) - fr.y;
                 const float rz = ((float)z - an.z) - fr.z;
@@ -247,9 +315,10 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
         }
         const float drho = (float)drho_d;
         const float rho = 1.0f + drho;
-        const float u0 = j0 / rho + 0.5f * Ph.g[0];
-        const float u1 = j1 / rho + 0.5f * Ph.g[1];
-        const float u2 = j2 / rho + 0.5f * Ph.g[2];
+        const float irho = 1.0f / rho;
+        const float u0 = j0 * irho + 0.5f * Ph.g[0];
+        const float u1 = j1 * irho + 0.5f * Ph.g[1];
+        const float u2 = j2 * irho + 0.5f * Ph.g[2];
         if (!(rho == rho) || !(u0 == u0) || !(u1 == u1) || !(u2 == u2)) atomicOr(D.err, ERR_NAN);
 
         if (fl == IFC) {
@@ -326,24 +395,42 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geom G, Phys Ph, Dev D, 
     const bool interior = x0 >= 1 && x0 + TX + 1 <= nx && y0 >= 1 && y0 + TY + 1 <= ny && z >= 1 &&
                           z + 2 <= nz;
 
-    for (int i = threadIdx.x; i < 3 * (TY + 2) * (TX + 2); i += 256) {
-        int lx = i % (TX + 2), ly = (i / (TX + 2)) % (TY + 2), lz = i / ((TX + 2) * (TY + 2));
-        int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z + lz - 1;
-        bool ok = true;
-        if (gx < 0 || gx >= nx) { if (G.per[0]) gx = wrapc(gx, nx); else ok = false; }
-        if (gy < 0 || gy >= ny) { if (G.per[1]) gy = wrapc(gy, ny); else ok = false; }
-        if (gz < 0 || gz >= nz) { if (G.per[2]) gz = wrapc(gz, nz); else ok = false; }
-        uint8_t v = WALL;
-        if (ok) v = D.flags[gx + (long long)nx * (gy + (long long)ny * gz)];
-        tile[lz][ly][lx] = v;
+    // cell types of the tile and its one-cell halo: 18 rows of 66 bytes; a wave
+    // loads 64 bytes of a row, the last two bytes of every row come from lanes of
+    // the first wave
+    {
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        if (interior) {
+            const uint8_t *base = D.flags + (long long)(z - 1) * nx * ny + (long long)(y0 - 1) * nx + (x0 - 1);
+            for (int r = wv; r < 3 * (TY + 2); r += 4) {
+                const int lz = r / (TY + 2), ly = r - lz * (TY + 2);
+                tile[lz][ly][lane] = base[(long long)lz * nx * ny + ly * nx + lane];
+            }
+            if (threadIdx.x < 2 * 3 * (TY + 2)) {
+                const int r = threadIdx.x >> 1, lz = r / (TY + 2), ly = r - lz * (TY + 2), lx = TX + (threadIdx.x & 1);
+                tile[lz][ly][lx] = base[(long long)lz * nx * ny + ly * nx + lx];
+            }
+        } else {
+            for (int i = threadIdx.x; i < 3 * (TY + 2) * (TX + 2); i += 256) {
+                int lx = i % (TX + 2), ly = (i / (TX + 2)) % (TY + 2), lz = i / ((TX + 2) * (TY + 2));
+                int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z + lz - 1;
+                bool ok = true;
+                if (gx < 0 || gx >= nx) { if (G.per[0]) gx = wrapc(gx, nx); else ok = false; }
+                if (gy < 0 || gy >= ny) { if (G.per[1]) gy = wrapc(gy, ny); else ok = false; }
+                if (gz < 0 || gz >= nz) { if (G.per[2]) gz = wrapc(gz, nz); else ok = false; }
+                uint8_t v = WALL;
+                if (ok) v = D.flags[gx + (long long)nx * (gy + (long long)ny * gz)];
+                tile[lz][ly][lx] = v;
+            }
+        }
     }
     __syncthreads();
 
     const int lx = threadIdx.x & (TX - 1), ly = threadIdx.x >> 6;
     const int x = x0 + lx, y = y0 + ly;
-    if (x >= nx || y >= ny) return;
-    if (interior) sc_cell<ST, true>(G, Ph, D, tile, lx, ly, x, y, z);
-    else sc_cell<ST, false>(G, Ph, D, tile, lx, ly, x, y, z);
+    const bool inb = x < nx && y < ny;
+    if (interior) sc_cell<ST, true>(G, Ph, D, tile, lx, ly, x, y, z, inb);
+    else sc_cell<ST, false>(G, Ph, D, tile, lx, ly, x, y, z, inb);
 }
 
 }  // namespace fsl
