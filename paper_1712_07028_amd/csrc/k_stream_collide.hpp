@@ -46,17 +46,26 @@ __device__ __forceinline__ void acc_zero(LinkAcc &L) {
     L.dm = 0.f;
 }
 
-// rare path: one lane's links of a particle straight to the accumulators
-__device__ __noinline__ void acc_flush(const Dev &D, const LinkAcc &L, int x, int y, int z) {
-    if (L.P < 0) return;
-    double F[3];
-    for (int k = 0; k < 3; ++k) F[k] = (double)L.fs[k] + (L.ca[k] * (1.0 / 9.0) + L.cd[k] * (1.0 / 18.0));
-    const double rx = ((double)x - L.an[0]) - L.fr[0], ry = ((double)y - L.an[1]) - L.fr[1],
-                 rz = ((double)z - L.an[2]) - L.fr[2];
+// rare path: one lane's links of a particle straight to the accumulators.  Takes
+// the sums by value so that the accumulator never needs an address (it stays in
+// registers; only this call, when taken, uses the stack).
+__device__ __noinline__ void acc_flush_v(double *pacc, int P, float fs0, float fs1, float fs2, int ca0,
+                                         int ca1, int ca2, int cd0, int cd1, int cd2, float dm, float rx,
+                                         float ry, float rz) {
+    const double F[3] = {(double)fs0 + (ca0 * (1.0 / 9.0) + cd0 * (1.0 / 18.0)),
+                         (double)fs1 + (ca1 * (1.0 / 9.0) + cd1 * (1.0 / 18.0)),
+                         (double)fs2 + (ca2 * (1.0 / 9.0) + cd2 * (1.0 / 18.0))};
     const double a[7] = {F[0], F[1], F[2], ry * F[2] - rz * F[1], rz * F[0] - rx * F[2],
-                         rx * F[1] - ry * F[0], (double)L.dm};
-    double *dst = D.pacc + (long long)L.P * ACC_STRIDE;
+                         rx * F[1] - ry * F[0], (double)dm};
+    double *dst = pacc + (long long)P * ACC_STRIDE;
     for (int k = 0; k < 7; ++k) unsafeAtomicAdd(dst + k, a[k]);
+}
+__device__ __forceinline__ void acc_flush(const Dev &D, const LinkAcc &L, int x, int y, int z) {
+    if (L.P < 0) return;
+    // lever arm x - x_P = (x - a) - f
+    acc_flush_v(D.pacc, L.P, L.fs[0], L.fs[1], L.fs[2], L.ca[0], L.ca[1], L.ca[2], L.cd[0], L.cd[1],
+                L.cd[2], L.dm, ((float)x - L.an[0]) - L.fr[0], ((float)y - L.an[1]) - L.fr[1],
+                ((float)z - L.an[2]) - L.fr[2]);
 }
 
 // wave64 sum of a 32-bit value, the same in every lane: DPP within rows of 16 lanes
