@@ -1119,9 +1119,217 @@ int orc_field_set(orc_ctx *c, int which, const void *in)
     return 0;
 }
 
-/* placeholder until the frozen-window derivative is written */
+/* ---- differentiation form: summed drag over a frozen window ------------------ */
+/* d lambda_- / d tau of the TRT constraint (Sec. 2.1); for SRT lambda_- = lambda_+ */
+static double dlm_dtau(double tau, double magic, int trt)
+{
+    if (!trt) return 1.0 / (tau * tau);
+    double a = 0.5 - tau;            /* 1/lp + 1/2 */
+    double lm = orc_lambda_minus(tau, magic, trt);
+    return -lm * lm * magic / (a * a);
+}
+
+/* J_t of the window: -sum_P uhat_P . F_P with F_P the momentum exchange of
+ * force_pass (fluid links and the equilibrium links of other particles) evaluated
+ * on the state s; its tangents along the four parameter directions from ds.  Wall
+ * links carry no particle force.  Serial, in cell order. */
+static void window_drag(const orc_ctx *c, const double *s, const double *ds, const double *uhat,
+                        double *J, double dJ[4])
+{
+    const size_t N = (size_t)c->N;
+    for (int x = 0; x < c->N; ++x) {
+        int i, j, k;
+        cell_ijk(c, x, &i, &j, &k);
+        if (c->flag[x] == LIQ) {
+            double rw = 0, drw[4] = {0, 0, 0, 0};
+            for (int q = 0; q < 19; ++q) {
+                rw += s[(size_t)q * N + x];
+                for (int d = 0; d < 4; ++d) drw[d] += ds[((size_t)d * 19 + q) * N + x];
+            }
+            for (int q = 1; q < 19; ++q) {
+                int src = nbr(c, i, j, k, -CX[q], -CY[q], -CZ[q], NULL);
+                if (src < 0 || c->flag[src] != SOL) continue;
+                int P = c->pid[src];
+                const double *uh = uhat + 3 * P;
+                double xw[3] = {i - 0.5 * CX[q], j - 0.5 * CY[q], k - 0.5 * CZ[q]}, uw[3];
+                rigid_velocity(c, P, xw, uw);
+                double cu = CX[q] * uw[0] + CY[q] * uw[1] + CZ[q] * uw[2];
+                double cuh = CX[q] * uh[0] + CY[q] * uh[1] + CZ[q] * uh[2];
+                int o = OPP[q];
+                /* Delta j = -c_q (f*_qbar + f_q(t+1)), f_q(t+1) from Eq. (bbrule) */
+                double fout = s[(size_t)o * N + x];
+                double fin = fout + 6.0 * W[q] * rw * cu;
+                *J += cuh * (fout + fin);
+                for (int d = 0; d < 4; ++d) {
+                    double dfo = ds[((size_t)d * 19 + o) * N + x];
+                    dJ[d] += cuh * (2.0 * dfo + 6.0 * W[q] * drw[d] * cu);
+                }
+            }
+        } else if (c->flag[x] == SOL) {
+            int Pp = c->pid[x];
+            for (int q = 1; q < 19; ++q) {
+                int n = nbr(c, i, j, k, CX[q], CY[q], CZ[q], NULL);
+                if (n < 0 || c->flag[n] != SOL) continue;
+                int P = c->pid[n];
+                if (P == Pp) continue;
+                double p[3] = {i, j, k}, ur[3];
+                rigid_velocity(c, Pp, p, ur);
+                const double *uh = uhat + 3 * P;
+                double cuh = CX[q] * uh[0] + CY[q] * uh[1] + CZ[q] * uh[2];
+                *J -= cuh * 2.0 * eq_plus(q, 1.0, ur);
+            }
+        }
+    }
+}
+
+/* Summed drag J = sum_{t<T} J_t over T frozen-flag steps from the current state
+ * and its tangent-linear (forward-mode) derivatives along tau and g, found by
+ * differentiating each part of the step -- streaming with bounce-back (Eq. bbrule,
+ * including its density rho_w), moments with the half-force shift and the TRT
+ * collision with Guo forcing (Eq. LBE2) -- with respect to the parameters, the
+ * window's initial state held fixed.  Every non-solid cell must be liquid and the
+ * spheres kinematic (integrate off), so the cell types cannot change.  The
+ * oracle's own state is left as it was. */
 int orc_window_J(orc_ctx *c, int T, double *J, double *dJ)
 {
-    (void)c; (void)T; (void)J; (void)dJ;
-    return -1;
+    const size_t N = (size_t)c->N;
+    if (T < 0 || !J) return -1;
+    if (c->cfg.integrate && c->np > 0) return -1;
+    for (int x = 0; x < c->N; ++x)
+        if (c->flag[x] == GAS || c->flag[x] == IFC) return -1;
+    double *s = (double *)malloc(sizeof(double) * 19 * N);
+    double *sn = (double *)malloc(sizeof(double) * 19 * N);
+    double *ds = (double *)calloc(4 * 19 * N, sizeof(double));
+    double *dsn = (double *)calloc(4 * 19 * N, sizeof(double));
+    double *uhat = (double *)calloc(3 * (size_t)(c->np > 0 ? c->np : 1), sizeof(double));
+    if (!s || !sn || !ds || !dsn || !uhat) {
+        free(s); free(sn); free(ds); free(dsn); free(uhat);
+        return -1;
+    }
+    memcpy(s, c->f, sizeof(double) * 19 * N);
+    memcpy(sn, c->f, sizeof(double) * 19 * N);
+    for (int P = 0; P < c->np; ++P) {
+        const double *u = c->pu + 3 * P;
+        double nu = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        if (nu > 0)
+            for (int a = 0; a < 3; ++a) uhat[3 * P + a] = u[a] / nu;
+    }
+    const double *g = c->cfg.g;
+    const double lp = c->lp, lm = c->lm;
+    /* derivatives of the rates and of g along direction d: d = 0 tau, d = 1..3 g */
+    double dlp[4] = {1.0 / (c->cfg.tau * c->cfg.tau), 0, 0, 0};
+    double dlmv[4] = {dlm_dtau(c->cfg.tau, c->cfg.magic, c->cfg.trt), 0, 0, 0};
+    double dg[4][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    double Jv = 0, dJv[4] = {0, 0, 0, 0};
+
+    for (int t = 0; t < T; ++t) {
+        window_drag(c, s, ds, uhat, &Jv, dJv);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(c->cfg.n_threads > 0 ? c->cfg.n_threads : omp_get_max_threads())
+#endif
+        for (int x = 0; x < c->N; ++x) {
+            if (c->flag[x] != LIQ) continue;
+            int i, j, k;
+            cell_ijk(c, x, &i, &j, &k);
+            /* streaming with reconstruction, and its tangent */
+            double fc[19], dfc[4][19];
+            double rt = 0, drt[4] = {0, 0, 0, 0};
+            for (int q = 0; q < 19; ++q) {
+                rt += s[(size_t)q * N + x];
+                for (int d = 0; d < 4; ++d) drt[d] += ds[((size_t)d * 19 + q) * N + x];
+            }
+            for (int q = 0; q < 19; ++q) {
+                int face = -1;
+                int src = q == 0 ? x : nbr(c, i, j, k, -CX[q], -CY[q], -CZ[q], &face);
+                int o = OPP[q];
+                if (src >= 0 && c->flag[src] == LIQ) {
+                    fc[q] = s[(size_t)q * N + src];
+                    for (int d = 0; d < 4; ++d) dfc[d][q] = ds[((size_t)d * 19 + q) * N + src];
+                    continue;
+                }
+                double uw[3] = {0, 0, 0};
+                if (src < 0) {
+                    const double *w = c->cfg.wall_u[face / 2][face % 2];
+                    uw[0] = w[0]; uw[1] = w[1]; uw[2] = w[2];
+                } else {
+                    double xw[3] = {i - 0.5 * CX[q], j - 0.5 * CY[q], k - 0.5 * CZ[q]};
+                    rigid_velocity(c, c->pid[src], xw, uw);
+                }
+                double cu = CX[q] * uw[0] + CY[q] * uw[1] + CZ[q] * uw[2];
+                fc[q] = s[(size_t)o * N + x] + 6.0 * W[q] * rt * cu;
+                for (int d = 0; d < 4; ++d)
+                    dfc[d][q] = ds[((size_t)d * 19 + o) * N + x] + 6.0 * W[q] * drt[d] * cu;
+            }
+            /* moments: rho, u = (j + rho g / 2) / rho */
+            double rho = 0, jm[3] = {0, 0, 0};
+            for (int q = 0; q < 19; ++q) {
+                rho += fc[q];
+                jm[0] += CX[q] * fc[q];
+                jm[1] += CY[q] * fc[q];
+                jm[2] += CZ[q] * fc[q];
+            }
+            double u[3] = {(jm[0] + 0.5 * rho * g[0]) / rho, (jm[1] + 0.5 * rho * g[1]) / rho,
+                           (jm[2] + 0.5 * rho * g[2]) / rho};
+            double e[19], Fq[19], F[3] = {rho * g[0], rho * g[1], rho * g[2]};
+            orc_equilibrium(rho, u, e);
+            double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            for (int q = 0; q < 19; ++q) {
+                double cu = CX[q] * u[0] + CY[q] * u[1] + CZ[q] * u[2];
+                double cF = CX[q] * F[0] + CY[q] * F[1] + CZ[q] * F[2];
+                Fq[q] = W[q] * (3.0 * (cF - (u[0] * F[0] + u[1] * F[1] + u[2] * F[2])) + 9.0 * cu * cF);
+            }
+            for (int d = 0; d < 4; ++d) {
+                /* tangent of the moments */
+                double drho = 0, dj[3] = {0, 0, 0};
+                for (int q = 0; q < 19; ++q) {
+                    drho += dfc[d][q];
+                    dj[0] += CX[q] * dfc[d][q];
+                    dj[1] += CY[q] * dfc[d][q];
+                    dj[2] += CZ[q] * dfc[d][q];
+                }
+                double du[3], dF[3];
+                for (int a = 0; a < 3; ++a) {
+                    du[a] = (dj[a] - (jm[a] / rho) * drho) / rho + 0.5 * dg[d][a];
+                    dF[a] = drho * g[a] + rho * dg[d][a];
+                }
+                double udu = u[0] * du[0] + u[1] * du[1] + u[2] * du[2];
+                double de[19], dFq[19];
+                for (int q = 0; q < 19; ++q) {
+                    double cu = CX[q] * u[0] + CY[q] * u[1] + CZ[q] * u[2];
+                    double dcu = CX[q] * du[0] + CY[q] * du[1] + CZ[q] * du[2];
+                    de[q] = W[q] * (drho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu) +
+                                    rho * (3.0 * dcu + 9.0 * cu * dcu - 3.0 * udu));
+                    double cF = CX[q] * F[0] + CY[q] * F[1] + CZ[q] * F[2];
+                    double cdF = CX[q] * dF[0] + CY[q] * dF[1] + CZ[q] * dF[2];
+                    double duF = du[0] * F[0] + du[1] * F[1] + du[2] * F[2];
+                    double udF = u[0] * dF[0] + u[1] * dF[1] + u[2] * dF[2];
+                    dFq[q] = W[q] * (3.0 * (cdF - duF - udF) + 9.0 * (dcu * cF + cu * cdF));
+                }
+                /* tangent of f* = f + lp (f+ - e+) + lm (f- - e-) + (1 + lp/2) F+ + (1 + lm/2) F- */
+                for (int q = 0; q < 19; ++q) {
+                    int o = OPP[q];
+                    double fp = 0.5 * (fc[q] + fc[o]), fm = 0.5 * (fc[q] - fc[o]);
+                    double ep = 0.5 * (e[q] + e[o]), em = 0.5 * (e[q] - e[o]);
+                    double Fp = 0.5 * (Fq[q] + Fq[o]), Fm = 0.5 * (Fq[q] - Fq[o]);
+                    double dfp = 0.5 * (dfc[d][q] + dfc[d][o]), dfm = 0.5 * (dfc[d][q] - dfc[d][o]);
+                    double dep = 0.5 * (de[q] + de[o]), dem = 0.5 * (de[q] - de[o]);
+                    double dFp = 0.5 * (dFq[q] + dFq[o]), dFm = 0.5 * (dFq[q] - dFq[o]);
+                    dsn[((size_t)d * 19 + q) * N + x] =
+                        dfc[d][q] + dlp[d] * (fp - ep) + lp * (dfp - dep) + dlmv[d] * (fm - em) +
+                        lm * (dfm - dem) + 0.5 * dlp[d] * Fp + (1.0 + 0.5 * lp) * dFp +
+                        0.5 * dlmv[d] * Fm + (1.0 + 0.5 * lm) * dFm;
+                }
+            }
+            /* primal: the oracle's own collision */
+            collide_cell(c, fc, rho, u);
+            for (int q = 0; q < 19; ++q) sn[(size_t)q * N + x] = fc[q];
+        }
+        double *tp = s; s = sn; sn = tp;
+        tp = ds; ds = dsn; dsn = tp;
+    }
+    *J = Jv;
+    if (dJ)
+        for (int d = 0; d < 4; ++d) dJ[d] = dJv[d];
+    free(s); free(sn); free(ds); free(dsn); free(uhat);
+    return 0;
 }

@@ -76,10 +76,12 @@ int orc_bubbles_set(orc_ctx *c, int n, const double *M, const int *root, const i
 uint32_t orc_error(const orc_ctx *c);
 int orc_num_cells(const orc_ctx *c);
 
-/* Frozen-flag window (differentiation form): fully-liquid periodic box, kinematic
- * spheres, no interface.  Runs T steps from the equilibrium at rest and returns
- * J = sum_t sum_P (-F_P(t) . u_P/|u_P|).  When dJ is non-null it also returns the
- * forward-mode (tangent-linear) derivatives dJ/dtau and dJ/dg[3] in dJ[0..3]. */
+/* Frozen-flag window (differentiation form): every non-solid cell liquid,
+ * kinematic spheres (integrate off).  Runs T steps from the current state, which
+ * it leaves unchanged, and returns J = sum_t sum_P (-F_P(t) . u_P/|u_P|), F_P(t)
+ * the force reported by step t.  When dJ is non-null it also returns the
+ * forward-mode (tangent-linear) derivatives dJ/dtau and dJ/dg[3] in dJ[0..3].
+ * Returns -1 when the state does not allow a frozen window. */
 int orc_window_J(orc_ctx *c, int T, double *J, double *dJ);
 
 /* exposed pieces of the method for unit checks */

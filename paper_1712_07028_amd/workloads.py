@@ -89,6 +89,9 @@ def rsa_spheres(n_target, R, box, zs, bubble=None, seed=0, gap=1.0, max_draws=No
     acc = np.empty((0, 3))
     draws = 0
     max_draws = max_draws or 2000 * n_target + 100000
+    # the accepted set does not depend on the batch size (candidates are tested in
+    # draw order); small targets use small batches to keep the pair lists short
+    batch = min(batch, max(64, 8 * n_target))
     while acc.shape[0] < n_target and draws < max_draws:
         cand = _draw_centres(rng, lo, hi, batch)
         draws += batch
