@@ -7,10 +7,16 @@ conversions, bubble model, particle update and coverage).  Prints one JSON line:
 box MLUPS (all box cells counted), the HBM roofline of the dominant kernel
 (timed with HIP events on the library's stream) and the FP64 oracle timed on a
 bounded sample of the same workload on the host cores.
+
+Also reported: the storage forms (shifted binary16 / bfloat16 populations) on the
+same column with their error against the oracle on the 128^3 pool with 1,400
+spheres after 1,000 steps, and the differentiation form (adjoint MLUPS of the
+summed-drag window, 64^3 and 256^3).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -46,6 +52,78 @@ def workload(name, storage):
     return w.replace(storage=storage)
 
 
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "k_stream_collide_column_traffic.json")
+KERNEL_SOURCES = [os.path.join(HERE, "paper_1712_07028_amd", "csrc", f)
+                  for f in ("k_stream_collide.hpp", "fsl_device.hpp")]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(path, storage):
+    """HBM bytes per stream-collide launch from the counter runs recorded in path,
+    or None when they were taken on other kernel sources or another storage."""
+    if not path or not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if t.get("kernel_hash") != kernel_hash() or t.get("storage") != storage:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def precision_errors(fsl, W, storage):
+    """Errors of one storage form against the oracle's stored results on the 128^3
+    pool with one bubble and 1,400 spheres after 1,000 steps."""
+    ref = json.load(open(os.path.join(HERE, "tests", "golden", "precision_bed128.json")))
+    T = ref["steps"]
+    w = W.bubble_bed_128(storage=storage)
+    n = w.particles.n
+    s = fsl.Sim(w)
+    M0 = s.mass()[0]
+    s.step(T - 10)
+    b0 = s.bubbles()
+    drag = []
+    for _ in range(10):
+        s.step(1)
+        drag.append(float(s.particles_get(n)["F"][:, 2].mean()))
+    b1 = s.bubbles()
+    M1 = s.mass()[0]
+    s.close()
+    rise = (b1[1]["centroid"][2] - b0[1]["centroid"][2]) / 10.0
+    return {"workload": ref["workload"], "steps": T,
+            "mass_drift": abs(M1 / M0 - 1.0), "mass_vs_oracle": abs(M1 / ref["mass"] - 1.0),
+            "rise_velocity_rel_err": abs(rise / ref["rise_velocity"] - 1.0),
+            "mean_drag_rel_err": abs(float(np.mean(drag)) / ref["mean_drag_z"] - 1.0)}
+
+
+def adjoint_rate(fsl, W, torch, n, n_particles, T=200, k=20):
+    """Summed-drag window: forward (T steps with checkpoints) and the adjoint sweep
+    (recompute + reverse), MLUPS = box cells x T / time."""
+    w = W.adjoint_window(n=n, n_particles=n_particles)
+    s = fsl.Sim(w, window=(T, k))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = s.window_forward(T, k)
+    t1 = time.perf_counter()
+    dtau, dg = s.window_backward(1.0)
+    t2 = time.perf_counter()
+    flags = s.get(fsl.FIELD_FLAGS)
+    n_liq = int((flags == fsl.LIQ).sum())
+    s.close()
+    N = w.cells
+    # adjoint step kernel: s_{t-1} pulled, mu_{t+1} gathered, mu_t written (FP32)
+    return {"workload": w.name, "steps": T, "checkpoint_every": k,
+            "forward_mlups": round(N * T / (t1 - t0) / 1e6, 1),
+            "adjoint_mlups": round(N * T / (t2 - t1) / 1e6, 1),
+            "backward_ms": round((t2 - t1) * 1e3, 2),
+            "adjoint_bytes_per_step": 3 * 19 * 4 * n_liq + N,
+            "J": J, "dJ_dtau": dtau, "dJ_dg": [float(v) for v in dg]}
+
+
 def cpu_baseline(w, steps):
     """The FP64 oracle on a bounded sample: the lowest 16 layers of the column."""
     import oracle
@@ -72,10 +150,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="column")
     ap.add_argument("--storage", default="f32", choices=list(STORAGES))
-    ap.add_argument("--forms", action="store_true", help="also time f16s and bf16s storage")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the storage forms and the differentiation form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
-    ap.add_argument("--traffic", default=None,
+    ap.add_argument("--traffic", default=TRAFFIC_FILE,
                     help="JSON file with measured HBM bytes per stream-collide launch")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="after the run, copy a buffer of this many GiB three times (plain "
@@ -132,9 +211,7 @@ def main():
     avg_s = ms_sc / max(n_sc, 1) / 1e3
     alg_bytes = 2 * 19 * ELEM[st] * n_active + N  # populations in and out + cell types
     achieved = alg_bytes / avg_s / 1e9
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+    traffic = measured_traffic(args.traffic, args.storage)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
             "kernel": "k_stream_collide", "kernel_ms": round(avg_s * 1e3, 4),
@@ -144,14 +221,27 @@ def main():
         f"breakdown ms/step {breakdown}")
 
     forms = {}
-    if args.forms:
-        for name, s2 in (("f16s", 1), ("bf16s", 2)):
-            d2, na2, p2 = run(s2, args.steps, args.warmup, True)
+    adjoint = {}
+    if not args.no_forms:
+        from paper_1712_07028_amd import workloads as W
+
+        for name, s2 in STORAGES.items():
+            if s2 == st:
+                d2, na2, p2 = dt, n_active, prof
+            else:
+                d2, na2, p2 = run(s2, args.steps, args.warmup, True)
             ms2, n2 = p2["stream_collide"]
-            a2 = (2 * 19 * 2 * na2 + N) / (ms2 / max(n2, 1) / 1e3) / 1e9
+            a2 = (2 * 19 * ELEM[s2] * na2 + N) / (ms2 / max(n2, 1) / 1e3) / 1e9
             forms[name] = {"mlups": round(N * args.steps / d2 / 1e6, 1),
-                           "speedup_vs_f32": round(dt / d2, 3), "stream_collide_GBs": round(a2, 1)}
+                           "speedup_vs_f32": None, "stream_collide_GBs": round(a2, 1),
+                           "stream_collide_ms": round(ms2 / max(n2, 1), 4),
+                           "error_vs_oracle": precision_errors(fsl, W, s2)}
             log(name, forms[name])
+        for name in forms:
+            forms[name]["speedup_vs_f32"] = round(forms[name]["mlups"] / forms["f32"]["mlups"], 3)
+        for n, npart in ((64, 20), (256, 1280)):
+            adjoint[f"{n}^3"] = adjoint_rate(fsl, W, torch, n, npart)
+            log("adjoint", adjoint[f"{n}^3"])
 
     if args.calibrate_copy_gib > 0:
         nbytes = int(args.calibrate_copy_gib * (1 << 30))
@@ -183,6 +273,8 @@ def main():
     }
     if forms:
         out["forms"] = forms
+    if adjoint:
+        out["adjoint"] = adjoint
     print(json.dumps(out), flush=True)
 
 

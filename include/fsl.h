@@ -169,17 +169,33 @@ void fsl_destroy(fsl_ctx *ctx);
 int fsl_profile_enable(fsl_ctx *ctx, int on);
 int fsl_profile_get(fsl_ctx *ctx, double *ms, long long *count, int n);
 
-/* Differentiation form (flags frozen over a window, Sec. 2.1/2.3 operators):
- * fsl_window_forward runs T steps from the current state with flags, particle
- * positions and velocities frozen, storing a checkpoint every k steps in the
- * workspace, and returns J = sum_{t=1..T} sum_P (-F_P(t) . u_P/|u_P|) (FP64).
- * fsl_window_backward returns dJ/dtau and dJ/dg (times the seed dJ) by a reverse
- * (adjoint) sweep that recomputes each segment from its checkpoint.  The state
- * after forward is the state after T steps.  The checkpoint memory is part of the
- * workspace when cfg.window_steps / cfg.window_every are set; FSL_E_ARG if T or k
- * exceed them or the box holds gas or interface cells. */
+/* Differentiation form: the summed drag over a window with frozen cell types and
+ * its gradient with respect to the relaxation time and the body force.
+ *
+ * fsl_window_forward runs T ordinary steps (Sec. 2.1 stream-collide with the
+ * bounce-back of Eq. bbrule) from the current state and returns, in FP64,
+ *   J = sum_{t=1..T} sum_P (-F_P(t) . u_P/|u_P|),
+ * F_P(t) the momentum-exchange force of step t (Eqs. netforce, momentum_transfer);
+ * particles at rest do not contribute.  It keeps the state at t = 0, k, 2k, ... as
+ * checkpoints in the workspace; afterwards the state is the state after T steps.
+ * Requirements (FSL_E_ARG otherwise): the configuration reserved the window
+ * (cfg.window_steps >= T, cfg.window_every >= k, ceil(T/k) <= ceil(window_steps /
+ * window_every)), FP32 storage, spheres kinematic (integrate = 0) and every
+ * non-solid cell liquid, so that no cell type can change.
+ *
+ * fsl_window_backward returns dJ/dtau (total derivative, including lambda_- of the
+ * TRT constraint) and dJ/dg[3], both multiplied by the seed dJ, by a reverse sweep
+ * that recomputes each segment of k steps from its checkpoint.  It needs a
+ * completed fsl_window_forward with no fsl_params_set, fsl_particles_set or
+ * fsl_fields_set since (FSL_E_ARG otherwise) and does not change the state.
+ * Both synchronise the stream. */
 int fsl_window_forward(fsl_ctx *ctx, int T, int k, double *J);
 int fsl_window_backward(fsl_ctx *ctx, double dJ, double *dJ_dtau, double dJ_dg[3]);
+
+/* Replace the relaxation time tau (> 1/2; lambda_- follows the TRT constraint with
+ * the configured magic parameter) and the body force g for the following steps
+ * (Sec. 2.1).  Invalidates a recorded window.  Asynchronous. */
+int fsl_params_set(fsl_ctx *ctx, double tau, const double g[3]);
 
 #ifdef __cplusplus
 }

@@ -23,7 +23,7 @@ EXPORTS = [
     "fsl_workspace_bytes", "fsl_init", "fsl_step", "fsl_particles_set", "fsl_particles_get",
     "fsl_bubbles_get", "fsl_bubbles_set", "fsl_fields_get", "fsl_fields_set", "fsl_mass_get",
     "fsl_sync", "fsl_error_string", "fsl_destroy", "fsl_profile_enable", "fsl_profile_get",
-    "fsl_window_forward", "fsl_window_backward",
+    "fsl_window_forward", "fsl_window_backward", "fsl_params_set",
 ]
 
 
@@ -86,6 +86,7 @@ def load_library(path=LIB_PATH):
     L.fsl_profile_get.argtypes = [P, dp, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int]
     L.fsl_window_forward.argtypes = [P, ctypes.c_int, ctypes.c_int, dp]
     L.fsl_window_backward.argtypes = [P, ctypes.c_double, dp, dp]
+    L.fsl_params_set.argtypes = [P, ctypes.c_double, dp]
     _lib = L
     return L
 
@@ -254,3 +255,45 @@ class Sim:
         self._check(self.L.fsl_window_backward(self.ctx, float(dJ), ctypes.byref(dtau), _dp(dg)),
                     "fsl_window_backward")
         return dtau.value, dg
+
+    def params_set(self, tau, g):
+        gg = np.ascontiguousarray(np.asarray(g, dtype=np.float64).reshape(3))
+        self._check(self.L.fsl_params_set(self.ctx, float(tau), _dp(gg)), "fsl_params_set")
+
+
+def _drag_window_function():
+    import torch
+
+    class DragWindow(torch.autograd.Function):
+        """J(tau, g): summed drag of a frozen-cell-type window run by the library
+        (fsl_window_forward); the backward pass is the library's adjoint sweep
+        (fsl_window_backward).  Runs T steps from the simulation's current state."""
+
+        @staticmethod
+        def forward(ctx, tau, g, sim, T, k):
+            sim.params_set(float(tau), [float(v) for v in g.reshape(3)])
+            J = sim.window_forward(T, k)
+            ctx.sim = sim
+            return torch.tensor(J, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            dtau, dg = ctx.sim.window_backward(float(gJ))
+            return (torch.tensor(dtau, dtype=torch.float64), torch.from_numpy(dg.copy()),
+                    None, None, None)
+
+    return DragWindow
+
+
+_DRAG_WINDOW = None
+
+
+def drag_window(sim, tau, g, T, k):
+    """Differentiable summed sphere drag over T steps with checkpoints every k steps.
+
+    tau: 0-d float64 tensor, g: float64 tensor of 3 entries; returns a 0-d float64
+    tensor whose backward gives dJ/dtau and dJ/dg."""
+    global _DRAG_WINDOW
+    if _DRAG_WINDOW is None:
+        _DRAG_WINDOW = _drag_window_function()
+    return _DRAG_WINDOW.apply(tau, g, sim, int(T), int(k))

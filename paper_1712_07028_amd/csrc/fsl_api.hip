@@ -40,7 +40,7 @@ struct Layout {
     size_t win;  // differentiation window storage
     size_t total;
     long long S;
-    int cap, capEv, pcap, maxP, maxB, ncellMax;
+    int cap, capEv, pcap, maxP, maxB, ncellMax, nTiles;
     size_t stageBytes, winBytes;
 };
 
@@ -118,7 +118,9 @@ Layout layout_of(const fsl_config *c) {
     L.balive = take((size_t)L.maxB * 4);
     L.rhog = take((size_t)L.maxB * 4);
     L.stage = take(L.stageBytes);
-    L.winBytes = adjoint_window_bytes(c->window_steps, c->window_every, (size_t)L.S, c->max_particles);
+    L.nTiles = ((c->n[0] + TX - 1) / TX) * ((c->n[1] + TY - 1) / TY) * c->n[2];
+    L.winBytes = adjoint_window_bytes(c->window_steps, c->window_every, (size_t)L.S, c->max_particles,
+                                      L.nTiles);
     L.win = take(L.winBytes);
     L.total = o;
     return L;
@@ -407,6 +409,104 @@ int read_error(fsl_ctx *c) {
     return fail(c, FSL_E_NUMERIC, "device error");
 }
 
+
+// ---- differentiation window -------------------------------------------------------
+double dlambda_minus_dtau(const fsl_config &f) {
+    if (f.collision != FSL_TRT) return 1.0 / (f.tau * f.tau);
+    // lambda_- = 1 / (Lambda / (1/lambda_+ + 1/2) - 1/2), 1/lambda_+ + 1/2 = 1/2 - tau
+    const double a = 0.5 - f.tau;
+    const double lm = 1.0 / (f.magic / a - 0.5);
+    return -lm * lm * f.magic / (a * a);
+}
+
+int window_forward(fsl_ctx *c, int T, int k, double *J) {
+    AdjointState &A = c->adj;
+    Dev &D = c->D;
+    A.ready = 0;
+    if (!A.bytes) return fail(c, FSL_E_ARG, "window_forward: no window in the workspace (set window_steps and window_every)");
+    if (c->cfg.storage != FSL_STORE_F32) return fail(c, FSL_E_ARG, "window_forward: the window runs on FP32 storage");
+    if (T < 1 || k < 1 || T > A.Tmax || k > A.kmax || (T + k - 1) / k > A.ncp)
+        return fail(c, FSL_E_ARG, "window_forward: T or k exceed the window reserved in the workspace");
+    if (c->cfg.integrate && D.np > 0) return fail(c, FSL_E_ARG, "window_forward: spheres must be kinematic (integrate off)");
+    int *bad = (int *)(A.acc + 32);
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, c->st, A.acc, 64LL, 0.0);
+    hipLaunchKernelGGL(k_win_check, dim3(grid_for(c->G.N, 256, 2048)), dim3(256), 0, c->st, c->G, D, bad);
+    int nbad = 0;
+    HIPCHK(c, hipMemcpyAsync(&nbad, bad, 4, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (nbad) return fail(c, FSL_E_ARG, "window_forward: the box holds gas or interface cells");
+    if (D.np > 0) hipLaunchKernelGGL(k_win_uhat, dim3(grid_for(D.np)), dim3(256), 0, c->st, D, A.uh);
+    const size_t st = (size_t)Q * c->G.S * 4, stride = adj_up(st) / 4;
+    HIPCHK(c, hipMemcpyAsync(A.cp, D.fA, st, hipMemcpyDeviceToDevice, c->st));
+    for (int t = 0; t < T; ++t) {
+        int rc = enqueue_steps<ST_F32>(c, 1);
+        if (rc) return rc;
+        if (D.np > 0) hipLaunchKernelGGL(k_win_J, dim3(1), dim3(256), 0, c->st, D, A.acc);
+        if ((t + 1) % k == 0 && t + 1 < T)
+            HIPCHK(c, hipMemcpyAsync(A.cp + (size_t)((t + 1) / k) * stride, c->D.fA, st, hipMemcpyDeviceToDevice, c->st));
+    }
+    LAUNCHCHK(c);
+    double Jh = 0;
+    HIPCHK(c, hipMemcpyAsync(&Jh, A.acc, 8, hipMemcpyDeviceToHost, c->st));
+    int rc = read_error(c);
+    if (rc) return rc;
+    if (J) *J = Jh;
+    A.T = T;
+    A.k = k;
+    A.lp_tau = 1.0 / (c->cfg.tau * c->cfg.tau);
+    A.lm_tau = dlambda_minus_dtau(c->cfg);
+    A.ready = 1;
+    return FSL_OK;
+}
+
+int window_backward(fsl_ctx *c, double dJ, double *dJ_dtau, double *dJ_dg) {
+    AdjointState &A = c->adj;
+    if (!A.ready) return fail(c, FSL_E_ARG, "window_backward: no completed window_forward since the last change of state or parameters");
+    const int T = A.T, k = A.k;
+    const size_t stride = adj_up((size_t)Q * c->G.S * 4) / 4;
+    const long long lat = (long long)Q * c->G.S;
+    Dev Dr = c->D;
+    Dr.pacc = A.dummy;
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)A.nTiles * ADJ_NPART)), dim3(256), 0, c->st, A.part,
+                       (long long)A.nTiles * ADJ_NPART, 0.0);
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)c->L.maxP * ACC_STRIDE)), dim3(256), 0, c->st, A.dummy,
+                       (long long)c->L.maxP * ACC_STRIDE, 0.0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(lat, 256, 8192)), dim3(256), 0, c->st, (int *)A.mu[0], lat, 0);
+    int cur = 0;  // mu[cur] holds mu_{t+1}
+    const int nseg = (T + k - 1) / k;
+    for (int j = nseg - 1; j >= 0; --j) {
+        const int t0 = j * k;
+        const int thi = std::min(std::min(T, t0 + k), T - 1);  // last adjoint step using this segment
+        if (thi < t0 + 1) continue;
+        auto slot = [&](int i) -> float * { return i == 0 ? A.cp + (size_t)j * stride : A.seg + (size_t)(i - 1) * stride; };
+        // recompute s_{t0+1} .. s_{thi-1} from the checkpoint s_{t0}
+        for (int i = 1; i <= thi - 1 - t0; ++i) {
+            Dr.fA = slot(i - 1);
+            Dr.fB = slot(i);
+            ProfScope ps(c, 0);
+            hipLaunchKernelGGL(k_stream_collide<ST_F32>, dim3(c->nTiles), dim3(256), 0, c->st, c->G, c->Ph, Dr,
+                               c->tilesX, c->tilesY, c->nTiles);
+        }
+        for (int t = thi; t >= t0 + 1; --t) {
+            hipLaunchKernelGGL(k_adj_step, dim3(c->nTiles), dim3(256), 0, c->st, c->G, c->Ph, Dr,
+                               (const float *)slot(t - 1 - t0), (const float *)A.mu[cur], A.mu[1 - cur],
+                               (const float4 *)A.uh, A.part, c->tilesX, c->tilesY, c->nTiles);
+            cur ^= 1;
+        }
+        LAUNCHCHK(c);
+    }
+    hipLaunchKernelGGL(k_adj_reduce, dim3(1), dim3(256), 0, c->st, (const double *)A.part, A.nTiles, A.acc);
+    LAUNCHCHK(c);
+    double r[6];
+    HIPCHK(c, hipMemcpyAsync(r, A.acc, sizeof r, hipMemcpyDeviceToHost, c->st));
+    int rc = read_error(c);
+    if (rc) return rc;
+    if (dJ_dtau) *dJ_dtau = dJ * (r[1] * A.lp_tau + r[2] * A.lm_tau);
+    if (dJ_dg)
+        for (int a = 0; a < 3; ++a) dJ_dg[a] = dJ * r[3 + a];
+    return FSL_OK;
+}
+
 }  // namespace
 
 // ==================================================================================
@@ -493,7 +593,7 @@ int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, 
     c->nTiles = c->tilesX * c->tilesY * G.nz;
     c->profiling = 0;
     for (int k = 0; k < NPROF; ++k) { c->prof_ms[k] = 0; c->prof_n[k] = 0; }
-    adjoint_bind(c->adj, w + L.win, L.winBytes);
+    adjoint_bind(c->adj, w + L.win, L.winBytes, cfg->window_steps, cfg->window_every, L.S, L.maxP, L.nTiles);
 
     // control block, tables, accumulators
     hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, c->st, (double *)(w + L.ctl), 64LL, 0.0);
@@ -557,6 +657,7 @@ int fsl_particles_set(fsl_ctx *c, int n, const double *x, const double *u, const
                       const double *R, const double *rho_p) {
     if (!c || n < 0 || n > c->cfg.max_particles || (n > 0 && (!x || !R || !rho_p)))
         return fail(c, FSL_E_ARG, "particles_set: bad arguments");
+    c->adj.ready = 0;
     std::vector<double> tab((size_t)std::max(n, 1) * P_STRIDE, 0.0);
     double Rmax = 0;
     for (int P = 0; P < n; ++P) {
@@ -707,6 +808,7 @@ int fsl_fields_get(fsl_ctx *c, int field, void *host) {
 
 int fsl_fields_set(fsl_ctx *c, int field, const void *host) {
     if (!c || !host) return FSL_E_ARG;
+    c->adj.ready = 0;
     const long long N = c->G.N;
     Dev &D = c->D;
     double *stage = (double *)(c->ws + c->L.stage);
@@ -816,14 +918,22 @@ int fsl_profile_get(fsl_ctx *c, double *ms, long long *count, int n) {
 
 int fsl_window_forward(fsl_ctx *c, int T, int k, double *J) {
     if (!c) return FSL_E_ARG;
-    return by_storage(c, [&](auto st) { return adjoint_forward<decltype(st)::value>(c->adj, c->G, c->Ph, c->D, c->st, T, k, J, c->err); });
+    return window_forward(c, T, k, J);
 }
 
 int fsl_window_backward(fsl_ctx *c, double dJ, double *dJ_dtau, double dJ_dg[3]) {
     if (!c) return FSL_E_ARG;
-    return by_storage(c, [&](auto st) {
-        return adjoint_backward<decltype(st)::value>(c->adj, c->G, c->Ph, c->D, c->st, c->cfg, dJ, dJ_dtau, dJ_dg, c->err);
-    });
+    return window_backward(c, dJ, dJ_dtau, dJ_dg);
+}
+
+int fsl_params_set(fsl_ctx *c, double tau, const double g[3]) {
+    if (!c || !(tau > 0.5) || !g) return fail(c, FSL_E_ARG, "params_set: tau must exceed 1/2");
+    if (c->cfg.collision == FSL_TRT && !(tau != 0.5)) return fail(c, FSL_E_ARG, "params_set: bad tau");
+    c->cfg.tau = tau;
+    for (int a = 0; a < 3; ++a) c->cfg.g[a] = g[a];
+    set_phys(c);
+    c->adj.ready = 0;
+    return FSL_OK;
 }
 
 }  // extern "C"

@@ -76,17 +76,25 @@ __device__ __forceinline__ void cell_rho_u(const Geom &G, const Phys &Ph, const 
 // separately so that it keeps its own precision
 template <int ST>
 __device__ __forceinline__ void store_equilibrium(const Geom &G, const Phys &Ph, void *F, int c,
-                                                  float drho, float u0, float u1, float u2) {
+                                                  double drho_d, float u0, float u1, float u2) {
     using SS = Store<ST>;
     typename SS::T *p = (typename SS::T *)F;
+    const float drho = (float)drho_d;
     const float rho = 1.0f + drho;
     float uu = u0 * u0 + u1 * u1 + u2 * u2;
+    // moving populations in FP32; the rest population carries the exact mass balance
+    // sum_q h_q = rho - 1 (the equilibrium's zeroth moment), so that the rounded
+    // weights do not bias the mass of the cell
+    double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
+    for (int q = 1; q < Q; ++q) {
         float cu = cx(q) * u0 + cy(q) * u1 + cz(q) * u2;
         float h = wq(q) * (drho + rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * uu));
-        SS::st(p + q * G.S + c, h, Ph.scale);
+        const typename SS::T v = SS::enc(h, Ph.scale);
+        s += (double)SS::dec(v, Ph.inv);
+        p[q * G.S + c] = v;
     }
+    SS::st(p + c, (float)(drho_d - s), Ph.scale);
 }
 
 __device__ __forceinline__ uint8_t cv_or(uint8_t *cv, int c, uint8_t bits) {
@@ -167,7 +175,7 @@ __global__ void k_conv_init(Geom G, Phys Ph, Dev D) {
             ++cnt;
         }
         float inv = 1.0f / (float)cnt;
-        store_equilibrium<ST>(G, Ph, D.fB, c, rs * inv, s0 * inv, s1 * inv, s2 * inv);
+        store_equilibrium<ST>(G, Ph, D.fB, c, (double)(rs * inv), s0 * inv, s1 * inv, s2 * inv);
         D.m[c] = 0.0;
     }
     GRID_STRIDE(i, nL) {

@@ -81,7 +81,7 @@ __global__ void k_init_pdf(Geom G, Phys Ph, Dev D, InitGeo I) {
         if (f != LIQ && f != IFC) continue;
         int k = (int)(c / ((long long)G.nx * G.ny));
         double rho = I.zs < 0.0 ? 1.0 : I.rho_g0 * (1.0 - 3.0 * I.gz * (I.zs - k));
-        store_equilibrium<ST>(G, Ph, D.fA, (int)c, (float)(rho - 1.0), 0.f, 0.f, 0.f);
+        store_equilibrium<ST>(G, Ph, D.fA, (int)c, rho - 1.0, 0.f, 0.f, 0.f);
         if (f == IFC) D.m[c] = D.phi_cur[c] * rho;
         else D.phi_cur[c] = 1.0;
     }

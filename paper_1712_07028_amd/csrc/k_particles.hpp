@@ -407,7 +407,7 @@ __global__ void k_unc_apply(Geom G, Phys Ph, Dev D, double *phi) {
             u1 = (float)(t[P_U + 1] + (t[P_W + 2] * rx - t[P_W] * rz));
             u2 = (float)(t[P_U + 2] + (t[P_W] * ry - t[P_W + 1] * rx));
         }
-        store_equilibrium<ST>(G, Ph, D.fB, c, (float)(rb - 1.0), u0, u1, u2);
+        store_equilibrium<ST>(G, Ph, D.fB, c, rb - 1.0, u0, u1, u2);
         unsafeAtomicAdd(D.ledger, -rb);
         phi[c] = 1.0;
         if (type == IFC) {

@@ -389,6 +389,44 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
     if (D.np > 0) acc_reduce_wave(D, acc, x, y, z);
 }
 
+// Cell types of a 64 x 4 x 1 tile and its one-cell halo (WALL outside a
+// non-periodic face): 18 rows of 66 bytes; a wave loads 64 bytes of a row, the last
+// two bytes of every row come from lanes of the first wave.  The caller syncs.
+__device__ __forceinline__ void stage_flag_tile(const Geom &G, const uint8_t *flags,
+                                                uint8_t (&tile)[3][TY + 2][TX + 2], int x0, int y0,
+                                                int z, bool interior) {
+    const int nx = G.nx, ny = G.ny, nz = G.nz;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (interior) {
+        const uint8_t *base = flags + (long long)(z - 1) * nx * ny + (long long)(y0 - 1) * nx + (x0 - 1);
+        for (int r = wv; r < 3 * (TY + 2); r += 4) {
+            const int lz = r / (TY + 2), ly = r - lz * (TY + 2);
+            tile[lz][ly][lane] = base[(long long)lz * nx * ny + ly * nx + lane];
+        }
+        if (threadIdx.x < 2 * 3 * (TY + 2)) {
+            const int r = threadIdx.x >> 1, lz = r / (TY + 2), ly = r - lz * (TY + 2), lx = TX + (threadIdx.x & 1);
+            tile[lz][ly][lx] = base[(long long)lz * nx * ny + ly * nx + lx];
+        }
+    } else {
+        for (int i = threadIdx.x; i < 3 * (TY + 2) * (TX + 2); i += 256) {
+            int lx = i % (TX + 2), ly = (i / (TX + 2)) % (TY + 2), lz = i / ((TX + 2) * (TY + 2));
+            int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z + lz - 1;
+            bool ok = true;
+            if (gx < 0 || gx >= nx) { if (G.per[0]) gx = wrapc(gx, nx); else ok = false; }
+            if (gy < 0 || gy >= ny) { if (G.per[1]) gy = wrapc(gy, ny); else ok = false; }
+            if (gz < 0 || gz >= nz) { if (G.per[2]) gz = wrapc(gz, nz); else ok = false; }
+            uint8_t v = WALL;
+            if (ok) v = flags[gx + (long long)nx * (gy + (long long)ny * gz)];
+            tile[lz][ly][lx] = v;
+        }
+    }
+}
+
+// tile t of the launch: XCD-contiguous ranges when the tile count allows
+__device__ __forceinline__ int tile_of_block(int b, int nTiles) {
+    return (nTiles % 8 == 0) ? (b % 8) * (nTiles / 8) + b / 8 : b;
+}
+
 template <int ST>
 __global__ __launch_bounds__(256) void k_stream_collide(Geom G, Phys Ph, Dev D, int tilesX,
                                                         int tilesY, int nTiles) {
@@ -396,7 +434,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geom G, Phys Ph, Dev D, 
 
     const int nx = G.nx, ny = G.ny, nz = G.nz;
     const int b = blockIdx.x;
-    const int t = (nTiles % 8 == 0) ? (b % 8) * (nTiles / 8) + b / 8 : b;
+    const int t = tile_of_block(b, nTiles);
     const int x0 = (t % tilesX) * TX;
     const int rest = t / tilesX;
     const int y0 = (rest % tilesY) * TY;
@@ -404,35 +442,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geom G, Phys Ph, Dev D, 
     const bool interior = x0 >= 1 && x0 + TX + 1 <= nx && y0 >= 1 && y0 + TY + 1 <= ny && z >= 1 &&
                           z + 2 <= nz;
 
-    // cell types of the tile and its one-cell halo: 18 rows of 66 bytes; a wave
-    // loads 64 bytes of a row, the last two bytes of every row come from lanes of
-    // the first wave
-    {
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        if (interior) {
-            const uint8_t *base = D.flags + (long long)(z - 1) * nx * ny + (long long)(y0 - 1) * nx + (x0 - 1);
-            for (int r = wv; r < 3 * (TY + 2); r += 4) {
-                const int lz = r / (TY + 2), ly = r - lz * (TY + 2);
-                tile[lz][ly][lane] = base[(long long)lz * nx * ny + ly * nx + lane];
-            }
-            if (threadIdx.x < 2 * 3 * (TY + 2)) {
-                const int r = threadIdx.x >> 1, lz = r / (TY + 2), ly = r - lz * (TY + 2), lx = TX + (threadIdx.x & 1);
-                tile[lz][ly][lx] = base[(long long)lz * nx * ny + ly * nx + lx];
-            }
-        } else {
-            for (int i = threadIdx.x; i < 3 * (TY + 2) * (TX + 2); i += 256) {
-                int lx = i % (TX + 2), ly = (i / (TX + 2)) % (TY + 2), lz = i / ((TX + 2) * (TY + 2));
-                int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z + lz - 1;
-                bool ok = true;
-                if (gx < 0 || gx >= nx) { if (G.per[0]) gx = wrapc(gx, nx); else ok = false; }
-                if (gy < 0 || gy >= ny) { if (G.per[1]) gy = wrapc(gy, ny); else ok = false; }
-                if (gz < 0 || gz >= nz) { if (G.per[2]) gz = wrapc(gz, nz); else ok = false; }
-                uint8_t v = WALL;
-                if (ok) v = D.flags[gx + (long long)nx * (gy + (long long)ny * gz)];
-                tile[lz][ly][lx] = v;
-            }
-        }
-    }
+    stage_flag_tile(G, D.flags, tile, x0, y0, z, interior);
     __syncthreads();
 
     const int lx = threadIdx.x & (TX - 1), ly = threadIdx.x >> 6;
