@@ -153,6 +153,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the storage forms and the differentiation form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="time only the differentiation form (for kernel profiles)")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--traffic", default=TRAFFIC_FILE,
                     help="JSON file with measured HBM bytes per stream-collide launch")
@@ -173,6 +175,13 @@ def main():
         print("no HIP device", file=sys.stderr)
         sys.exit(1)
     fsl.load_library()
+
+    if args.adjoint_only:
+        from paper_1712_07028_amd import workloads as W
+
+        res = {f"{n}^3": adjoint_rate(fsl, W, torch, n, npart) for n, npart in ((64, 20), (256, 1280))}
+        print(json.dumps({"adjoint": res}), flush=True)
+        return
 
     st = STORAGES[args.storage]
     t0 = time.perf_counter()
