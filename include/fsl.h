@@ -115,7 +115,7 @@ int fsl_step(fsl_ctx *ctx, int n);
  * coordinates, velocities, angular velocities; n: radii, specific densities;
  * u / omega may be NULL for zero) and recompute node coverage.  Newly covered
  * cells hand their liquid mass to the ledger, uncovered cells are re-initialised.
- * FSL_E_ARG if n > max_particles. */
+ * FSL_E_ARG if n > max_particles or a radius is not in (0, 60] cells. */
 int fsl_particles_set(fsl_ctx *ctx, int n, const double *x, const double *u,
                       const double *omega, const double *R, const double *rho_p);
 

@@ -227,6 +227,13 @@ void set_phys(fsl_ctx *c) {
     c->Ph.inv = 1.0f / c->Ph.scale;
 }
 
+// one lattice update of every cell
+template <int ST>
+void launch_stream_collide(fsl_ctx *c, const Dev &Dv) {
+    hipLaunchKernelGGL(k_stream_collide<ST>, dim3(c->nTiles), dim3(256), 0, c->st, c->G, c->Ph, Dv, c->tilesX,
+                       c->tilesY, c->nTiles);
+}
+
 template <int ST> int enqueue_steps(fsl_ctx *c, int n);
 template <int ST> int enqueue_integration(fsl_ctx *c);
 template <int ST> int enqueue_pair_forces(fsl_ctx *c);
@@ -340,8 +347,7 @@ int enqueue_steps(fsl_ctx *c, int n) {
         hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, c->st, D);
         {
             ProfScope ps(c, 0);
-            hipLaunchKernelGGL(k_stream_collide<ST>, dim3(c->nTiles), dim3(256), 0, c->st, c->G, c->Ph, D,
-                               c->tilesX, c->tilesY, c->nTiles);
+            launch_stream_collide<ST>(c, D);
         }
         LAUNCHCHK(c);
         int rc = enqueue_conversions<ST>(c);
@@ -484,8 +490,7 @@ int window_backward(fsl_ctx *c, double dJ, double *dJ_dtau, double *dJ_dg) {
             Dr.fA = slot(i - 1);
             Dr.fB = slot(i);
             ProfScope ps(c, 0);
-            hipLaunchKernelGGL(k_stream_collide<ST_F32>, dim3(c->nTiles), dim3(256), 0, c->st, c->G, c->Ph, Dr,
-                               c->tilesX, c->tilesY, c->nTiles);
+            launch_stream_collide<ST_F32>(c, Dr);
         }
         for (int t = thi; t >= t0 + 1; --t) {
             hipLaunchKernelGGL(k_adj_step, dim3(c->nTiles), dim3(256), 0, c->st, c->G, c->Ph, Dr,
@@ -669,6 +674,7 @@ int fsl_particles_set(fsl_ctx *c, int n, const double *x, const double *u, const
             t[P_W + a] = omega ? omega[3 * P + a] : 0.0;
         }
         if (!(R[P] > 0.0) || !(rho_p[P] > 0.0)) return fail(c, FSL_E_ARG, "particles_set: radius and density must be > 0");
+        if (R[P] > 60.0) return fail(c, FSL_E_ARG, "particles_set: radius above 60 cells");
         t[P_R] = R[P];
         t[P_RHO] = rho_p[P];
         Rmax = std::max(Rmax, R[P]);

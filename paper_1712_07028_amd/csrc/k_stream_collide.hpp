@@ -68,34 +68,38 @@ __device__ __forceinline__ void acc_flush(const Dev &D, const LinkAcc &L, int x,
                 ((float)z - L.an[2]) - L.fr[2]);
 }
 
-// wave64 sum of a 32-bit value, the same in every lane: DPP within rows of 16 lanes
-// (pairs, quads, half-row and row mirrors), then the four row sums via readlane
-__device__ __forceinline__ int row_sum_i(int v) {
-    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
-    v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
-    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
-    v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);  // row_mirror
-    return v;
+// wave64 sums with DPP: pairs, quads, half-row and row mirrors leave every lane of a
+// row of 16 with the row sum; row_bcast:15 on rows 1 and 3 then adds the sum of the
+// row before (lane 31 = rows 0+1, lane 63 = rows 2+3), row_bcast:31 on rows 2 and 3
+// adds lane 31 (lane 63 = whole wave).  Every lane of the wave must be active.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_add_i(int v) {
+    return v + __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, false);
 }
-__device__ __forceinline__ float row_sum_f(float f) {
-    int v = __float_as_int(f);
-    v = __float_as_int(__int_as_float(v) + __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false)));
-    v = __float_as_int(__int_as_float(v) + __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false)));
-    v = __float_as_int(__int_as_float(v) + __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false)));
-    v = __float_as_int(__int_as_float(v) + __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false)));
-    return __int_as_float(v);
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_add_f(float f) {
+    const int v = __float_as_int(f);
+    return f + __int_as_float(__builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, false));
 }
 __device__ __forceinline__ int wave_total_i(int v) {
-    v = row_sum_i(v);
-    return __builtin_amdgcn_readlane(v, 15) + __builtin_amdgcn_readlane(v, 31) +
-           __builtin_amdgcn_readlane(v, 47) + __builtin_amdgcn_readlane(v, 63);
+    v = dpp_add_i<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v = dpp_add_i<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v = dpp_add_i<0x141, 0xF>(v);  // row_half_mirror
+    v = dpp_add_i<0x140, 0xF>(v);  // row_mirror
+    v = dpp_add_i<0x142, 0xA>(v);  // row_bcast:15
+    v = dpp_add_i<0x143, 0xC>(v);  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
 }
+// FP32 sums of 32 lanes, the two halves added in FP64
 __device__ __forceinline__ double wave_total_f(float f) {
-    int v = __float_as_int(row_sum_f(f));
-    return ((double)__int_as_float(__builtin_amdgcn_readlane(v, 15)) +
-            (double)__int_as_float(__builtin_amdgcn_readlane(v, 31))) +
-           ((double)__int_as_float(__builtin_amdgcn_readlane(v, 47)) +
-            (double)__int_as_float(__builtin_amdgcn_readlane(v, 63)));
+    f = dpp_add_f<0xB1, 0xF>(f);
+    f = dpp_add_f<0x4E, 0xF>(f);
+    f = dpp_add_f<0x141, 0xF>(f);
+    f = dpp_add_f<0x140, 0xF>(f);
+    f = dpp_add_f<0x142, 0xA>(f);
+    const int v = __float_as_int(f);
+    return (double)__int_as_float(__builtin_amdgcn_readlane(v, 31)) +
+           (double)__int_as_float(__builtin_amdgcn_readlane(v, 63));
 }
 // two small integers (|value| < 2^15 after the wave sum) in one 32-bit word
 __device__ __forceinline__ int pack2(int hi, int lo) { return hi * 65536 + lo; }
@@ -114,9 +118,12 @@ __device__ __forceinline__ void acc_reduce_wave(const Dev &D, const LinkAcc &L, 
     const float ts0 = dy * L.fs[2] - dz * L.fs[1], ts1 = dz * L.fs[0] - dx * L.fs[2], ts2 = dx * L.fs[1] - dy * L.fs[0];
     const int ta0 = dy * L.ca[2] - dz * L.ca[1], ta1 = dz * L.ca[0] - dx * L.ca[2], ta2 = dx * L.ca[1] - dy * L.ca[0];
     const int td0 = dy * L.cd[2] - dz * L.cd[1], td1 = dz * L.cd[0] - dx * L.cd[2], td2 = dx * L.cd[1] - dy * L.cd[0];
-    // direction counts are at most 6 (axis) and 12 (diagonal) per lane, so their wave
-    // sums fit 16 bits; the torque counts scale with the sphere size and stay 32-bit
+    // direction counts per lane and component are at most 2 (axis) and 4 (diagonal),
+    // so their wave sums fit 16 bits; torque counts are bounded by the lever arm
+    // (|x - a| <= R + 2 for the nodes next to a sphere of radius R <= 60): the
+    // diagonal ones stay below 2^15 in a wave sum, the axis ones far below 2^15
     const int p0 = pack2(L.ca[0], L.cd[0]), p1 = pack2(L.ca[1], L.cd[1]), p2 = pack2(L.ca[2], L.cd[2]);
+    const int r0 = pack2(ta0, td0), r1 = pack2(ta1, td1), r2 = pack2(ta2, td2);
     while (true) {
         const unsigned long long act = __ballot(key >= 0);
         if (!act) break;
@@ -129,13 +136,15 @@ __device__ __forceinline__ void acc_reduce_wave(const Dev &D, const LinkAcc &L, 
                      T2s = wave_total_f(mine ? ts2 : 0.f);
         const double dms = wave_total_f(mine ? L.dm : 0.f);
         const int q0 = wave_total_i(mine ? p0 : 0), q1 = wave_total_i(mine ? p1 : 0), q2 = wave_total_i(mine ? p2 : 0);
-        const int ta = wave_total_i(mine ? ta0 : 0), tc = wave_total_i(mine ? ta1 : 0), tf = wave_total_i(mine ? ta2 : 0);
-        const int tb = wave_total_i(mine ? td0 : 0), te = wave_total_i(mine ? td1 : 0), tg = wave_total_i(mine ? td2 : 0);
+        const int s0 = wave_total_i(mine ? r0 : 0), s1 = wave_total_i(mine ? r1 : 0), s2 = wave_total_i(mine ? r2 : 0);
         if ((int)lane_id() == leader) {
-            int a0, d0, a1, d1, a2, d2;
+            int a0, d0, a1, d1, a2, d2, ta, tb, tc, te, tf, tg;
             unpack2(q0, a0, d0);
             unpack2(q1, a1, d1);
             unpack2(q2, a2, d2);
+            unpack2(s0, ta, tb);
+            unpack2(s1, tc, te);
+            unpack2(s2, tf, tg);
             const double F[3] = {F0s + (a0 * (1.0 / 9.0) + d0 * (1.0 / 18.0)),
                                  F1s + (a1 * (1.0 / 9.0) + d1 * (1.0 / 18.0)),
                                  F2s + (a2 * (1.0 / 9.0) + d2 * (1.0 / 18.0))};
@@ -159,9 +168,82 @@ __device__ __forceinline__ void acc_reduce_wave(const Dev &D, const LinkAcc &L, 
     }
 }
 
-// One cell of the fused step.  INTERIOR: the tile and its halo lie inside the box,
-// so a source is the cell index minus a uniform offset (no wrap, no wall).  Lanes
-// past the box edge (inb false) stay in the wave with nothing to do, because the
+// ---- moments and collision of one cell ------------------------------------------
+// Populations come in shifted (h = f - w).  The D3Q19 opposite pairs (q, opp(q)) with
+// q < opp(q) are (1,2) (3,4) (5,6) (7,10) (8,9) (11,14) (12,13) (15,18) (16,17); the
+// sums below are written as short trees over these pairs so that no long chain of
+// dependent additions forms.
+struct Moments {
+    double drho;    // rho - 1 in FP64 (the FP32 terms are summed without loss that matters)
+    float j0, j1, j2;
+};
+__device__ __forceinline__ Moments cell_moments(const float (&h)[Q]) {
+    auto dp = [&](int q, int o) { return (double)h[q] + (double)h[o]; };
+    const double a = ((double)h[0] + dp(1, 2)) + (dp(3, 4) + dp(5, 6));
+    const double b = (dp(7, 10) + dp(8, 9)) + (dp(11, 14) + dp(12, 13));
+    const double c = dp(15, 18) + dp(16, 17);
+    const float d1 = h[1] - h[2], d3 = h[3] - h[4], d5 = h[5] - h[6], d7 = h[7] - h[10], d8 = h[8] - h[9];
+    const float d11 = h[11] - h[14], d12 = h[12] - h[13], d15 = h[15] - h[18], d16 = h[16] - h[17];
+    Moments M;
+    M.drho = (a + b) + c;
+    M.j0 = ((d1 + d7) + (d8 + d11)) + d12;
+    M.j1 = ((d3 + d7) + (d15 + d16)) - d8;
+    M.j2 = ((d5 + d11) + (d15 - d16)) - d12;
+    return M;
+}
+
+// TRT collision with Guo forcing (Eq. LBE2) in shifted form, written to B at cell c.
+// The rest population is stored as the exact mass balance of the collision,
+// h*_0 = sum_q h_q - sum_{q>0} h*_q with the stored moving values summed in FP64:
+// in exact arithmetic it is the same population, and FP32 rounding of the weights
+// then cannot bias the mass.  Returns false on a NaN density or velocity.
+template <int ST>
+__device__ __forceinline__ bool collide_store(const Phys &Ph, const float (&fi)[Q], const Moments &M,
+                                              typename Store<ST>::T *B, long long S, unsigned c) {
+    using SS = Store<ST>;
+    using T = typename SS::T;
+    const float inv = Ph.inv, sc = Ph.scale;
+    const float drho = (float)M.drho;
+    const float rho = 1.0f + drho;
+    const float irho = __builtin_amdgcn_rcpf(rho);
+    const float u0 = M.j0 * irho + 0.5f * Ph.g[0];
+    const float u1 = M.j1 * irho + 0.5f * Ph.g[1];
+    const float u2 = M.j2 * irho + 0.5f * Ph.g[2];
+    const float F0 = rho * Ph.g[0], F1 = rho * Ph.g[1], F2 = rho * Ph.g[2];
+    const float uu = u0 * u0 + u1 * u1 + u2 * u2;
+    const float uF = u0 * F0 + u1 * F1 + u2 * F2;
+    const float lp = Ph.lp, lm = Ph.lm;
+    const float ap = 1.0f + 0.5f * lp, am = 1.0f + 0.5f * lm;
+    double sp[9];
+    int k = 0;
+#pragma unroll
+    for (int q = 1; q < Q; q += 1) {
+        if (opp(q) < q) continue;
+        const int o = opp(q);
+        const float w = wq(q);
+        const float cu = cx(q) * u0 + cy(q) * u1 + cz(q) * u2;
+        const float cF = cx(q) * F0 + cy(q) * F1 + cz(q) * F2;
+        const float ep = w * (drho + rho * (4.5f * cu * cu - 1.5f * uu));
+        const float em = w * rho * 3.0f * cu;
+        const float Fp = w * (-3.0f * uF + 9.0f * cu * cF);
+        const float Fm = w * 3.0f * cF;
+        const float hp = 0.5f * (fi[q] + fi[o]) - ep;
+        const float hm = 0.5f * (fi[q] - fi[o]) - em;
+        const float even = lp * hp + ap * Fp, odd = lm * hm + am * Fm;
+        const T vq = SS::enc(fi[q] + even + odd, sc), vo = SS::enc(fi[o] + even - odd, sc);
+        sp[k++] = (double)SS::dec(vq, inv) + (double)SS::dec(vo, inv);
+        B[q * S + c] = vq;
+        B[o * S + c] = vo;
+    }
+    const double sout = (((sp[0] + sp[1]) + (sp[2] + sp[3])) + ((sp[4] + sp[5]) + (sp[6] + sp[7]))) + sp[8];
+    SS::st(B + c, (float)(M.drho - sout), sc);
+    return rho == rho && u0 == u0 && u1 == u1 && u2 == u2;
+}
+
+// One boundary cell of the fused step (a cell with an interface, gas or particle
+// next to it, or an interface cell).  INTERIOR: the tile and its halo lie inside
+// the box, so a source is the cell index minus a uniform offset (no wrap, no wall).
+// Lanes without a cell (inb false) stay in the wave with nothing to do, because the
 // wave-level sums below read every lane.
 template <int ST, bool INTERIOR>
 __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev &D,
@@ -209,12 +291,12 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
         // all independent loads first: own populations, pulled populations, ids
         if (needOwn) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) fo[q] = SS::ld(A + q * S + c, inv);
+            for (int q = 0; q < Q; ++q) fo[q] = SS::ld(A + q * S + (unsigned)c, inv);
         }
-        fi[0] = needOwn ? fo[0] : SS::ld(A + c, inv);
+        fi[0] = needOwn ? fo[0] : SS::ld(A + (unsigned)c, inv);
 #pragma unroll
         for (int q = 1; q < Q; ++q)
-            if (!((miss >> q) & 1u)) fi[q] = SS::ld(A + q * S + src(q), inv);
+            if (!((miss >> q) & 1u)) fi[q] = SS::ld(A + q * S + (unsigned)src(q), inv);
         // particle ids of the solid sources: one batch of loads, reduced to the first
         // id P0 and the mask of links whose particle is P0
         int P0 = -1;
@@ -312,24 +394,9 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
                 }
             }
         }
-        // moments; the density deviation is summed in FP64 (exact for 19 FP32 terms)
-        double drho_d = 0.0;
-        float j0 = 0.f, j1 = 0.f, j2 = 0.f;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            drho_d += (double)fi[q];
-            j0 += cx(q) * fi[q];
-            j1 += cy(q) * fi[q];
-            j2 += cz(q) * fi[q];
-        }
-        const float drho = (float)drho_d;
-        const float rho = 1.0f + drho;
-        const float irho = 1.0f / rho;
-        const float u0 = j0 * irho + 0.5f * Ph.g[0];
-        const float u1 = j1 * irho + 0.5f * Ph.g[1];
-        const float u2 = j2 * irho + 0.5f * Ph.g[2];
-        if (!(rho == rho) || !(u0 == u0) || !(u1 == u1) || !(u2 == u2)) atomicOr(D.err, ERR_NAN);
-
+        // moments; the density deviation in FP64
+        const Moments M = cell_moments(fi);
+        const double drho_d = M.drho;
         if (fl == IFC) {
             // Eqs. (massExchange, massExchangeb), mass form, FP64
             const double phx = D.phi_cur[c];
@@ -351,37 +418,7 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
             isE = !isF && phin <= Ph.eps;
         }
 
-        // TRT collision with Guo forcing (Eq. LBE2), shifted form: e - w and f - w
-        const float F0 = rho * Ph.g[0], F1 = rho * Ph.g[1], F2 = rho * Ph.g[2];
-        const float uu = u0 * u0 + u1 * u1 + u2 * u2;
-        const float uF = u0 * F0 + u1 * F1 + u2 * F2;
-        const float lp = Ph.lp, lm = Ph.lm;
-        const float ap = 1.0f + 0.5f * lp, am = 1.0f + 0.5f * lm;
-        // moving populations; their stored values are summed in FP64 so that the rest
-        // population can carry the exact mass balance of the collision (in exact
-        // arithmetic the collision conserves mass, so h*_0 = sum_q h_q - sum_{q>0} h*_q
-        // is the same population; this only keeps FP32 rounding from biasing the mass)
-        double sout = 0.0;
-#pragma unroll
-        for (int q = 1; q < Q; q += 1) {
-            if (opp(q) < q) continue;
-            const int o = opp(q);
-            const float w = wq(q);
-            const float cu = cx(q) * u0 + cy(q) * u1 + cz(q) * u2;
-            const float cF = cx(q) * F0 + cy(q) * F1 + cz(q) * F2;
-            const float ep = w * (drho + rho * (4.5f * cu * cu - 1.5f * uu));
-            const float em = w * rho * 3.0f * cu;
-            const float Fp = w * (-3.0f * uF + 9.0f * cu * cF);
-            const float Fm = w * 3.0f * cF;
-            const float hp = 0.5f * (fi[q] + fi[o]) - ep;
-            const float hm = 0.5f * (fi[q] - fi[o]) - em;
-            const float even = lp * hp + ap * Fp, odd = lm * hm + am * Fm;
-            const T vq = SS::enc(fi[q] + even + odd, sc), vo = SS::enc(fi[o] + even - odd, sc);
-            sout += (double)SS::dec(vq, inv) + (double)SS::dec(vo, inv);
-            B[q * S + c] = vq;
-            B[o * S + c] = vo;
-        }
-        SS::st(B + c, (float)(drho_d - sout), sc);
+        if (!collide_store<ST>(Ph, fi, M, B, S, (unsigned)c)) atomicOr(D.err, ERR_NAN);
     }
 
     wave_append(isF, c, D.lF, D.counters + C_NF, D.cap, D.err);
@@ -390,34 +427,61 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
 }
 
 // Cell types of a 64 x 4 x 1 tile and its one-cell halo (WALL outside a
-// non-periodic face): 18 rows of 66 bytes; a wave loads 64 bytes of a row, the last
-// two bytes of every row come from lanes of the first wave.  The caller syncs.
+// non-periodic face): 3 x 6 rows of 66 bytes, 1,188 bytes, at most five per thread.
+// All loads of a thread are issued before the first is written, so that their
+// latencies overlap.  The caller syncs.
 __device__ __forceinline__ void stage_flag_tile(const Geom &G, const uint8_t *flags,
                                                 uint8_t (&tile)[3][TY + 2][TX + 2], int x0, int y0,
                                                 int z, bool interior) {
+    constexpr int NE = 3 * (TY + 2) * (TX + 2);
+    constexpr int K = (NE + 255) / 256;
     const int nx = G.nx, ny = G.ny, nz = G.nz;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (interior) {
-        const uint8_t *base = flags + (long long)(z - 1) * nx * ny + (long long)(y0 - 1) * nx + (x0 - 1);
-        for (int r = wv; r < 3 * (TY + 2); r += 4) {
-            const int lz = r / (TY + 2), ly = r - lz * (TY + 2);
-            tile[lz][ly][lane] = base[(long long)lz * nx * ny + ly * nx + lane];
-        }
-        if (threadIdx.x < 2 * 3 * (TY + 2)) {
-            const int r = threadIdx.x >> 1, lz = r / (TY + 2), ly = r - lz * (TY + 2), lx = TX + (threadIdx.x & 1);
-            tile[lz][ly][lx] = base[(long long)lz * nx * ny + ly * nx + lx];
-        }
-    } else {
-        for (int i = threadIdx.x; i < 3 * (TY + 2) * (TX + 2); i += 256) {
-            int lx = i % (TX + 2), ly = (i / (TX + 2)) % (TY + 2), lz = i / ((TX + 2) * (TY + 2));
+    uint8_t v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int e = threadIdx.x + 256 * k;
+        v[k] = WALL;
+        if (e < NE) {
+            const int lx = e % (TX + 2), r = e / (TX + 2);
+            const int ly = r % (TY + 2), lz = r / (TY + 2);
             int gx = x0 + lx - 1, gy = y0 + ly - 1, gz = z + lz - 1;
-            bool ok = true;
-            if (gx < 0 || gx >= nx) { if (G.per[0]) gx = wrapc(gx, nx); else ok = false; }
-            if (gy < 0 || gy >= ny) { if (G.per[1]) gy = wrapc(gy, ny); else ok = false; }
-            if (gz < 0 || gz >= nz) { if (G.per[2]) gz = wrapc(gz, nz); else ok = false; }
-            uint8_t v = WALL;
-            if (ok) v = flags[gx + (long long)nx * (gy + (long long)ny * gz)];
-            tile[lz][ly][lx] = v;
+            if (interior) {
+                v[k] = flags[gx + (long long)nx * (gy + (long long)ny * gz)];
+            } else {
+                bool ok = true;
+                if (gx < 0 || gx >= nx) { if (G.per[0]) gx = wrapc(gx, nx); else ok = false; }
+                if (gy < 0 || gy >= ny) { if (G.per[1]) gy = wrapc(gy, ny); else ok = false; }
+                if (gz < 0 || gz >= nz) { if (G.per[2]) gz = wrapc(gz, nz); else ok = false; }
+                if (ok) v[k] = flags[gx + (long long)nx * (gy + (long long)ny * gz)];
+            }
+        }
+    }
+    uint8_t *flat = &tile[0][0][0];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int e = threadIdx.x + 256 * k;
+        if (e < NE) flat[e] = v[k];
+    }
+}
+
+// Per row of the staged tile (3 planes x 6 rows of 66 cells): w3 bit i is set when
+// one of the columns i, i+1, i+2 (the cells x-1, x, x+1 of lane i) is neither liquid
+// nor a wall, w1 bit i when column i+1 (the cell x of lane i) is neither.  One
+// ballot per row; the caller syncs before and after.
+__device__ __forceinline__ void build_row_masks(const uint8_t (&tile)[3][TY + 2][TX + 2],
+                                                unsigned long long (&w3)[3 * (TY + 2)],
+                                                unsigned long long (&w1)[3 * (TY + 2)]) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int r = wv; r < 3 * (TY + 2); r += 4) {
+        const int lz = r / (TY + 2), ly = r - lz * (TY + 2);
+        const uint8_t a = tile[lz][ly][lane], b = tile[lz][ly][TX + (lane & 1)];
+        const unsigned long long lo = __ballot(a != LIQ && a != WALL);
+        const unsigned long long hi = __ballot(lane < 2 && b != LIQ && b != WALL) & 3ull;
+        const unsigned long long s1 = (lo >> 1) | (hi << 63);
+        const unsigned long long s2 = (lo >> 2) | (hi << 62);
+        if (lane == 0) {
+            w3[r] = lo | s1 | s2;
+            w1[r] = s1;
         }
     }
 }
@@ -427,29 +491,100 @@ __device__ __forceinline__ int tile_of_block(int b, int nTiles) {
     return (nTiles % 8 == 0) ? (b % 8) * (nTiles / 8) + b / 8 : b;
 }
 
+// A liquid cell whose 18 neighbours are liquid or beyond a wall: plain pull
+// (Eq. LBE1) with half-way bounce-back at walls, then the collision (Eq. LBE2).
+template <int ST, bool INTERIOR>
+__device__ __forceinline__ void lean_cell(const Geom &G, const Phys &Ph, const Dev &D,
+                                          const uint8_t (&tile)[3][TY + 2][TX + 2], int lx, int ly, int x,
+                                          int y, int z) {
+    using SS = Store<ST>;
+    using T = typename SS::T;
+    const int nx = G.nx, ny = G.ny, nz = G.nz, nxy = nx * ny;
+    const int c = x + nx * y + nxy * z;
+    const T *A = (const T *)D.fA;
+    T *B = (T *)D.fB;
+    const long long S = G.S;
+    float fi[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const T *p;
+        if (INTERIOR || q == 0) {
+            p = A + q * S + (unsigned)(c - (cx(q) + cy(q) * nx + cz(q) * nxy));
+        } else {
+            const bool wall = tile[1 - cz(q)][ly + 1 - cy(q)][lx + 1 - cx(q)] == WALL;
+            const int s = wrapc(x - cx(q), nx) + nx * wrapc(y - cy(q), ny) + nxy * wrapc(z - cz(q), nz);
+            p = wall ? A + opp(q) * S + (unsigned)c : A + q * S + (unsigned)s;
+        }
+        fi[q] = SS::ld(p, Ph.inv);
+    }
+    const Moments M = cell_moments(fi);
+    if (!collide_store<ST>(Ph, fi, M, B, S, (unsigned)c)) atomicOr(D.err, ERR_NAN);
+}
+
+// The fused step of one 64 x 4 tile of a plane: the cell types of the tile and its
+// halo are staged in LDS; lean cells (liquid, with liquid or wall neighbours only)
+// take the plain path in place; the other liquid and interface cells of the tile
+// are compacted into a list and handled by as few waves as they fill, so that the
+// boundary work (bounce-back, free surface, mass exchange, forces, lists) is not
+// repeated by every wave that holds one such cell.
 template <int ST>
 __global__ __launch_bounds__(256) void k_stream_collide(Geom G, Phys Ph, Dev D, int tilesX,
                                                         int tilesY, int nTiles) {
     __shared__ uint8_t tile[3][TY + 2][TX + 2];
+    __shared__ unsigned long long w3[3 * (TY + 2)], w1[3 * (TY + 2)];
+    __shared__ uint8_t list[TX * TY];
+    __shared__ int wcount[4];
 
-    const int nx = G.nx, ny = G.ny, nz = G.nz;
-    const int b = blockIdx.x;
-    const int t = tile_of_block(b, nTiles);
+    const int t = tile_of_block(blockIdx.x, nTiles);
     const int x0 = (t % tilesX) * TX;
     const int rest = t / tilesX;
     const int y0 = (rest % tilesY) * TY;
     const int z = rest / tilesY;
-    const bool interior = x0 >= 1 && x0 + TX + 1 <= nx && y0 >= 1 && y0 + TY + 1 <= ny && z >= 1 &&
-                          z + 2 <= nz;
-
+    const bool interior = x0 >= 1 && x0 + TX + 1 <= G.nx && y0 >= 1 && y0 + TY + 1 <= G.ny && z >= 1 &&
+                          z + 2 <= G.nz;
     stage_flag_tile(G, D.flags, tile, x0, y0, z, interior);
     __syncthreads();
+    build_row_masks(tile, w3, w1);
+    __syncthreads();
 
-    const int lx = threadIdx.x & (TX - 1), ly = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lx = lane, ly = wv;
     const int x = x0 + lx, y = y0 + ly;
-    const bool inb = x < nx && y < ny;
-    if (interior) sc_cell<ST, true>(G, Ph, D, tile, lx, ly, x, y, z, inb);
-    else sc_cell<ST, false>(G, Ph, D, tile, lx, ly, x, y, z, inb);
+    const bool inb = x < G.nx && y < G.ny;
+    const uint8_t fl = inb ? tile[1][ly + 1][lx + 1] : WALL;
+    // any neighbour of the wave's cells that is neither liquid nor a wall (same
+    // plane: the 3 x 3 square; planes z +- 1: the plus shape)
+    constexpr int R6 = TY + 2;
+    const unsigned long long nb = w3[R6 + ly + 1] | w3[R6 + ly] | w3[R6 + ly + 2] | w3[ly + 1] |
+                                  w3[2 * R6 + ly + 1] | w1[ly] | w1[ly + 2] | w1[2 * R6 + ly] |
+                                  w1[2 * R6 + ly + 2];
+    const bool lean = inb && fl == LIQ && !((nb >> lx) & 1ull);
+    if (lean) {
+        if (interior) lean_cell<ST, true>(G, Ph, D, tile, lx, ly, x, y, z);
+        else lean_cell<ST, false>(G, Ph, D, tile, lx, ly, x, y, z);
+    }
+
+    // the tile's boundary cells, in lane order
+    const bool need = inb && !lean && (fl == LIQ || fl == IFC);
+    const unsigned long long m = __ballot(need);
+    if (lane == 0) wcount[wv] = (int)__popcll(m);
+    __syncthreads();
+    int base = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const int n = wcount[w];
+        base += w < wv ? n : 0;
+        total += n;
+    }
+    if (need) list[base + (int)__popcll(m & ((1ull << lane) - 1ull))] = (uint8_t)threadIdx.x;
+    __syncthreads();
+    if (wv * 64 < total) {
+        const bool has = (int)threadIdx.x < total;
+        const int e = has ? list[threadIdx.x] : 0;
+        const int ex = e & (TX - 1), ey = e >> 6;
+        if (interior) sc_cell<ST, true>(G, Ph, D, tile, ex, ey, x0 + ex, y0 + ey, z, has);
+        else sc_cell<ST, false>(G, Ph, D, tile, ex, ey, x0 + ex, y0 + ey, z, has);
+    }
 }
 
 }  // namespace fsl
