@@ -330,7 +330,9 @@ int enqueue_coverage_step(fsl_ctx *c) {
     const int np = D.np;
     ProfScope ps(c, 5);
     dim3 pw((np + 3) / 4);
-    hipLaunchKernelGGL(k_cov_claim, pw, dim3(256), 0, c->st, c->G, D);
+    hipLaunchKernelGGL(k_cov_flag_init, dim3(grid_for(np)), dim3(256), 0, c->st, D);
+    hipLaunchKernelGGL(k_cov_flag_pairs, dim3(grid_for(c->L.pcap, 256, 1024)), dim3(256), 0, c->st, D, c->L.pcap);
+    hipLaunchKernelGGL(k_cov_claim, pw, dim3(256), 0, c->st, c->G, D, 0);
     hipLaunchKernelGGL(k_cov_scan, pw, dim3(256), 0, c->st, c->G, D);
     int rc = enqueue_cover_events<ST>(c, D, D.phi_nxt);
     if (rc) return rc;
@@ -372,7 +374,7 @@ int enqueue_coverage_full(fsl_ctx *c) {
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, c->st, Dv);
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(c->G.N, 256, 4096)), dim3(256), 0, c->st, Dv.claim,
                        c->G.N, CLAIM_NONE);
-    if (Dv.np > 0) hipLaunchKernelGGL(k_cov_claim, dim3((Dv.np + 3) / 4), dim3(256), 0, c->st, c->G, Dv);
+    if (Dv.np > 0) hipLaunchKernelGGL(k_cov_claim, dim3((Dv.np + 3) / 4), dim3(256), 0, c->st, c->G, Dv, 1);
     hipLaunchKernelGGL(k_cov_scan_dense, dim3(grid_for(c->G.N, 256, 4096)), dim3(256), 0, c->st, c->G, Dv);
     int rc = enqueue_cover_events<ST>(c, Dv, Dv.phi_cur);
     if (rc) return rc;

@@ -46,12 +46,14 @@ constexpr uint8_t CV_F = 1, CV_E0 = 2, CV_E = 4, CV_NEWG = 8, CV_NEWL = 16;
 
 // counters in the control block
 enum Counter {
-    C_NF = 0, C_NE0, C_NE, C_NNG, C_NNL, C_NMERGE, C_NCOVER, C_NUNCOVER, C_NPAIRS,
+    C_NF = 0, C_NE0, C_NE, C_NNG, C_NNL, C_NMERGE, C_NCOVER, C_NUNCOVER, C_NPAIRS, C_COVALL,
     C_COUNT
 };
 
 // particle table: 16 doubles per particle
-enum PSlot { P_X = 0, P_U = 3, P_W = 6, P_R = 9, P_RHO = 10, P_XOLD = 11, P_STRIDE = 16 };
+// P_OVL: 1 when the coverage update must resolve overlaps through claims (a sphere
+// within one cell of another, or one that moved half a cell or more in a step)
+enum PSlot { P_X = 0, P_U = 3, P_W = 6, P_R = 9, P_RHO = 10, P_XOLD = 11, P_OVL = 14, P_STRIDE = 16 };
 // particle accumulators: F(3) T(3) dm(1) pad -> 8 doubles
 constexpr int ACC_STRIDE = 8;
 // bubble table: 16 doubles per id

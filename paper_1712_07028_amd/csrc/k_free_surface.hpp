@@ -310,6 +310,23 @@ __global__ __launch_bounds__(256) void k_bubble_accum(Geom G, Dev D, const doubl
     __syncthreads();
     const long long N = G.N;
     const long long nchunk = (N + 15) / 16;
+    // the thread's sums for the bubble of the cells it is walking; they go to the
+    // block's table only when the bubble changes (the cells of one region mostly
+    // belong to one bubble)
+    int bc = -1;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0, a5 = 0.0;
+    auto flush = [&]() {
+        if (bc >= 0) {
+            double *a = acc + bc * BACC_STRIDE;
+            atomicAdd(a + 0, a0);
+            atomicAdd(a + 1, a1);
+            atomicAdd(a + 2, a2);
+            atomicAdd(a + 3, a3);
+            atomicAdd(a + 4, a4);
+            atomicAdd(a + 5, a5);
+        }
+        a0 = a1 = a2 = a3 = a4 = a5 = 0.0;
+    };
     for (long long ch = blockIdx.x * (long long)blockDim.x + threadIdx.x; ch < nchunk;
          ch += (long long)gridDim.x * blockDim.x) {
         long long c0 = ch * 16;
@@ -328,22 +345,27 @@ __global__ __launch_bounds__(256) void k_bubble_accum(Geom G, Dev D, const doubl
         }
         if (!any) continue;
         for (int k = 0; k < 16; ++k) {
-            long long c = c0 + k;
+            const int c = (int)(c0 + k);
             if (c >= N) break;
             uint32_t f = (wds[k >> 2] >> (8 * (k & 3))) & 0xffu;
             if (f != GAS && f != IFC) continue;
             int id = D.bub[c];
             int b = id < nb ? root[id] : 0;
+            if (b != bc) {
+                flush();
+                bc = b;
+            }
             double w = (f == GAS) ? 1.0 : 1.0 - phi[c];
-            int x = (int)(c % G.nx), y = (int)((c / G.nx) % G.ny), z = (int)(c / ((long long)G.nx * G.ny));
-            double *a = acc + b * BACC_STRIDE;
-            atomicAdd(a + 0, w);
-            atomicAdd(a + 1, w * x);
-            atomicAdd(a + 2, w * y);
-            atomicAdd(a + 3, w * z);
-            atomicAdd(a + (f == GAS ? 4 : 5), 1.0);
+            const int x = c % G.nx, yz = c / G.nx, y = yz % G.ny, z = yz / G.ny;
+            a0 += w;
+            a1 += w * x;
+            a2 += w * y;
+            a3 += w * z;
+            if (f == GAS) a4 += 1.0;
+            else a5 += 1.0;
         }
     }
+    flush();
     __syncthreads();
     for (int i = threadIdx.x; i < nb * BACC_STRIDE; i += blockDim.x)
         if (acc[i] != 0.0) unsafeAtomicAdd(D.bacc + i, acc[i]);

@@ -170,9 +170,18 @@ __global__ __launch_bounds__(256) void k_solid_pairs(Geom G, Dev D, int pcap) {
     const int lane = threadIdx.x & 63;
     for (int k = blockIdx.x * 4 + (threadIdx.x >> 6); k < n; k += gridDim.x * 4) {
     const int pa = D.pairs[k].x, pb = D.pairs[k].y;
+    {
+        // nodes of one sphere next to nodes of the other need the centres closer than
+        // the radii plus the longest link (sqrt 2); margin 1.5
+        const double *ta = D.ptab + (long long)pa * P_STRIDE, *tb = D.ptab + (long long)pb * P_STRIDE;
+        const double d0 = ta[P_X] - tb[P_X], d1 = ta[P_X + 1] - tb[P_X + 1], d2 = ta[P_X + 2] - tb[P_X + 2];
+        const double reach = ta[P_R] + tb[P_R] + 1.5;
+        if (d0 * d0 + d1 * d1 + d2 * d2 > reach * reach) continue;
+    }
     for (int side = 0; side < 2; ++side) {
         const int Pp = side ? pb : pa, Po = side ? pa : pb;
         const double *tp = D.ptab + (long long)Pp * P_STRIDE, *to = D.ptab + (long long)Po * P_STRIDE;
+        const double ro = (to[P_R] + 1.5) * (to[P_R] + 1.5);
         int lo[3], hi[3], lo2[3], hi2[3];
         sphere_box(G, tp + P_X, tp[P_R], lo, hi);
         sphere_box(G, to + P_X, to[P_R] + 1.0, lo2, hi2);
@@ -183,6 +192,11 @@ __global__ __launch_bounds__(256) void k_solid_pairs(Geom G, Dev D, int pcap) {
             const int tot = ex * ey * ez;
             for (int s2 = lane; s2 < tot; s2 += 64) {
                 const int i = lo[0] + s2 % ex, j = lo[1] + (s2 / ex) % ey, kk = lo[2] + s2 / (ex * ey);
+                {
+                    // only nodes within a link of the other sphere can have such links
+                    const double e0 = i - to[P_X], e1 = j - to[P_X + 1], e2 = kk - to[P_X + 2];
+                    if (e0 * e0 + e1 * e1 + e2 * e2 > ro) continue;
+                }
                 const int c = i + G.nx * (j + G.ny * kk);
                 if (D.flags[c] != SOL || D.pid[c] != Pp) continue;
                 const double rx = i - tp[P_X], ry = j - tp[P_X + 1], rz = kk - tp[P_X + 2];
@@ -274,11 +288,47 @@ __global__ void k_substep(Dev D, Geom G, double dt, double g0, double g1, double
 }
 
 // ---- coverage update --------------------------------------------------------------
-// one wave per particle walks its bounding box
-__global__ __launch_bounds__(256) void k_cov_claim(Geom G, Dev D) {
+// Which spheres resolve their coverage through claims (lowest index wins an
+// overlap): those with a candidate partner whose centre is closer than the radii
+// plus one cell at the new positions, and those that moved half a cell or more.
+// For every other sphere no node can be inside it and another sphere at once, so
+// its cover and uncover events follow from the inside tests at the old and new
+// positions alone.
+__global__ void k_cov_flag_init(Dev D) {
+    GRID_STRIDE(P, D.np) {
+        double *t = D.ptab + (long long)P * P_STRIDE;
+        const double m = fmax(fabs(t[P_X] - t[P_XOLD]), fmax(fabs(t[P_X + 1] - t[P_XOLD + 1]), fabs(t[P_X + 2] - t[P_XOLD + 2])));
+        t[P_OVL] = 0.0;
+        // a sphere that moved half a cell or more in one step may meet partners that
+        // the pair list (taken at the old positions) does not hold: then every
+        // sphere takes the claim path this step
+        if (m >= 0.5) atomicOr(D.counters + C_COVALL, 1);
+    }
+}
+__device__ __forceinline__ bool cov_claims(const Dev &D, const double *t) {
+    return t[P_OVL] != 0.0 || D.counters[C_COVALL] != 0;
+}
+__global__ void k_cov_flag_pairs(Dev D, int pcap) {
+    const int n = min(D.counters[C_NPAIRS], pcap);
+    GRID_STRIDE(k, n) {
+        const int a = D.pairs[k].x, b = D.pairs[k].y;
+        double *ta = D.ptab + (long long)a * P_STRIDE, *tb = D.ptab + (long long)b * P_STRIDE;
+        const double d0 = ta[P_X] - tb[P_X], d1 = ta[P_X + 1] - tb[P_X + 1], d2 = ta[P_X + 2] - tb[P_X + 2];
+        const double r = ta[P_R] + tb[P_R] + 1.0;
+        if (d0 * d0 + d1 * d1 + d2 * d2 < r * r) {
+            ta[P_OVL] = 1.0;
+            tb[P_OVL] = 1.0;
+        }
+    }
+}
+
+// one wave per particle walks its bounding box; all = 0 limits the claims to the
+// spheres flagged above
+__global__ __launch_bounds__(256) void k_cov_claim(Geom G, Dev D, int all) {
     int P = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (P >= D.np) return;
     const double *t = D.ptab + (long long)P * P_STRIDE;
+    if (!all && !cov_claims(D, t)) return;
     int lo[3], hi[3];
     sphere_box(G, t + P_X, t[P_R], lo, hi);
     int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
@@ -322,9 +372,27 @@ __global__ __launch_bounds__(256) void k_cov_scan(Geom G, Dev D) {
     for (int a = 0; a < 3; ++a) { lo[a] = min(lo[a], lo2[a]); hi[a] = max(hi[a], hi2[a]); }
     int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
     int tot = ex * ey * ez;
+    if (cov_claims(D, t)) {
+        for (int s = threadIdx.x & 63; s < tot; s += 64) {
+            int i = lo[0] + s % ex, j = lo[1] + (s / ex) % ey, k = lo[2] + s / (ex * ey);
+            classify_node(D, i + G.nx * (j + G.ny * k), P);
+        }
+        return;
+    }
+    // a sphere alone: only nodes whose inside test changed between the old and new
+    // positions can change owner
     for (int s = threadIdx.x & 63; s < tot; s += 64) {
         int i = lo[0] + s % ex, j = lo[1] + (s / ex) % ey, k = lo[2] + s / (ex * ey);
-        classify_node(D, i + G.nx * (j + G.ny * k), P);
+        const bool in_new = inside(i, j, k, t + P_X, t[P_R]);
+        const bool in_old = inside(i, j, k, t + P_XOLD, t[P_R]);
+        if (in_new == in_old) continue;
+        const int c = i + G.nx * (j + G.ny * k);
+        const uint8_t f = D.flags[c];
+        if (in_new) {
+            if (f != SOL) push_event(D, D.lCov, C_NCOVER, c, P);
+        } else if (f == SOL && D.pid[c] == P) {
+            push_event(D, D.lUnc, C_NUNCOVER, c, P);
+        }
     }
 }
 
@@ -440,6 +508,7 @@ __global__ __launch_bounds__(256) void k_cov_reset(Geom G, Dev D) {
     int P = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (P >= D.np) return;
     const double *t = D.ptab + (long long)P * P_STRIDE;
+    if (!cov_claims(D, t)) return;
     int lo[3], hi[3];
     sphere_box(G, t + P_X, t[P_R], lo, hi);
     int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
