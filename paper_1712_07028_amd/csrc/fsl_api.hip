@@ -35,7 +35,7 @@ size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 struct Layout {
     size_t fA, fB, flags, cv, phiA, phiB, m, bub, pid, claim;
     size_t lF, lE0, lE, lNG, lNL, lCov, lUnc, uncRho, uncDec, merges, pairs;
-    size_t counters, ctl, ptab, pacc, pFT, pFTp, pFl, pmir, gStart, gCount, gIdx;
+    size_t counters, ctl, ptab, pacc, pFT, pFTp, pFl, pmir, gStart, gCount, gIdx, gBsum;
     size_t btab, bacc, broot, balive, rhog, stage;
     size_t win;  // differentiation window storage
     size_t total;
@@ -112,6 +112,7 @@ Layout layout_of(const fsl_config *c) {
     L.gStart = take((size_t)(L.ncellMax + 1) * 4);
     L.gCount = take((size_t)L.ncellMax * 4);
     L.gIdx = take((size_t)L.maxP * 4);
+    L.gBsum = take(1025 * 4);
     L.btab = take((size_t)L.maxB * B_STRIDE * 8);
     L.bacc = take((size_t)L.maxB * BACC_STRIDE * 8);
     L.broot = take((size_t)L.maxB * 4);
@@ -298,7 +299,14 @@ int enqueue_pair_forces(fsl_ctx *c) {
     // candidate pairs (positions at t): particle-particle links and lubrication
     hipLaunchKernelGGL(k_grid_zero, dim3(grid_for(c->ncell)), dim3(256), 0, c->st, D, c->ncell);
     hipLaunchKernelGGL(k_grid_count, dim3(grid_for(np)), dim3(256), 0, c->st, D, c->PG);
-    hipLaunchKernelGGL(k_grid_scan, dim3(1), dim3(1024), 0, c->st, D, c->ncell);
+    {
+        const int chunk = std::max(256, (c->ncell + 1023) / 1024 + 255) / 256 * 256;
+        const int nb = (c->ncell + chunk - 1) / chunk;
+        int *bsum = (int *)(c->ws + c->L.gBsum);
+        hipLaunchKernelGGL(k_gscan_sum, dim3(nb), dim3(256), 0, c->st, D, c->ncell, chunk, bsum);
+        hipLaunchKernelGGL(k_gscan_top, dim3(1), dim3(1024), 0, c->st, D, c->ncell, nb, bsum);
+        hipLaunchKernelGGL(k_gscan_apply, dim3(nb), dim3(256), 0, c->st, D, c->ncell, chunk, (const int *)bsum);
+    }
     hipLaunchKernelGGL(k_grid_fill, dim3(grid_for(np)), dim3(256), 0, c->st, D, c->PG);
     hipLaunchKernelGGL(k_pairs, dim3(grid_for(np)), dim3(256), 0, c->st, D, c->PG, c->L.pcap);
     hipLaunchKernelGGL(k_solid_pairs, dim3(grid_for(c->L.pcap, 4, 8192)), dim3(256), 0, c->st, c->G, D, c->L.pcap);

@@ -99,29 +99,61 @@ __global__ void k_grid_count(Dev D, PGrid PG) {
 }
 
 // exclusive scan of the grid counts by one block; gridCount becomes the fill cursor
-__global__ __launch_bounds__(1024) void k_grid_scan(Dev D, int ncell) {
-    __shared__ int part[1024];
-    const int T = blockDim.x, t = threadIdx.x;
-    int chunk = (ncell + T - 1) / T;
-    int lo = t * chunk, hi = min(ncell, lo + chunk);
+// exclusive prefix sum of the per-cell counts into gridStart (and the fill cursors
+// in gridCount), over many blocks: block sums, a scan of the block sums (at most
+// 1,024), then each block scans its own range from its offset
+__global__ __launch_bounds__(256) void k_gscan_sum(Dev D, int ncell, int chunk, int *bsum) {
+    __shared__ int red[256];
+    const int lo = blockIdx.x * chunk, hi = min(ncell, lo + chunk);
     int s = 0;
-    for (int i = lo; i < hi; ++i) s += D.gridCount[i];
-    part[t] = s;
+    for (int i = lo + (int)threadIdx.x; i < hi; i += 256) s += D.gridCount[i];
+    red[threadIdx.x] = s;
     __syncthreads();
-    for (int o = 1; o < T; o <<= 1) {
-        int v = t >= o ? part[t - o] : 0;
-        __syncthreads();
-        part[t] += v;
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    int run = part[t] - s;
-    for (int i = lo; i < hi; ++i) {
-        int cnt = D.gridCount[i];
-        D.gridStart[i] = run;
-        D.gridCount[i] = run;
-        run += cnt;
+    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+}
+__global__ __launch_bounds__(1024) void k_gscan_top(Dev D, int ncell, int nb, int *bsum) {
+    __shared__ int v[1024];
+    const int t = threadIdx.x;
+    const int x = t < nb ? bsum[t] : 0;
+    v[t] = x;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int y = t >= o ? v[t - o] : 0;
+        __syncthreads();
+        v[t] += y;
+        __syncthreads();
     }
-    if (t == T - 1) D.gridStart[ncell] = part[t];
+    if (t < nb) bsum[t] = v[t] - x;
+    if (t == 1023) D.gridStart[ncell] = v[t];
+}
+__global__ __launch_bounds__(256) void k_gscan_apply(Dev D, int ncell, int chunk, const int *bsum) {
+    __shared__ int v[256];
+    const int lo = blockIdx.x * chunk, hi = min(ncell, lo + chunk);
+    const int t = threadIdx.x;
+    int carry = bsum[blockIdx.x];
+    for (int base = lo; base < hi; base += 256) {
+        const int i = base + t;
+        const int x = i < hi ? D.gridCount[i] : 0;
+        v[t] = x;
+        __syncthreads();
+        for (int o = 1; o < 256; o <<= 1) {
+            const int y = t >= o ? v[t - o] : 0;
+            __syncthreads();
+            v[t] += y;
+            __syncthreads();
+        }
+        if (i < hi) {
+            const int st = carry + v[t] - x;
+            D.gridStart[i] = st;
+            D.gridCount[i] = st;
+        }
+        carry += v[255];
+        __syncthreads();
+    }
 }
 
 __global__ void k_grid_fill(Dev D, PGrid PG) {
