@@ -50,6 +50,7 @@ class OrcConfig(ctypes.Structure):
         ("max_bubbles", ctypes.c_int),
         ("wall_u", ((ctypes.c_double * 3) * 2) * 3),
         ("n_threads", ctypes.c_int),
+        ("sigma", ctypes.c_double),
     ]
 
 
@@ -89,6 +90,7 @@ def lib():
         L.orc_error.argtypes = [P]
         L.orc_num_cells.argtypes = [P]
         L.orc_window_J.argtypes = [P, ctypes.c_int, dp, dp]
+        L.orc_curvature.argtypes = [P, dp]
         L.orc_equilibrium.argtypes = [ctypes.c_double, dp, dp]
         L.orc_lubrication.argtypes = [dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, dp]
@@ -150,6 +152,7 @@ class Oracle:
                     for d in range(3):
                         cfg.wall_u[a][s][d] = float(wall_u[a][s][d])
         cfg.n_threads = int(n_threads)
+        cfg.sigma = float(getattr(w, "sigma", 0.0))
         self.w = w
         self.N = w.cells
         self.L = lib()
@@ -223,6 +226,12 @@ class Oracle:
         rc = self.L.orc_field_set(self.c, which, a.ctypes.data_as(ctypes.c_void_p))
         if rc:
             raise ValueError("orc_field_set failed")
+
+    def curvature(self):
+        k = np.zeros(self.N)
+        if self.L.orc_curvature(self.c, _dp(k)):
+            raise RuntimeError("orc_curvature failed")
+        return k
 
     def window_J(self, T, derivative=True):
         J = ctypes.c_double(0)

@@ -769,6 +769,94 @@ static void collide_cell(const orc_ctx *c, double fcell[19], double rho, const d
     for (int q = 0; q < 19; ++q) fcell[q] = fs[q];
 }
 
+/* ---- surface tension: interface curvature (end of Sec. 2.2) ---------------------- */
+/* The fill level as the curvature sees it: liquid 1, gas 0, interface its fill
+ * level, particle nodes 1 (reading of perfect wettability: the liquid spreads on the
+ * particles); a position beyond a wall takes the value of the nearest cell inside
+ * the box, so the normal has no component into the wall. */
+static int clamp_axis(int v, int n, int periodic)
+{
+    if (periodic) {
+        v %= n;
+        return v < 0 ? v + n : v;
+    }
+    return v < 0 ? 0 : (v >= n ? n - 1 : v);
+}
+
+static double phi_eff(const orc_ctx *c, int i, int j, int k)
+{
+    i = clamp_axis(i, c->nx, c->cfg.periodic[0]);
+    j = clamp_axis(j, c->ny, c->cfg.periodic[1]);
+    k = clamp_axis(k, c->nz, c->cfg.periodic[2]);
+    int x = i + c->nx * (j + c->ny * k);
+    switch (c->flag[x]) {
+    case GAS: return 0.0;
+    case IFC: return c->phi[x];
+    default: return 1.0; /* liquid and particle nodes */
+    }
+}
+
+/* weight of a cell displaced along the differentiation axis when its two other
+ * offsets are a and b (Parker and Youngs): 4, 2 or 1 for 0, 1 or 2 of them nonzero */
+static double py_weight(int a, int b)
+{
+    return (a == 0 && b == 0) ? 4.0 : ((a == 0 || b == 0) ? 2.0 : 1.0);
+}
+
+/* n = grad phi by the weighted central differences over the 3x3x3 block (the
+ * weights of one axis sum to 16 over a distance of 2, hence 1/32) */
+static void py_gradient(const orc_ctx *c, int i, int j, int k, double n[3])
+{
+    n[0] = n[1] = n[2] = 0.0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (!dx && !dy && !dz) continue;
+                double v = phi_eff(c, i + dx, j + dy, k + dz);
+                if (dx) n[0] += dx * py_weight(dy, dz) * v;
+                if (dy) n[1] += dy * py_weight(dx, dz) * v;
+                if (dz) n[2] += dz * py_weight(dx, dy) * v;
+            }
+    n[0] /= 32.0;
+    n[1] /= 32.0;
+    n[2] /= 32.0;
+}
+
+/* kappa = -(1/2) div(n/|n|) with the same weighted differences.  Reading: the paper
+ * writes kappa = -div(n/|n|) together with p_w = p_g + 2 sigma kappa; the Laplace
+ * jump 2 sigma / R of a spherical bubble needs kappa to be the mean curvature, half
+ * the divergence.  With n pointing into the liquid, a gas bubble has kappa = -1/R. */
+static double curvature_at(const orc_ctx *c, int i, int j, int k)
+{
+    double div = 0.0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (!dx && !dy && !dz) continue;
+                int a = clamp_axis(i + dx, c->nx, c->cfg.periodic[0]);
+                int b = clamp_axis(j + dy, c->ny, c->cfg.periodic[1]);
+                int d = clamp_axis(k + dz, c->nz, c->cfg.periodic[2]);
+                double n[3];
+                py_gradient(c, a, b, d, n);
+                double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+                if (nn == 0.0) continue;
+                if (dx) div += dx * py_weight(dy, dz) * n[0] / nn;
+                if (dy) div += dy * py_weight(dx, dz) * n[1] / nn;
+                if (dz) div += dz * py_weight(dx, dy) * n[2] / nn;
+            }
+    return -0.5 * div / 32.0;
+}
+
+int orc_curvature(orc_ctx *c, double *kappa)
+{
+    for (int x = 0; x < c->N; ++x) {
+        int i, j, k;
+        cell_ijk(c, x, &i, &j, &k);
+        kappa[x] = c->flag[x] == IFC ? curvature_at(c, i, j, k) : 0.0;
+    }
+    return 0;
+}
+
 static void stream_collide(orc_ctx *c)
 {
     const size_t N = (size_t)c->N;
@@ -789,6 +877,8 @@ static void stream_collide(orc_ctx *c)
                 double fc[19];
                 double rho_t = 0, u_t[3] = {0, 0, 0};
                 int have_t = 0;
+                double kappa = 0.0;
+                int have_kappa = 0;
                 fc[0] = c->f[x];
                 for (int q = 1; q < 19; ++q) {
                     int face = -1;
@@ -811,6 +901,14 @@ static void stream_collide(orc_ctx *c)
                     } else { /* gas: Eq. (fsk) with p_w = p_g of the neighbour's bubble */
                         if (fl == LIQ) nerr |= ERR_LG;
                         double rg = bubble_rho(c, c->bub[s]);
+                        /* Laplace pressure jump p_w = p_g + 2 sigma kappa, rho = 3 p */
+                        if (c->cfg.sigma != 0.0) {
+                            if (!have_kappa) {
+                                kappa = curvature_at(c, i, j, k);
+                                have_kappa = 1;
+                            }
+                            rg += 6.0 * c->cfg.sigma * kappa;
+                        }
                         fc[q] = -c->f[(size_t)OPP[q] * N + x] + 2.0 * eq_plus(q, rg, u_t);
                     }
                 }

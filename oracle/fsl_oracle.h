@@ -45,6 +45,7 @@ typedef struct {
     int max_bubbles;
     double wall_u[3][2][3];   /* velocity of each box face [axis][low/high][comp] */
     int n_threads;            /* OpenMP threads for the per-cell loops (0 = default) */
+    double sigma;             /* surface tension (0: no Laplace pressure jump)  */
 } orc_config;
 
 typedef struct {
@@ -83,6 +84,10 @@ int orc_num_cells(const orc_ctx *c);
  * forward-mode (tangent-linear) derivatives dJ/dtau and dJ/dg[3] in dJ[0..3].
  * Returns -1 when the state does not allow a frozen window. */
 int orc_window_J(orc_ctx *c, int T, double *J, double *dJ);
+
+/* Interface curvature of the current state (the kappa of the Laplace pressure
+ * jump): kappa[x] for every interface cell x, 0 elsewhere. */
+int orc_curvature(orc_ctx *c, double *kappa);
 
 /* exposed pieces of the method for unit checks */
 void orc_equilibrium(double rho, const double u[3], double e[19]);

@@ -52,6 +52,7 @@ class Workload:
     n_sub: int = 10
     storage: int = STORAGE_F32
     particles: Particles | None = None
+    sigma: float = 0.0  # surface tension (0: no Laplace pressure jump)
 
     @property
     def cells(self) -> int:
