@@ -82,6 +82,8 @@ typedef struct {
     int max_bubbles;            /* bubble table capacity, 0 = auto (64)               */
     int window_steps;           /* differentiation window length T (0 = no window)    */
     int window_every;           /* checkpoint interval k of the window                */
+    double sigma;               /* surface tension: the free-surface condition takes
+                                   p_w = p_g + 2 sigma kappa (0 = none)                */
 } fsl_config;
 
 typedef struct {
@@ -135,7 +137,9 @@ int fsl_bubbles_set(fsl_ctx *ctx, int n, const double *M, const int *root, const
 /* Field exchange for tests and checkpoints.  Host layouts:
  *   FSL_FIELD_FLAGS u8[N]; FSL_FIELD_MASS f64[N] (interface mass m);
  *   FSL_FIELD_PHI f64[N]; FSL_FIELD_F f64[19][N] post-collision populations,
- *   unshifted; FSL_FIELD_BUBBLE_ID i32[N]; FSL_FIELD_PID i32[N] (-1 = none).
+ *   unshifted; FSL_FIELD_BUBBLE_ID i32[N]; FSL_FIELD_PID i32[N] (-1 = none);
+ *   FSL_FIELD_KAPPA f64[N] (get only, sigma != 0): interface curvature used by the
+ *   last step, 0 outside interface cells.
  * fields_get synchronises; fields_set is stream-ordered and synchronises. */
 #define FSL_FIELD_FLAGS 0
 #define FSL_FIELD_MASS 1
@@ -143,6 +147,7 @@ int fsl_bubbles_set(fsl_ctx *ctx, int n, const double *M, const int *root, const
 #define FSL_FIELD_F 3
 #define FSL_FIELD_BUBBLE_ID 4
 #define FSL_FIELD_PID 5
+#define FSL_FIELD_KAPPA 6
 int fsl_fields_get(fsl_ctx *ctx, int field, void *host);
 int fsl_fields_set(fsl_ctx *ctx, int field, const void *host);
 

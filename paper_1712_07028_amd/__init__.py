@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfsl.so")
 
 FSL_OK, FSL_E_ARG, FSL_E_HIP, FSL_E_CAPACITY, FSL_E_NUMERIC, FSL_E_INVARIANT = 0, -1, -2, -3, -4, -5
-FIELD_FLAGS, FIELD_MASS, FIELD_PHI, FIELD_F, FIELD_BUBBLE_ID, FIELD_PID = range(6)
+FIELD_FLAGS, FIELD_MASS, FIELD_PHI, FIELD_F, FIELD_BUBBLE_ID, FIELD_PID, FIELD_KAPPA = range(7)
 GAS, LIQ, IFC, SOL = 0, 1, 2, 3
 
 EXPORTS = [
@@ -36,6 +36,7 @@ class FslConfig(ctypes.Structure):
         ("n_sub", ctypes.c_int), ("integrate", ctypes.c_int), ("storage", ctypes.c_int),
         ("eps_c", ctypes.c_double), ("list_capacity", ctypes.c_int), ("max_bubbles", ctypes.c_int),
         ("window_steps", ctypes.c_int), ("window_every", ctypes.c_int),
+        ("sigma", ctypes.c_double),
     ]
 
 
@@ -120,6 +121,7 @@ def make_config(w, max_particles=None, list_capacity=0, window=(0, 0)):
     c.list_capacity = int(list_capacity)
     c.max_bubbles = 0
     c.window_steps, c.window_every = int(window[0]), int(window[1])
+    c.sigma = float(getattr(w, "sigma", 0.0))
     return c
 
 
@@ -210,7 +212,8 @@ class Sim:
         return t.value, l.value
 
     _dtypes = {FIELD_FLAGS: (np.uint8, 1), FIELD_MASS: (np.float64, 1), FIELD_PHI: (np.float64, 1),
-               FIELD_F: (np.float64, 19), FIELD_BUBBLE_ID: (np.int32, 1), FIELD_PID: (np.int32, 1)}
+               FIELD_F: (np.float64, 19), FIELD_BUBBLE_ID: (np.int32, 1), FIELD_PID: (np.int32, 1),
+               FIELD_KAPPA: (np.float64, 1)}
 
     def get(self, which):
         dt, k = self._dtypes[which]

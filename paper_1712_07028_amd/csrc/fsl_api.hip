@@ -36,7 +36,7 @@ struct Layout {
     size_t fA, fB, flags, cv, phiA, phiB, m, bub, pid, claim;
     size_t lF, lE0, lE, lNG, lNL, lCov, lUnc, uncRho, uncDec, merges, pairs;
     size_t counters, ctl, ptab, pacc, pFT, pFTp, pFl, pmir, gStart, gCount, gIdx, gBsum;
-    size_t btab, bacc, broot, balive, rhog, stage;
+    size_t btab, bacc, broot, balive, rhog, kappa, stage;
     size_t win;  // differentiation window storage
     size_t total;
     long long S;
@@ -61,6 +61,7 @@ bool valid(const fsl_config *c) {
     if (c->max_bubbles < 0 || c->max_bubbles > 64) return false;
     if (c->n_gas_spheres + 1 > (c->max_bubbles ? c->max_bubbles : 64)) return false;
     if (c->window_steps < 0 || c->window_every < 0) return false;
+    if (!(c->sigma >= 0.0) || !(c->sigma < 1.0)) return false;
     return true;
 }
 
@@ -118,6 +119,7 @@ Layout layout_of(const fsl_config *c) {
     L.broot = take((size_t)L.maxB * 4);
     L.balive = take((size_t)L.maxB * 4);
     L.rhog = take((size_t)L.maxB * 4);
+    L.kappa = take(c->sigma != 0.0 ? (size_t)L.S * 4 : 0);
     L.stage = take(L.stageBytes);
     L.nTiles = ((c->n[0] + TX - 1) / TX) * ((c->n[1] + TY - 1) / TY) * c->n[2];
     L.winBytes = adjoint_window_bytes(c->window_steps, c->window_every, (size_t)L.S, c->max_particles,
@@ -225,6 +227,7 @@ void set_phys(fsl_ctx *c) {
     for (int a = 0; a < 3; ++a) c->Ph.g[a] = (float)f.g[a];
     c->Ph.eps = f.eps_c;
     c->Ph.scale = f.storage == FSL_STORE_F16S ? 1024.0f : 1.0f;
+    c->Ph.s6 = (float)(6.0 * f.sigma);
     c->Ph.inv = 1.0f / c->Ph.scale;
 }
 
@@ -355,6 +358,9 @@ int enqueue_steps(fsl_ctx *c, int n) {
     for (int s = 0; s < n; ++s) {
         Dev &D = c->D;
         hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, c->st, D);
+        if (D.kappa)  // curvature of the interface at t for the Laplace jump
+            hipLaunchKernelGGL(k_curvature, dim3(grid_for((c->G.N + 15) / 16, 256, 4096)), dim3(256), 0, c->st,
+                               c->G, D, (const double *)D.phi_cur);
         {
             ProfScope ps(c, 0);
             launch_stream_collide<ST>(c, D);
@@ -594,6 +600,7 @@ int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, 
     D.broot = (int *)(w + L.broot);
     D.balive = (int *)(w + L.balive);
     D.rhog = (float *)(w + L.rhog);
+    D.kappa = cfg->sigma != 0.0 ? (float *)(w + L.kappa) : nullptr;
     D.cap = L.cap;
     D.capEv = L.capEv;
     D.maxP = L.maxP;
@@ -792,6 +799,22 @@ int fsl_fields_get(fsl_ctx *c, int field, void *host) {
     case FSL_FIELD_MASS: HIPCHK(c, hipMemcpyAsync(host, D.m, N * 8, hipMemcpyDeviceToHost, c->st)); break;
     case FSL_FIELD_PHI: HIPCHK(c, hipMemcpyAsync(host, D.phi_cur, N * 8, hipMemcpyDeviceToHost, c->st)); break;
     case FSL_FIELD_PID: HIPCHK(c, hipMemcpyAsync(host, D.pid, N * 4, hipMemcpyDeviceToHost, c->st)); break;
+    case FSL_FIELD_KAPPA: {
+        if (!D.kappa) return fail(c, FSL_E_ARG, "fields_get: no surface tension configured");
+        double *stage = (double *)(c->ws + c->L.stage);
+        const long long chunk = (long long)(c->L.stageBytes / 8);
+        std::vector<uint8_t> fl(N);
+        HIPCHK(c, hipMemcpyAsync(fl.data(), D.flags, N, hipMemcpyDeviceToHost, c->st));
+        for (long long c0 = 0; c0 < N; c0 += chunk) {
+            const long long n = std::min(chunk, N - c0);
+            hipLaunchKernelGGL(k_f32_to_f64, dim3(grid_for(n)), dim3(256), 0, c->st, (const float *)D.kappa + c0, n, stage);
+            HIPCHK(c, hipMemcpyAsync((double *)host + c0, stage, n * 8, hipMemcpyDeviceToHost, c->st));
+            HIPCHK(c, hipStreamSynchronize(c->st));
+        }
+        for (long long i = 0; i < N; ++i)
+            if (fl[i] != IFC) ((double *)host)[i] = 0.0;
+        break;
+    }
     case FSL_FIELD_BUBBLE_ID:
         for (long long c0 = 0; c0 < N; c0 += chunk / 2) {
             long long n = std::min(chunk / 2, N - c0);

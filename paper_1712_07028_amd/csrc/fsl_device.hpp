@@ -111,6 +111,7 @@ struct Phys {
     float g[3];
     double eps;        // conversion threshold slack
     float scale, inv;  // 16-bit storage scale and its inverse
+    float s6;          // 6 sigma: density form of the Laplace jump 2 sigma kappa (rho = 3 p)
 };
 
 struct Dev {
@@ -133,6 +134,7 @@ struct Dev {
     double *btab, *bacc;
     int *broot, *balive;
     float *rhog;                     // FP32 gas density per bubble id (through root)
+    float *kappa;                    // interface curvature (null without surface tension)
     int cap;                         // conversion list capacity
     int capEv;                       // coverage event list capacity
     int maxP, maxB;

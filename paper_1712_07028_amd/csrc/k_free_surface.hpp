@@ -404,4 +404,76 @@ __global__ void k_bubble_finalize(Dev D, int init) {
         D.rhog[b] = (float)D.btab[bubble_root(D, b) * B_STRIDE + B_RHO];
 }
 
+
+// ---- surface tension: interface curvature (end of Sec. 2.2) ----------------------
+// The fill level as the curvature sees it: liquid and particle nodes 1 (perfect
+// wetting), gas 0, interface cells their fill level; a position beyond a wall takes
+// the nearest cell inside the box, a periodic one wraps.
+__device__ __forceinline__ int st_axis(int v, int n, int per) {
+    if (per) return v < 0 ? v + n : (v >= n ? v - n : v);
+    return v < 0 ? 0 : (v >= n ? n - 1 : v);
+}
+__device__ __forceinline__ double st_fill(const Geom &G, const Dev &D, const double *phi, int i, int j, int k) {
+    i = st_axis(i, G.nx, G.per[0]);
+    j = st_axis(j, G.ny, G.per[1]);
+    k = st_axis(k, G.nz, G.per[2]);
+    const long long c = i + (long long)G.nx * (j + (long long)G.ny * k);
+    const uint8_t f = D.flags[c];
+    return f == GAS ? 0.0 : (f == IFC ? phi[c] : 1.0);
+}
+// Parker-Youngs weighted central differences over the 3x3x3 block: a cell displaced
+// along the axis of the derivative counts 4, 2 or 1 for 0, 1 or 2 nonzero
+// transverse offsets (sum 16, distance 2)
+__device__ __forceinline__ double st_w(int a, int b) {
+    return (a == 0 && b == 0) ? 4.0 : ((a == 0 || b == 0) ? 2.0 : 1.0);
+}
+__device__ void st_normal(const Geom &G, const Dev &D, const double *phi, int i, int j, int k, double n[3]) {
+    n[0] = n[1] = n[2] = 0.0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (!dx && !dy && !dz) continue;
+                const double v = st_fill(G, D, phi, i + dx, j + dy, k + dz);
+                if (dx) n[0] += dx * st_w(dy, dz) * v;
+                if (dy) n[1] += dy * st_w(dx, dz) * v;
+                if (dz) n[2] += dz * st_w(dx, dy) * v;
+            }
+    n[0] *= 1.0 / 32.0;
+    n[1] *= 1.0 / 32.0;
+    n[2] *= 1.0 / 32.0;
+}
+// kappa = -(1/2) div(n/|n|) at every interface cell: the mean curvature, so that
+// 2 sigma kappa is the Laplace jump (a gas bubble of radius R has kappa = -1/R)
+__global__ __launch_bounds__(256) void k_curvature(Geom G, Dev D, const double *phi) {
+    const long long N = G.N;
+    const long long nchunk = (N + 15) / 16;
+    for (long long ch = blockIdx.x * (long long)blockDim.x + threadIdx.x; ch < nchunk;
+         ch += (long long)gridDim.x * blockDim.x) {
+        const long long c0 = ch * 16;
+        const uint4 f4 = *(const uint4 *)(D.flags + c0);
+        const uint32_t wds[4] = {f4.x, f4.y, f4.z, f4.w};
+        for (int e = 0; e < 16; ++e) {
+            const long long c = c0 + e;
+            if (c >= N) break;
+            if (((wds[e >> 2] >> (8 * (e & 3))) & 0xffu) != IFC) continue;
+            const int i = (int)(c % G.nx), j = (int)((c / G.nx) % G.ny), k = (int)(c / ((long long)G.nx * G.ny));
+            double div = 0.0;
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        if (!dx && !dy && !dz) continue;
+                        double n[3];
+                        st_normal(G, D, phi, st_axis(i + dx, G.nx, G.per[0]), st_axis(j + dy, G.ny, G.per[1]),
+                                  st_axis(k + dz, G.nz, G.per[2]), n);
+                        const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+                        if (nn == 0.0) continue;
+                        if (dx) div += dx * st_w(dy, dz) * n[0] / nn;
+                        if (dy) div += dy * st_w(dx, dz) * n[1] / nn;
+                        if (dz) div += dz * st_w(dx, dy) * n[2] / nn;
+                    }
+            D.kappa[c] = (float)(-0.5 * div / 32.0);
+        }
+    }
+}
+
 }  // namespace fsl

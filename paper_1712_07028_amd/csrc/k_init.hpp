@@ -169,4 +169,10 @@ __global__ void k_zero_counters(Dev D) {
     if (threadIdx.x < C_COUNT && blockIdx.x == 0) D.counters[threadIdx.x] = 0;
 }
 
+__global__ void k_f32_to_f64(const float *in, long long n, double *out) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        out[i] = (double)in[i];
+}
+
 }  // namespace fsl

@@ -257,7 +257,7 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
     const T *A = (const T *)D.fA;
     T *B = (T *)D.fB;
     const long long S = G.S;
-    const float inv = Ph.inv, sc = Ph.scale;
+    const float inv = Ph.inv;
     auto src = [&](int q) -> int {
         if (INTERIOR) return c - (cx(q) + cy(q) * nx + cz(q) * nxy);
         const int sx = wrapc(x - cx(q), nx), sy = wrapc(y - cy(q), ny), sz = wrapc(z - cz(q), nz);
@@ -386,7 +386,8 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
                 } else if ((gm >> q) & 1u) {
                     if (fl == LIQ) atomicOr(D.err, ERR_LG);
                     const int bid = D.bub[src(q)];
-                    const float rg = D.rhog[bid < D.maxB ? bid : 0];
+                    // Laplace jump p_w = p_g + 2 sigma kappa in density form
+                    const float rg = D.rhog[bid < D.maxB ? bid : 0] + (D.kappa ? Ph.s6 * D.kappa[c] : 0.f);
                     const float cu = cx(q) * ut0 + cy(q) * ut1 + cz(q) * ut2;
                     const float uu = ut0 * ut0 + ut1 * ut1 + ut2 * ut2;
                     // Eq. (fsk) in shifted form: -h*_qbar + 2 (e+_q(rho_g, u) - w_q)
