@@ -30,7 +30,7 @@ def near_threshold(phi_o, eps, tol=1e-9):
     return (np.abs(phi_o - (1 - eps)) < tol) | (np.abs(phi_o - eps) < tol)
 
 
-def compare_step(o, s, w, f_rtol=1e-6, m_tol=1e-6, ft_rtol=1e-5, allow_flag_mismatch=0):
+def compare_step(o, s, w, f_rtol=1e-6, m_tol=1e-6, ft_rtol=1e-5, allow_flag_mismatch=0, x_tol=1e-9):
     """Compare the states after one step; returns a dict of the measured errors."""
     fo, fg = o.get(O.FLAGS), s.get(fsl.FIELD_FLAGS)
     mism = fo != fg
@@ -57,7 +57,7 @@ def compare_step(o, s, w, f_rtol=1e-6, m_tol=1e-6, ft_rtol=1e-5, allow_flag_mism
         out["T_rel"] = float(np.abs(a["T"] - b["T"]).max() / tscale)
         out["x_abs"] = float(np.abs(a["x"] - b["x"]).max())
         assert out["F_rel"] < ft_rtol and out["T_rel"] < ft_rtol, out
-        assert out["x_abs"] < 1e-9, out
+        assert out["x_abs"] < x_tol, out
         assert (o.get(O.PID) == s.get(fsl.FIELD_PID)).all()
     bo, bg = o.bubbles(), s.bubbles()
     for x, y in zip(bo, bg):

@@ -122,6 +122,40 @@ def test_single_step_touching_spheres(integrate):
     say(compare_step(o, s, w))
 
 
+@pytest.mark.parametrize("speed", [0.3, 0.7])
+def test_single_step_fast_sphere_coverage(speed):
+    """A sphere that moves more than half a cell in one step takes every sphere
+    through the claim path of the coverage update; a slower one leaves the isolated
+    spheres on the path that derives cover and uncover events from the inside tests
+    alone.  Both must give the oracle's cell types and owners."""
+    x = np.array([[9.3, 10.2, 9.6], [19.4, 9.7, 10.3], [14.2, 19.1, 10.1]])
+    p = W.Particles(x=x, u=np.array([[speed, 0.05, 0.0], [-0.02, 0.01, 0.0], [0.0, -0.03, 0.01]]),
+                    omega=np.zeros((3, 3)), R=np.array([3.4, 3.1, 3.7]), rho_p=np.full(3, 2.5))
+    w = W.Workload(name="fast", n=(28, 28, 22), trt=True, tau=0.7, g=(0, 0, -1e-5), zs=18.0,
+                   steps=0, particles=p)
+    say("single step, sphere speed", speed)
+    o = O.Oracle(w)
+    s = fsl.Sim(w)
+    transfer(o, s, w)
+    o.step(1)
+    s.step(1)
+    s.sync()
+    # at these speeds (Mach 0.5 to 1.2) the moving-wall term 6 w rho c.u brings
+    # populations through zero, so they are compared against the largest population
+    # instead of their own size; the cell types and owners, which are what this case
+    # is about, must be identical
+    np.testing.assert_array_equal(o.get(O.FLAGS), s.get(fsl.FIELD_FLAGS))
+    np.testing.assert_array_equal(o.get(O.PID), s.get(fsl.FIELD_PID))
+    fo = o.get(O.FLAGS)
+    act = (fo == O.LIQ) | (fo == O.IFC)
+    Fo, Fg = o.get(O.F)[:, act], s.get(fsl.FIELD_F)[:, act]
+    err = np.abs(Fg - Fo).max() / np.abs(Fo).max()
+    a, b = o.particles_get(3), s.particles_get(3)
+    dx = np.abs(a["x"] - b["x"]).max()
+    say(f"  populations {err:.2e} of the largest, positions {dx:.2e}")
+    assert err < 1e-6 and dx < 1e-7
+
+
 def test_single_step_periodic_window():
     w = W.adjoint_window(n=32, n_particles=6)
     say("single step, periodic window")
