@@ -287,13 +287,25 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
         }
         const uint32_t miss = gm | sm | wm;
         const bool needOwn = (fl == IFC) || gm || sm;
-        float fo[Q], fi[Q];
-        // all independent loads first: own populations, pulled populations, ids
+        float fi[Q];
+        // density and velocity of this cell at t from its own populations, which are
+        // then reloaded where a rule needs one (a compiler barrier keeps the two
+        // groups of loads apart, so that both arrays are never live together)
+        float rho_t = 1.0f, ut0 = 0.f, ut1 = 0.f, ut2 = 0.f;
         if (needOwn) {
+            float fa[Q];
 #pragma unroll
-            for (int q = 0; q < Q; ++q) fo[q] = SS::ld(A + q * S + (unsigned)c, inv);
+            for (int q = 0; q < Q; ++q) fa[q] = SS::ld(A + q * S + (unsigned)c, inv);
+            const Moments Mt = cell_moments(fa);
+            rho_t = 1.0f + (float)Mt.drho;
+            const float ir = __builtin_amdgcn_rcpf(rho_t);
+            ut0 = Mt.j0 * ir - 0.5f * Ph.g[0];
+            ut1 = Mt.j1 * ir - 0.5f * Ph.g[1];
+            ut2 = Mt.j2 * ir - 0.5f * Ph.g[2];
         }
-        fi[0] = needOwn ? fo[0] : SS::ld(A + (unsigned)c, inv);
+        __asm__ volatile("" ::: "memory");
+        auto fo = [&](int q) { return SS::ld(A + q * S + (unsigned)c, inv); };
+        fi[0] = fo(0);
 #pragma unroll
         for (int q = 1; q < Q; ++q)
             if (!((miss >> q) & 1u)) fi[q] = SS::ld(A + q * S + (unsigned)src(q), inv);
@@ -310,22 +322,6 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
                 if ((sm >> q) & 1u) P0 = pq[q];
 #pragma unroll
             for (int q = 1; q < Q; ++q) same |= (uint32_t)(((sm >> q) & 1u) && pq[q] == P0) << q;
-        }
-        float rho_t = 1.0f, ut0 = 0.f, ut1 = 0.f, ut2 = 0.f;
-        if (needOwn) {
-            float d = 0.f, j0 = 0.f, j1 = 0.f, j2 = 0.f;
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                d += fo[q];
-                j0 += cx(q) * fo[q];
-                j1 += cy(q) * fo[q];
-                j2 += cz(q) * fo[q];
-            }
-            rho_t = 1.0f + d;
-            const float ir = 1.0f / rho_t;
-            ut0 = j0 * ir - 0.5f * Ph.g[0];
-            ut1 = j1 * ir - 0.5f * Ph.g[1];
-            ut2 = j2 * ir - 0.5f * Ph.g[2];
         }
         if (miss) {
             // rigid-body velocity of the lane's particle at the node: c_q . u_w at
@@ -352,12 +348,12 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
             for (int q = 1; q < Q; ++q) {
                 const int o = opp(q);
                 if (!INTERIOR && ((wm >> q) & 1u)) {
-                    fi[q] = needOwn ? fo[o] : SS::ld(A + o * S + c, inv);
+                    fi[q] = needOwn ? fo(o) : SS::ld(A + o * S + c, inv);
                 } else if ((sm >> q) & 1u) {
                     if (!((same >> q) & 1u) || acc.P != P0) {  // another particle (rare)
                         const int P = D.pid[src(q)];
                         if ((unsigned)P >= (unsigned)D.np) {  // inconsistent state: plain wall
-                            fi[q] = fo[o];
+                            fi[q] = fo(o);
                             atomicOr(D.err, ERR_LG);
                             continue;
                         }
@@ -369,9 +365,9 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
                         }
                     }
                     const float cu = cx(q) * un0 + cy(q) * un1 + cz(q) * un2;
-                    const float fin = fo[o] + 6.0f * wq(q) * rho_t * cu;  // Eq. (bbrule)
+                    const float fin = fo(o) + 6.0f * wq(q) * rho_t * cu;  // Eq. (bbrule)
                     fi[q] = fin;
-                    const float s2 = fo[o] + fin;
+                    const float s2 = fo(o) + fin;
                     acc.fs[0] -= cx(q) * s2;
                     acc.fs[1] -= cy(q) * s2;
                     acc.fs[2] -= cz(q) * s2;
@@ -382,7 +378,7 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
                     }
                     // the ledger pays the moving-wall mass of liquid cells only: an
                     // interface cell's mass is m, which the link does not change
-                    if (fl == LIQ) acc.dm += fin - fo[o];
+                    if (fl == LIQ) acc.dm += fin - fo(o);
                 } else if ((gm >> q) & 1u) {
                     if (fl == LIQ) atomicOr(D.err, ERR_LG);
                     const int bid = D.bub[src(q)];
@@ -391,7 +387,7 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
                     const float cu = cx(q) * ut0 + cy(q) * ut1 + cz(q) * ut2;
                     const float uu = ut0 * ut0 + ut1 * ut1 + ut2 * ut2;
                     // Eq. (fsk) in shifted form: -h*_qbar + 2 (e+_q(rho_g, u) - w_q)
-                    fi[q] = -fo[o] + 2.0f * wq(q) * ((rg - 1.0f) + rg * (4.5f * cu * cu - 1.5f * uu));
+                    fi[q] = -fo(o) + 2.0f * wq(q) * ((rg - 1.0f) + rg * (4.5f * cu * cu - 1.5f * uu));
                 }
             }
         }
@@ -406,7 +402,7 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
             for (int q = 1; q < Q; ++q) {
                 const uint8_t nf = tile[1 + cz(q)][ly + 1 + cy(q)][lx + 1 + cx(q)];
                 if (nf == LIQ || nf == IFC) {
-                    double d = (double)fi[opp(q)] - (double)fo[q];
+                    double d = (double)fi[opp(q)] - (double)fo(q);
                     if (nf == IFC) d *= 0.5 * (D.phi_cur[nbr(q)] + phx);
                     dm += d;
                 }
