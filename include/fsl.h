@@ -84,6 +84,10 @@ typedef struct {
     int window_every;           /* checkpoint interval k of the window                */
     double sigma;               /* surface tension: the free-surface condition takes
                                    p_w = p_g + 2 sigma kappa (0 = none)                */
+    double wall_u[3][2][3];     /* velocity of each non-periodic box face
+                                   [axis][low, high][component]; the half-way
+                                   bounce-back at a face takes the moving-wall form of
+                                   Eq. bbrule (all zero: resting walls)                */
 } fsl_config;
 
 typedef struct {

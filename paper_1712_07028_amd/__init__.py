@@ -37,6 +37,7 @@ class FslConfig(ctypes.Structure):
         ("eps_c", ctypes.c_double), ("list_capacity", ctypes.c_int), ("max_bubbles", ctypes.c_int),
         ("window_steps", ctypes.c_int), ("window_every", ctypes.c_int),
         ("sigma", ctypes.c_double),
+        ("wall_u", ((ctypes.c_double * 3) * 2) * 3),
     ]
 
 
@@ -96,7 +97,7 @@ def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def make_config(w, max_particles=None, list_capacity=0, window=(0, 0)):
+def make_config(w, max_particles=None, list_capacity=0, window=(0, 0), wall_u=None):
     """fsl_config from a workloads.Workload."""
     c = FslConfig()
     for a in range(3):
@@ -122,6 +123,11 @@ def make_config(w, max_particles=None, list_capacity=0, window=(0, 0)):
     c.max_bubbles = 0
     c.window_steps, c.window_every = int(window[0]), int(window[1])
     c.sigma = float(getattr(w, "sigma", 0.0))
+    if wall_u is not None:
+        for a in range(3):
+            for side in range(2):
+                for d in range(3):
+                    c.wall_u[a][side][d] = float(wall_u[a][side][d])
     return c
 
 
@@ -132,7 +138,7 @@ class Sim:
     stream.  ``w`` is a workloads.Workload."""
 
     def __init__(self, w, device="cuda", max_particles=None, list_capacity=0, window=(0, 0),
-                 set_particles=True):
+                 set_particles=True, wall_u=None):
         import torch
 
         self.L = load_library()
@@ -140,7 +146,7 @@ class Sim:
             raise FslError("no HIP device")
         self.w = w
         self.N = w.cells
-        self.cfg = make_config(w, max_particles, list_capacity, window)
+        self.cfg = make_config(w, max_particles, list_capacity, window, wall_u)
         nbytes = self.L.fsl_workspace_bytes(ctypes.byref(self.cfg))
         if nbytes == 0:
             raise FslError("invalid configuration")

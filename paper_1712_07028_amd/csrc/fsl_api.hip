@@ -36,7 +36,7 @@ struct Layout {
     size_t fA, fB, flags, cv, phiA, phiB, m, bub, pid, claim;
     size_t lF, lE0, lE, lNG, lNL, lCov, lUnc, uncRho, uncDec, merges, pairs;
     size_t counters, ctl, ptab, pacc, pFT, pFTp, pFl, pmir, gStart, gCount, gIdx, gBsum;
-    size_t btab, bacc, broot, balive, rhog, kappa, stage;
+    size_t btab, bacc, broot, balive, rhog, kappa, wallu, stage;
     size_t win;  // differentiation window storage
     size_t total;
     long long S;
@@ -120,6 +120,7 @@ Layout layout_of(const fsl_config *c) {
     L.balive = take((size_t)L.maxB * 4);
     L.rhog = take((size_t)L.maxB * 4);
     L.kappa = take(c->sigma != 0.0 ? (size_t)L.S * 4 : 0);
+    L.wallu = take(18 * 4);
     L.stage = take(L.stageBytes);
     L.nTiles = ((c->n[0] + TX - 1) / TX) * ((c->n[1] + TY - 1) / TY) * c->n[2];
     L.winBytes = adjoint_window_bytes(c->window_steps, c->window_every, (size_t)L.S, c->max_particles,
@@ -228,14 +229,23 @@ void set_phys(fsl_ctx *c) {
     c->Ph.eps = f.eps_c;
     c->Ph.scale = f.storage == FSL_STORE_F16S ? 1024.0f : 1.0f;
     c->Ph.s6 = (float)(6.0 * f.sigma);
+    c->Ph.moving_walls = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int sd = 0; sd < 2; ++sd)
+            for (int d = 0; d < 3; ++d)
+                if (f.boundary[a] != FSL_PERIODIC && f.wall_u[a][sd][d] != 0.0) c->Ph.moving_walls = 1;
     c->Ph.inv = 1.0f / c->Ph.scale;
 }
 
 // one lattice update of every cell
 template <int ST>
 void launch_stream_collide(fsl_ctx *c, const Dev &Dv) {
-    hipLaunchKernelGGL(k_stream_collide<ST>, dim3(c->nTiles), dim3(256), 0, c->st, c->G, c->Ph, Dv, c->tilesX,
-                       c->tilesY, c->nTiles);
+    if (c->Ph.moving_walls)
+        hipLaunchKernelGGL((k_stream_collide<ST, true>), dim3(c->nTiles), dim3(256), 0, c->st, c->G, c->Ph, Dv,
+                           c->tilesX, c->tilesY, c->nTiles);
+    else
+        hipLaunchKernelGGL((k_stream_collide<ST, false>), dim3(c->nTiles), dim3(256), 0, c->st, c->G, c->Ph, Dv,
+                           c->tilesX, c->tilesY, c->nTiles);
 }
 
 template <int ST> int enqueue_steps(fsl_ctx *c, int n);
@@ -601,6 +611,20 @@ int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, 
     D.balive = (int *)(w + L.balive);
     D.rhog = (float *)(w + L.rhog);
     D.kappa = cfg->sigma != 0.0 ? (float *)(w + L.kappa) : nullptr;
+    D.wallu = (float *)(w + L.wallu);
+    {
+        // face velocities (a periodic axis has no face)
+        float wv[18];
+        for (int a = 0; a < 3; ++a)
+            for (int sd = 0; sd < 2; ++sd)
+                for (int d = 0; d < 3; ++d)
+                    wv[(a * 2 + sd) * 3 + d] = cfg->boundary[a] == FSL_PERIODIC ? 0.0f : (float)cfg->wall_u[a][sd][d];
+        if (hipMemcpyAsync(D.wallu, wv, sizeof wv, hipMemcpyHostToDevice, c->st) != hipSuccess ||
+            hipStreamSynchronize(c->st) != hipSuccess) {
+            delete c;
+            return FSL_E_HIP;
+        }
+    }
     D.cap = L.cap;
     D.capEv = L.capEv;
     D.maxP = L.maxP;

@@ -112,6 +112,7 @@ struct Phys {
     double eps;        // conversion threshold slack
     float scale, inv;  // 16-bit storage scale and its inverse
     float s6;          // 6 sigma: density form of the Laplace jump 2 sigma kappa (rho = 3 p)
+    int moving_walls;  // a non-periodic face moves (velocities in Dev::wallu)
 };
 
 struct Dev {
@@ -135,6 +136,7 @@ struct Dev {
     int *broot, *balive;
     float *rhog;                     // FP32 gas density per bubble id (through root)
     float *kappa;                    // interface curvature (null without surface tension)
+    float *wallu;                    // face velocities [axis][low, high][component]
     int cap;                         // conversion list capacity
     int capEv;                       // coverage event list capacity
     int maxP, maxB;

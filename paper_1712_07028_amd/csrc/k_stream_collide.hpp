@@ -244,8 +244,9 @@ __device__ __forceinline__ bool collide_store(const Phys &Ph, const float (&fi)[
 // next to it, or an interface cell).  INTERIOR: the tile and its halo lie inside
 // the box, so a source is the cell index minus a uniform offset (no wrap, no wall).
 // Lanes without a cell (inb false) stay in the wave with nothing to do, because the
-// wave-level sums below read every lane.
-template <int ST, bool INTERIOR>
+// wave-level sums below read every lane.  MW: some box face moves (its wall links
+// then take the moving-wall form of Eq. bbrule).
+template <int ST, bool INTERIOR, bool MW>
 __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev &D,
                                         const uint8_t (&tile)[3][TY + 2][TX + 2], int lx, int ly,
                                         int x, int y, int z, bool inb) {
@@ -286,7 +287,7 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
             if (!INTERIOR) wm |= (uint32_t)(sf == WALL) << q;
         }
         const uint32_t miss = gm | sm | wm;
-        const bool needOwn = (fl == IFC) || gm || sm;
+        const bool needOwn = (fl == IFC) || gm || sm || (MW && wm);
         float fi[Q];
         // density and velocity of this cell at t from its own populations, which are
         // then reloaded where a rule needs one (a compiler barrier keeps the two
@@ -348,7 +349,19 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
             for (int q = 1; q < Q; ++q) {
                 const int o = opp(q);
                 if (!INTERIOR && ((wm >> q) & 1u)) {
-                    fi[q] = needOwn ? fo(o) : SS::ld(A + o * S + c, inv);
+                    // half-way bounce-back; a moving face adds 6 w_q rho_t (c_q . u_w)
+                    // (Eq. bbrule), the face being the first axis whose source lies
+                    // beyond a non-periodic face
+                    float add = 0.f;
+                    if (MW) {
+                        const int sx = x - cx(q), sy = y - cy(q), sz = z - cz(q);
+                        int a = 2, sd = sz < 0 ? 0 : 1;
+                        if (!G.per[0] && (sx < 0 || sx >= nx)) { a = 0; sd = sx < 0 ? 0 : 1; }
+                        else if (!G.per[1] && (sy < 0 || sy >= ny)) { a = 1; sd = sy < 0 ? 0 : 1; }
+                        const float *uw = D.wallu + (a * 2 + sd) * 3;
+                        add = 6.0f * wq(q) * rho_t * (cx(q) * uw[0] + cy(q) * uw[1] + cz(q) * uw[2]);
+                    }
+                    fi[q] = fo(o) + add;
                 } else if ((sm >> q) & 1u) {
                     if (!((same >> q) & 1u) || acc.P != P0) {  // another particle (rare)
                         const int P = D.pid[src(q)];
@@ -463,17 +476,17 @@ __device__ __forceinline__ void stage_flag_tile(const Geom &G, const uint8_t *fl
 
 // Per row of the staged tile (3 planes x 6 rows of 66 cells): w3 bit i is set when
 // one of the columns i, i+1, i+2 (the cells x-1, x, x+1 of lane i) is neither liquid
-// nor a wall, w1 bit i when column i+1 (the cell x of lane i) is neither.  One
-// ballot per row; the caller syncs before and after.
+// nor a resting wall, w1 bit i when column i+1 (the cell x of lane i) is neither.
+// One ballot per row; the caller syncs before and after.
 __device__ __forceinline__ void build_row_masks(const uint8_t (&tile)[3][TY + 2][TX + 2],
                                                 unsigned long long (&w3)[3 * (TY + 2)],
-                                                unsigned long long (&w1)[3 * (TY + 2)]) {
+                                                unsigned long long (&w1)[3 * (TY + 2)], bool wall_ok) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int r = wv; r < 3 * (TY + 2); r += 4) {
         const int lz = r / (TY + 2), ly = r - lz * (TY + 2);
         const uint8_t a = tile[lz][ly][lane], b = tile[lz][ly][TX + (lane & 1)];
-        const unsigned long long lo = __ballot(a != LIQ && a != WALL);
-        const unsigned long long hi = __ballot(lane < 2 && b != LIQ && b != WALL) & 3ull;
+        const unsigned long long lo = __ballot(a != LIQ && !(a == WALL && wall_ok));
+        const unsigned long long hi = __ballot(lane < 2 && b != LIQ && !(b == WALL && wall_ok)) & 3ull;
         const unsigned long long s1 = (lo >> 1) | (hi << 63);
         const unsigned long long s2 = (lo >> 2) | (hi << 62);
         if (lane == 0) {
@@ -524,7 +537,7 @@ __device__ __forceinline__ void lean_cell(const Geom &G, const Phys &Ph, const D
 // are compacted into a list and handled by as few waves as they fill, so that the
 // boundary work (bounce-back, free surface, mass exchange, forces, lists) is not
 // repeated by every wave that holds one such cell.
-template <int ST>
+template <int ST, bool MW>
 __global__ __launch_bounds__(256) void k_stream_collide(Geom G, Phys Ph, Dev D, int tilesX,
                                                         int tilesY, int nTiles) {
     __shared__ uint8_t tile[3][TY + 2][TX + 2];
@@ -541,7 +554,7 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geom G, Phys Ph, Dev D, 
                           z + 2 <= G.nz;
     stage_flag_tile(G, D.flags, tile, x0, y0, z, interior);
     __syncthreads();
-    build_row_masks(tile, w3, w1);
+    build_row_masks(tile, w3, w1, !MW);
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -579,8 +592,8 @@ __global__ __launch_bounds__(256) void k_stream_collide(Geom G, Phys Ph, Dev D, 
         const bool has = (int)threadIdx.x < total;
         const int e = has ? list[threadIdx.x] : 0;
         const int ex = e & (TX - 1), ey = e >> 6;
-        if (interior) sc_cell<ST, true>(G, Ph, D, tile, ex, ey, x0 + ex, y0 + ey, z, has);
-        else sc_cell<ST, false>(G, Ph, D, tile, ex, ey, x0 + ex, y0 + ey, z, has);
+        if (interior) sc_cell<ST, true, MW>(G, Ph, D, tile, ex, ey, x0 + ex, y0 + ey, z, has);
+        else sc_cell<ST, false, MW>(G, Ph, D, tile, ex, ey, x0 + ex, y0 + ey, z, has);
     }
 }
 

@@ -202,6 +202,44 @@ def test_poiseuille_gpu_closed_form():
     assert np.abs(u - ua).max() / ua.max() < 1e-4
 
 
+def test_couette_gpu_closed_form():
+    """Faces at y = -1/2 and n - 1/2 moving with -U and +U along x (Eq. bbrule at the
+    box walls): the steady profile is exactly linear, u_x = U (2 (y + 1/2)/n - 1)."""
+    n, U = 12, 0.01
+    w = W.Workload(name="couette", n=(1, n, 1), trt=True, tau=0.8, g=(0, 0, 0), zs=-1.0, steps=0,
+                   periodic=(1, 0, 1), integrate=False)
+    wall = [[[0, 0, 0], [0, 0, 0]], [[-U, 0, 0], [U, 0, 0]], [[0, 0, 0], [0, 0, 0]]]
+    s = fsl.Sim(w, wall_u=wall)
+    s.step(30000)
+    F = s.get(fsl.FIELD_F)[:, 0, :, 0]
+    C = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
+                  [1, 1, 0], [1, -1, 0], [-1, 1, 0], [-1, -1, 0], [1, 0, 1], [1, 0, -1], [-1, 0, 1],
+                  [-1, 0, -1], [0, 1, 1], [0, 1, -1], [0, -1, 1], [0, -1, -1]], float)
+    u = (C[:, 0] @ F) / F.sum(0)
+    y = np.arange(n)
+    ua = U * (2 * (y + 0.5) / n - 1)
+    say("  couette max |u - u_exact| / U", np.abs(u - ua).max() / U)
+    assert np.abs(u - ua).max() < 1e-5 * U
+
+
+def test_single_step_moving_walls():
+    """Every face of a closed box with a pool and a bubble moves with its own velocity:
+    the wall links (edges and corners included, where the first axis beyond the box
+    names the face) against the oracle."""
+    w = W.Workload(name="walls", n=(20, 14, 18), trt=True, tau=0.7, g=(0, 0, -1e-5), zs=13.0, steps=0,
+                   gas_spheres=[(10.0, 7.0, 6.0, 4.0, 1.0)])
+    wall = [[[0.0, 0.004, -0.002], [0.0, -0.003, 0.001]], [[0.005, 0.0, 0.002], [-0.004, 0.0, 0.003]],
+            [[0.003, -0.002, 0.0], [-0.001, 0.004, 0.0]]]
+    o = O.Oracle(w, wall_u=wall)
+    o.step(15)
+    s = fsl.Sim(w, wall_u=wall)
+    transfer(o, s, w)
+    o.step(1)
+    s.step(1)
+    s.sync()
+    say(compare_step(o, s, w))
+
+
 # ---------------------------------------------------------------------------------
 def rise_velocity(bubbles_t0, bubbles_t1, dt):
     return (bubbles_t1[1]["centroid"][2] - bubbles_t0[1]["centroid"][2]) / dt
