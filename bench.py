@@ -124,6 +124,29 @@ def adjoint_rate(fsl, W, torch, n, n_particles, T=200, k=20):
             "J": J, "dJ_dtau": dtau, "dJ_dg": [float(v) for v in dg]}
 
 
+def surface_tension_rate(fsl, torch, w, steps, sigma=0.005):
+    """The column with surface tension: whole step and the curvature pass."""
+    ws = w.replace(sigma=sigma)
+    s = fsl.Sim(ws)
+    s.step(5)
+    s.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # phase times from a separate bracketed run, so the events do not enter the rate
+    s.profile(True)
+    s.profile_get()
+    s.step(20)
+    prof = s.profile_get()
+    s.close()
+    torch.cuda.empty_cache()
+    return {"sigma": sigma, "steps": steps, "mlups": round(ws.cells * steps / dt / 1e6, 1),
+            "ms_per_step": round(dt / steps * 1e3, 4),
+            "curvature_ms": round(prof["curvature"][0] / max(prof["curvature"][1], 1), 4)}
+
+
 def cpu_baseline(w, steps):
     """The FP64 oracle on a bounded sample: the lowest 16 layers of the column."""
     import oracle
@@ -231,6 +254,7 @@ def main():
 
     forms = {}
     adjoint = {}
+    surface = None
     if not args.no_forms:
         from paper_1712_07028_amd import workloads as W
 
@@ -251,6 +275,8 @@ def main():
         for n, npart in ((64, 20), (256, 1280)):
             adjoint[f"{n}^3"] = adjoint_rate(fsl, W, torch, n, npart)
             log("adjoint", adjoint[f"{n}^3"])
+        surface = surface_tension_rate(fsl, torch, w.replace(storage=0), min(args.steps, 100))
+        log("surface tension", surface)
 
     if args.calibrate_copy_gib > 0:
         nbytes = int(args.calibrate_copy_gib * (1 << 30))
@@ -284,6 +310,8 @@ def main():
         out["forms"] = forms
     if adjoint:
         out["adjoint"] = adjoint
+    if surface:
+        out["surface_tension"] = surface
     print(json.dumps(out), flush=True)
 
 

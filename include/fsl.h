@@ -172,9 +172,10 @@ void fsl_destroy(fsl_ctx *ctx);
 /* Per-phase timing with HIP events on the library's stream.  When enabled, each
  * phase of a step is bracketed by events; fsl_profile_get writes, for phase k < n
  * (0 = fused stream-collide kernel, 1 = cell conversions, 2 = bubble volumes,
- * 3 = particle pairs and forces, 4 = particle substeps, 5 = coverage update), the
- * summed milliseconds and counts since the last call, resets them, synchronises
- * and returns the number of phases (6).  Off by default. */
+ * 3 = particle pairs and forces, 4 = particle substeps, 5 = coverage update,
+ * 6 = interface curvature, run only with sigma > 0), the summed milliseconds and
+ * counts since the last call, resets them, synchronises and returns the number of
+ * phases (7).  Off by default. */
 int fsl_profile_enable(fsl_ctx *ctx, int on);
 int fsl_profile_get(fsl_ctx *ctx, double *ms, long long *count, int n);
 

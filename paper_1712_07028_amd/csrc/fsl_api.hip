@@ -28,7 +28,7 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 constexpr int LIST_BLOCKS = 128;
-constexpr int NPROF = 6;
+constexpr int NPROF = 7;
 
 size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -368,9 +368,11 @@ int enqueue_steps(fsl_ctx *c, int n) {
     for (int s = 0; s < n; ++s) {
         Dev &D = c->D;
         hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, c->st, D);
-        if (D.kappa)  // curvature of the interface at t for the Laplace jump
-            hipLaunchKernelGGL(k_curvature, dim3(grid_for((c->G.N + 15) / 16, 256, 4096)), dim3(256), 0, c->st,
+        if (D.kappa) {  // curvature of the interface at t for the Laplace jump
+            ProfScope ps(c, 6);
+            hipLaunchKernelGGL(k_curvature, dim3(grid_for(c->G.N, 256, 8192)), dim3(256), 0, c->st,
                                c->G, D, (const double *)D.phi_cur);
+        }
         {
             ProfScope ps(c, 0);
             launch_stream_collide<ST>(c, D);

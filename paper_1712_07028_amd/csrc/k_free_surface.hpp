@@ -443,36 +443,30 @@ __device__ void st_normal(const Geom &G, const Dev &D, const double *phi, int i,
     n[2] *= 1.0 / 32.0;
 }
 // kappa = -(1/2) div(n/|n|) at every interface cell: the mean curvature, so that
-// 2 sigma kappa is the Laplace jump (a gas bubble of radius R has kappa = -1/R)
+// 2 sigma kappa is the Laplace jump (a gas bubble of radius R has kappa = -1/R).
+// One cell per thread: the interface cells of a surface lie side by side in memory,
+// so whole waves of them share the 5x5x5 stencil work and its cached loads.
 __global__ __launch_bounds__(256) void k_curvature(Geom G, Dev D, const double *phi) {
     const long long N = G.N;
-    const long long nchunk = (N + 15) / 16;
-    for (long long ch = blockIdx.x * (long long)blockDim.x + threadIdx.x; ch < nchunk;
-         ch += (long long)gridDim.x * blockDim.x) {
-        const long long c0 = ch * 16;
-        const uint4 f4 = *(const uint4 *)(D.flags + c0);
-        const uint32_t wds[4] = {f4.x, f4.y, f4.z, f4.w};
-        for (int e = 0; e < 16; ++e) {
-            const long long c = c0 + e;
-            if (c >= N) break;
-            if (((wds[e >> 2] >> (8 * (e & 3))) & 0xffu) != IFC) continue;
-            const int i = (int)(c % G.nx), j = (int)((c / G.nx) % G.ny), k = (int)(c / ((long long)G.nx * G.ny));
-            double div = 0.0;
-            for (int dz = -1; dz <= 1; ++dz)
-                for (int dy = -1; dy <= 1; ++dy)
-                    for (int dx = -1; dx <= 1; ++dx) {
-                        if (!dx && !dy && !dz) continue;
-                        double n[3];
-                        st_normal(G, D, phi, st_axis(i + dx, G.nx, G.per[0]), st_axis(j + dy, G.ny, G.per[1]),
-                                  st_axis(k + dz, G.nz, G.per[2]), n);
-                        const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-                        if (nn == 0.0) continue;
-                        if (dx) div += dx * st_w(dy, dz) * n[0] / nn;
-                        if (dy) div += dy * st_w(dx, dz) * n[1] / nn;
-                        if (dz) div += dz * st_w(dx, dy) * n[2] / nn;
-                    }
-            D.kappa[c] = (float)(-0.5 * div / 32.0);
-        }
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N;
+         c += (long long)gridDim.x * blockDim.x) {
+        if (D.flags[c] != IFC) continue;
+        const int i = (int)(c % G.nx), j = (int)((c / G.nx) % G.ny), k = (int)(c / ((long long)G.nx * G.ny));
+        double div = 0.0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    if (!dx && !dy && !dz) continue;
+                    double n[3];
+                    st_normal(G, D, phi, st_axis(i + dx, G.nx, G.per[0]), st_axis(j + dy, G.ny, G.per[1]),
+                              st_axis(k + dz, G.nz, G.per[2]), n);
+                    const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+                    if (nn == 0.0) continue;
+                    if (dx) div += dx * st_w(dy, dz) * n[0] / nn;
+                    if (dy) div += dy * st_w(dx, dz) * n[1] / nn;
+                    if (dz) div += dz * st_w(dx, dy) * n[2] / nn;
+                }
+        D.kappa[c] = (float)(-0.5 * div / 32.0);
     }
 }
 
