@@ -142,8 +142,8 @@ int fsl_bubbles_set(fsl_ctx *ctx, int n, const double *M, const int *root, const
  *   FSL_FIELD_FLAGS u8[N]; FSL_FIELD_MASS f64[N] (interface mass m);
  *   FSL_FIELD_PHI f64[N]; FSL_FIELD_F f64[19][N] post-collision populations,
  *   unshifted; FSL_FIELD_BUBBLE_ID i32[N]; FSL_FIELD_PID i32[N] (-1 = none);
- *   FSL_FIELD_KAPPA f64[N] (get only, sigma != 0): interface curvature used by the
- *   last step, 0 outside interface cells.
+ *   FSL_FIELD_KAPPA f64[N] (get only, sigma != 0): interface curvature of the
+ *   current state, the one the next step uses; 0 outside interface cells.
  * fields_get synchronises; fields_set is stream-ordered and synchronises. */
 #define FSL_FIELD_FLAGS 0
 #define FSL_FIELD_MASS 1

@@ -36,11 +36,12 @@ struct Layout {
     size_t fA, fB, flags, cv, phiA, phiB, m, bub, pid, claim;
     size_t lF, lE0, lE, lNG, lNL, lCov, lUnc, uncRho, uncDec, merges, pairs;
     size_t counters, ctl, ptab, pacc, pFT, pFTp, pFl, pmir, gStart, gCount, gIdx, gBsum;
-    size_t btab, bacc, broot, balive, rhog, kappa, wallu, stage;
+    size_t btab, bacc, broot, balive, rhog, kappa, ktf, klist, kcount, wallu, stage;
     size_t win;  // differentiation window storage
     size_t total;
     long long S;
     int cap, capEv, pcap, maxP, maxB, ncellMax, nTiles;
+    int ktx, kty, nKT;  // curvature tiles
     size_t stageBytes, winBytes;
 };
 
@@ -120,6 +121,12 @@ Layout layout_of(const fsl_config *c) {
     L.balive = take((size_t)L.maxB * 4);
     L.rhog = take((size_t)L.maxB * 4);
     L.kappa = take(c->sigma != 0.0 ? (size_t)L.S * 4 : 0);
+    L.ktx = (c->n[0] + KTX - 1) / KTX;
+    L.kty = (c->n[1] + KTY - 1) / KTY;
+    L.nKT = c->sigma != 0.0 ? L.ktx * L.kty * c->n[2] : 0;
+    L.ktf = take((size_t)L.nKT * 4);
+    L.klist = take((size_t)L.nKT * 4);
+    L.kcount = take(c->sigma != 0.0 ? 4 : 0);
     L.wallu = take(18 * 4);
     L.stage = take(L.stageBytes);
     L.nTiles = ((c->n[0] + TX - 1) / TX) * ((c->n[1] + TY - 1) / TY) * c->n[2];
@@ -363,6 +370,19 @@ int enqueue_coverage_step(fsl_ctx *c) {
     return FSL_OK;
 }
 
+// curvature at the interface cells of the current state (phi_cur, flags)
+void enqueue_curvature(fsl_ctx *c) {
+    const Layout &L = c->L;
+    char *w = c->ws;
+    unsigned *tf = (unsigned *)(w + L.ktf);
+    int *tl = (int *)(w + L.klist), *tc = (int *)(w + L.kcount);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->st, tc, 1LL, 0);
+    hipLaunchKernelGGL(k_curv_mark, dim3(grid_for((c->G.N + 15) / 16, 256, 8192)), dim3(256), 0, c->st, c->G,
+                       c->D, tf, tl, tc, L.ktx, L.kty);
+    hipLaunchKernelGGL(k_curv_tiles, dim3(std::min(L.nKT, 1024)), dim3(256), 0, c->st, c->G, c->D,
+                       (const double *)c->D.phi_cur, tf, (const int *)tl, (const int *)tc, L.ktx, L.kty);
+}
+
 template <int ST>
 int enqueue_steps(fsl_ctx *c, int n) {
     for (int s = 0; s < n; ++s) {
@@ -370,8 +390,7 @@ int enqueue_steps(fsl_ctx *c, int n) {
         hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, c->st, D);
         if (D.kappa) {  // curvature of the interface at t for the Laplace jump
             ProfScope ps(c, 6);
-            hipLaunchKernelGGL(k_curvature, dim3(grid_for(c->G.N, 256, 8192)), dim3(256), 0, c->st,
-                               c->G, D, (const double *)D.phi_cur);
+            enqueue_curvature(c);
         }
         {
             ProfScope ps(c, 0);
@@ -646,6 +665,9 @@ int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, 
     // control block, tables, accumulators
     hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, c->st, (double *)(w + L.ctl), 64LL, 0.0);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->st, D.counters, 64LL, 0);
+    if (L.nKT > 0)  // curvature tile flags: zero between steps
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(L.nKT)), dim3(256), 0, c->st, (int *)(w + L.ktf),
+                           (long long)L.nKT, 0);
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)L.maxP * ACC_STRIDE)), dim3(256), 0, c->st,
                        D.pacc, (long long)L.maxP * ACC_STRIDE, 0.0);
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)L.maxP * 6)), dim3(256), 0, c->st, D.pFT,
@@ -829,6 +851,8 @@ int fsl_fields_get(fsl_ctx *c, int field, void *host) {
         if (!D.kappa) return fail(c, FSL_E_ARG, "fields_get: no surface tension configured");
         double *stage = (double *)(c->ws + c->L.stage);
         const long long chunk = (long long)(c->L.stageBytes / 8);
+        enqueue_curvature(c);  // of the current state: the one the next step uses
+        LAUNCHCHK(c);
         std::vector<uint8_t> fl(N);
         HIPCHK(c, hipMemcpyAsync(fl.data(), D.flags, N, hipMemcpyDeviceToHost, c->st));
         for (long long c0 = 0; c0 < N; c0 += chunk) {

@@ -444,29 +444,120 @@ __device__ void st_normal(const Geom &G, const Dev &D, const double *phi, int i,
 }
 // kappa = -(1/2) div(n/|n|) at every interface cell: the mean curvature, so that
 // 2 sigma kappa is the Laplace jump (a gas bubble of radius R has kappa = -1/R).
-// One cell per thread: the interface cells of a surface lie side by side in memory,
-// so whole waves of them share the 5x5x5 stencil work and its cached loads.
-__global__ __launch_bounds__(256) void k_curvature(Geom G, Dev D, const double *phi) {
+//
+// Worked in tiles of KTX x KTY cells of one plane.  A marking pass lists the tiles
+// that hold interface cells; the curvature pass stages the fill levels of a listed
+// tile with a two-cell halo in LDS, forms the gradient of every cell of the tile
+// and a one-cell halo once, and takes the divergence at the tile's interface cells
+// (in the order of the per-cell definition, so the result is the same).
+constexpr int KTX = 32, KTY = 8;
+constexpr int KFX = KTX + 4, KFY = KTY + 4, KFZ = 5;  // staged fill levels
+constexpr int KNX = KTX + 2, KNY = KTY + 2, KNZ = 3;  // gradients and their norms
+
+// every tile with an interface cell enters the list once (tflag is zero for all
+// tiles on entry; the curvature pass clears the flags of the tiles it takes)
+__global__ __launch_bounds__(256) void k_curv_mark(Geom G, Dev D, unsigned *tflag, int *tlist, int *count,
+                                                   int ktx, int kty) {
     const long long N = G.N;
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N;
-         c += (long long)gridDim.x * blockDim.x) {
-        if (D.flags[c] != IFC) continue;
-        const int i = (int)(c % G.nx), j = (int)((c / G.nx) % G.ny), k = (int)(c / ((long long)G.nx * G.ny));
-        double div = 0.0;
-        for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                    if (!dx && !dy && !dz) continue;
-                    double n[3];
-                    st_normal(G, D, phi, st_axis(i + dx, G.nx, G.per[0]), st_axis(j + dy, G.ny, G.per[1]),
-                              st_axis(k + dz, G.nz, G.per[2]), n);
-                    const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-                    if (nn == 0.0) continue;
-                    if (dx) div += dx * st_w(dy, dz) * n[0] / nn;
-                    if (dy) div += dy * st_w(dx, dz) * n[1] / nn;
-                    if (dz) div += dz * st_w(dx, dy) * n[2] / nn;
-                }
-        D.kappa[c] = (float)(-0.5 * div / 32.0);
+    const long long nchunk = (N + 15) / 16;
+    for (long long ch = blockIdx.x * (long long)blockDim.x + threadIdx.x; ch < nchunk;
+         ch += (long long)gridDim.x * blockDim.x) {
+        const long long c0 = ch * 16;
+        const uint4 f4 = *(const uint4 *)(D.flags + c0);
+        const uint32_t wds[4] = {f4.x, f4.y, f4.z, f4.w};
+        int last = -1;
+        for (int e = 0; e < 16; ++e) {
+            const long long c = c0 + e;
+            if (c >= N) break;
+            if (((wds[e >> 2] >> (8 * (e & 3))) & 0xffu) != IFC) continue;
+            const int i = (int)(c % G.nx), j = (int)((c / G.nx) % G.ny), k = (int)(c / ((long long)G.nx * G.ny));
+            const int t = (k * kty + j / KTY) * ktx + i / KTX;
+            if (t == last) continue;
+            last = t;
+            if (atomicExch(tflag + t, 1u) == 0u) tlist[atomicAdd(count, 1)] = t;
+        }
+    }
+}
+
+// a staged coordinate: wrapped on a periodic axis (the halo may reach past the box
+// more than once in a short axis), the nearest cell inside beyond a wall
+__device__ __forceinline__ int kc_wrap(int v, int n, int per) {
+    if (per) {
+        v %= n;
+        return v < 0 ? v + n : v;
+    }
+    return v < 0 ? 0 : (v >= n ? n - 1 : v);
+}
+
+// LDS index of the point whose gradient stands for position v of the one-cell halo:
+// beyond a wall the nearest cell inside (the per-cell definition clamps the
+// position first); on a periodic axis v itself, since the staged fill levels are
+// already wrapped
+__device__ __forceinline__ int kc_pos(int v, int n, int per, int origin) {
+    if (!per) v = v < 0 ? 0 : (v >= n ? n - 1 : v);
+    return v - origin;
+}
+
+__global__ __launch_bounds__(256) void k_curv_tiles(Geom G, Dev D, const double *phi, unsigned *tflag,
+                                                    const int *tlist, const int *count, int ktx, int kty) {
+    __shared__ double F[KFZ][KFY][KFX];
+    __shared__ double NG[4][KNZ][KNY][KNX];  // gradient components and norm
+    const int nt = *count;
+    for (int it = blockIdx.x; it < nt; it += gridDim.x) {
+        const int t = tlist[it];
+        const int x0 = (t % ktx) * KTX, y0 = ((t / ktx) % kty) * KTY, z = t / (ktx * kty);
+        for (int e = threadIdx.x; e < KFX * KFY * KFZ; e += blockDim.x) {
+            const int ex = e % KFX, ey = (e / KFX) % KFY, ez = e / (KFX * KFY);
+            F[ez][ey][ex] = st_fill(G, D, phi, kc_wrap(x0 - 2 + ex, G.nx, G.per[0]),
+                                    kc_wrap(y0 - 2 + ey, G.ny, G.per[1]), kc_wrap(z - 2 + ez, G.nz, G.per[2]));
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < KNX * KNY * KNZ; e += blockDim.x) {
+            const int ex = e % KNX, ey = (e / KNX) % KNY, ez = e / (KNX * KNY);
+            const int px = kc_pos(x0 - 1 + ex, G.nx, G.per[0], x0 - 2);
+            const int py = kc_pos(y0 - 1 + ey, G.ny, G.per[1], y0 - 2);
+            const int pz = kc_pos(z - 1 + ez, G.nz, G.per[2], z - 2);
+            double n0 = 0.0, n1 = 0.0, n2 = 0.0;
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        if (!dx && !dy && !dz) continue;
+                        const double v = F[pz + dz][py + dy][px + dx];
+                        if (dx) n0 += dx * st_w(dy, dz) * v;
+                        if (dy) n1 += dy * st_w(dx, dz) * v;
+                        if (dz) n2 += dz * st_w(dx, dy) * v;
+                    }
+            n0 *= 1.0 / 32.0;
+            n1 *= 1.0 / 32.0;
+            n2 *= 1.0 / 32.0;
+            NG[0][ez][ey][ex] = n0;
+            NG[1][ez][ey][ex] = n1;
+            NG[2][ez][ey][ex] = n2;
+            NG[3][ez][ey][ex] = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < KTX * KTY; e += blockDim.x) {
+            const int lx = e % KTX, ly = e / KTX;
+            const int x = x0 + lx, y = y0 + ly;
+            if (x >= G.nx || y >= G.ny) continue;
+            const long long c = x + (long long)G.nx * (y + (long long)G.ny * z);
+            if (D.flags[c] != IFC) continue;
+            double div = 0.0;
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        if (!dx && !dy && !dz) continue;
+                        const int a = 1 + lx + dx, b = 1 + ly + dy, d = 1 + dz;
+                        const double nn = NG[3][d][b][a];
+                        if (nn == 0.0) continue;
+                        if (dx) div += dx * st_w(dy, dz) * NG[0][d][b][a] / nn;
+                        if (dy) div += dy * st_w(dx, dz) * NG[1][d][b][a] / nn;
+                        if (dz) div += dz * st_w(dx, dy) * NG[2][d][b][a] / nn;
+                    }
+            D.kappa[c] = (float)(-0.5 * div / 32.0);
+        }
+        if (threadIdx.x == 0) tflag[t] = 0u;
+        __syncthreads();
     }
 }
 
