@@ -91,6 +91,7 @@ def lib():
         L.orc_num_cells.argtypes = [P]
         L.orc_window_J.argtypes = [P, ctypes.c_int, dp, dp]
         L.orc_curvature.argtypes = [P, dp]
+        L.orc_split.argtypes = [P]
         L.orc_equilibrium.argtypes = [ctypes.c_double, dp, dp]
         L.orc_lubrication.argtypes = [dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, dp]
@@ -125,7 +126,7 @@ def lambda_minus(tau, magic=3.0 / 16.0, trt=True):
 class Oracle:
     """One FP64 simulation state.  ``w`` is a workloads.Workload."""
 
-    def __init__(self, w, wall_u=None, n_threads=0, max_particles=None):
+    def __init__(self, w, wall_u=None, n_threads=0, max_particles=None, max_bubbles=64):
         cfg = OrcConfig()
         for a in range(3):
             cfg.n[a] = int(w.n[a])
@@ -145,7 +146,7 @@ class Oracle:
         cfg.n_sub = int(w.n_sub)
         npart = w.particles.n if w.particles is not None else 0
         cfg.max_particles = int(max_particles if max_particles is not None else max(npart, 1))
-        cfg.max_bubbles = 64
+        cfg.max_bubbles = int(max_bubbles)
         if wall_u is not None:
             for a in range(3):
                 for s in range(2):
@@ -232,6 +233,21 @@ class Oracle:
         if self.L.orc_curvature(self.c, _dp(k)):
             raise RuntimeError("orc_curvature failed")
         return k
+
+    def bubbles_set(self, M, root, alive):
+        M = np.ascontiguousarray(M, dtype=np.float64)
+        r = np.ascontiguousarray(root, dtype=np.int32)
+        a = np.ascontiguousarray(alive, dtype=np.int32)
+        ip = ctypes.POINTER(ctypes.c_int)
+        if self.L.orc_bubbles_set(self.c, int(M.size), _dp(M), r.ctypes.data_as(ip), a.ctypes.data_as(ip)):
+            raise ValueError("orc_bubbles_set failed")
+
+    def split(self):
+        """Bubble splitting of the current state: the number of new bubbles."""
+        n = self.L.orc_split(self.c)
+        if n < 0:
+            raise RuntimeError("orc_split: bubble table full")
+        return n
 
     def window_J(self, T, derivative=True):
         J = ctypes.c_double(0)

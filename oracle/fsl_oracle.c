@@ -22,7 +22,7 @@
  *   6. particle update: lubrication correction Eq. (lubrication) and up to ten
  *      substeps per lattice step (Sec. 2.3), then the obstacle-coverage update;
  *   7. bubble model (end of Sec. 2.2): per-bubble volume, constant gas mass,
- *      gas density = mass / volume.
+ *      gas density = mass / volume; a bubble whose gas falls apart splits.
  * Where the paper is silent the reading used is stated at the place it is used.
  * Parity-pinned parts are listed in the tests; the conversion rules (reading
  * of the fill thresholds, conflict rule, G->I initial state, excess split), the
@@ -231,6 +231,7 @@ void orc_destroy(orc_ctx *c)
 }
 
 static void bubbles_recompute(orc_ctx *c);
+static int split_bubbles(orc_ctx *c);
 
 /* Initial state (reading of the configs; the same specification is implemented
  * independently by the library):
@@ -373,6 +374,7 @@ orc_ctx *orc_create(const orc_config *cfg)
         c->brho[b] = rg;
     }
     bubbles_recompute(c);
+    split_bubbles(c);
     return c;
 }
 
@@ -414,6 +416,122 @@ static void bubbles_recompute(orc_ctx *c)
             c->err |= ERR_VOL;
         }
     }
+}
+
+/* ---- bubble splitting (bubble model, end of Sec. 2.2) ----------------------------
+ * A bubble is a connected region of gas.  Readings: two gas cells are connected when
+ * they are D3Q19 neighbours (the neighbourhood of the merge rule) and belong to the
+ * same root bubble.  When the gas cells of a root fall into several components, the
+ * component holding the lowest cell index keeps the bubble; every other component,
+ * in order of its lowest cell index, becomes a bubble with the next unused id.  An
+ * interface cell of the root goes with the component of its gas neighbours of that
+ * root (the one with the lowest cell index if they differ); one without such a
+ * neighbour stays with the bubble.  The gas mass is shared in proportion to the
+ * volumes of the parts (gas cells plus 1 - phi of their interface cells), so every
+ * part starts at the density of the bubble it came from.  The volumes of the
+ * bubble table must be those of the current state.  Returns the number of new
+ * bubbles; a full table sets ERR_CAP and stops. */
+static int split_bubbles(orc_ctx *c)
+{
+    const int N = c->N, MB = c->cfg.max_bubbles;
+    int *lab = (int *)xcalloc((size_t)N, sizeof(int));   /* lowest cell index of the component */
+    int *nid = (int *)xcalloc((size_t)N, sizeof(int));   /* per component (at that cell): new id or -1 */
+    int *stack = (int *)xcalloc((size_t)N, sizeof(int));
+    int *newb = (int *)xcalloc((size_t)N, sizeof(int));  /* per cell: new id or -1 */
+    int *parent = (int *)xcalloc((size_t)MB, sizeof(int));
+    double *Vn = (double *)xcalloc((size_t)MB, sizeof(double));
+    unsigned char *seen = (unsigned char *)xcalloc((size_t)MB, 1);
+    int created = 0;
+    for (int x = 0; x < N; ++x) lab[x] = nid[x] = newb[x] = -1;
+    /* components: flood fill from the lowest unlabelled gas cell */
+    for (int x = 0; x < N; ++x) {
+        if (c->flag[x] != GAS || lab[x] >= 0) continue;
+        const int r = find_root(c, c->bub[x]);
+        int top = 0;
+        stack[top++] = x;
+        lab[x] = x;
+        while (top) {
+            int y = stack[--top], i, j, k;
+            cell_ijk(c, y, &i, &j, &k);
+            for (int q = 1; q < 19; ++q) {
+                int n = nbr(c, i, j, k, CX[q], CY[q], CZ[q], NULL);
+                if (n < 0 || c->flag[n] != GAS || lab[n] >= 0 || find_root(c, c->bub[n]) != r) continue;
+                lab[n] = x;
+                stack[top++] = n;
+            }
+        }
+    }
+    /* the first component of each root keeps it; the others take new ids */
+    for (int x = 0; x < N; ++x) {
+        if (lab[x] != x) continue;
+        const int r = find_root(c, c->bub[x]);
+        if (!seen[r]) {
+            seen[r] = 1;
+            continue;
+        }
+        if (c->nb >= MB) {
+            c->err |= ERR_CAP;
+            break;
+        }
+        nid[x] = c->nb++;
+        parent[nid[x]] = r;
+        ++created;
+    }
+    if (created) {
+        /* interface cells first: they look at the ids of their gas neighbours */
+        for (int x = 0; x < N; ++x) {
+            if (c->flag[x] != IFC) continue;
+            const int r = find_root(c, c->bub[x]);
+            int best = -1, i, j, k;
+            cell_ijk(c, x, &i, &j, &k);
+            for (int q = 1; q < 19; ++q) {
+                int n = nbr(c, i, j, k, CX[q], CY[q], CZ[q], NULL);
+                if (n < 0 || c->flag[n] != GAS || find_root(c, c->bub[n]) != r) continue;
+                if (best < 0 || lab[n] < best) best = lab[n];
+            }
+            if (best >= 0 && nid[best] >= 0) {
+                newb[x] = nid[best];
+                Vn[nid[best]] += 1.0 - c->phi[x];
+            }
+        }
+        for (int x = 0; x < N; ++x) {
+            if (c->flag[x] != GAS || nid[lab[x]] < 0) continue;
+            newb[x] = nid[lab[x]];
+            Vn[newb[x]] += 1.0;
+        }
+        for (int x = 0; x < N; ++x)
+            if (newb[x] >= 0) c->bub[x] = newb[x];
+        /* masses: each new part at the density of its bubble */
+        for (int r = 0; r < MB; ++r) {
+            if (!seen[r]) continue;
+            const double Mr = c->bM[r];
+            double taken = 0.0;
+            for (int b = c->nb - created; b < c->nb; ++b) {
+                if (parent[b] != r) continue;
+                c->bM[b] = Mr * Vn[b] / c->bV[r];
+                c->bV0[b] = Vn[b];
+                c->broot[b] = b;
+                c->balive[b] = 1;
+                taken += c->bM[b];
+            }
+            c->bM[r] = Mr - taken;
+        }
+        bubbles_recompute(c);
+    }
+    free(lab);
+    free(nid);
+    free(stack);
+    free(newb);
+    free(parent);
+    free(Vn);
+    free(seen);
+    return created;
+}
+
+int orc_split(orc_ctx *c)
+{
+    int n = split_bubbles(c);
+    return (c->err & ERR_CAP) ? -1 : n;
 }
 
 /* ---- coverage update (Sec. 2.3: nodes inside a particle are obstacle nodes) ----
@@ -575,6 +693,7 @@ int orc_particles_set(orc_ctx *c, int n, const double *x, const double *u,
     }
     coverage_update(c);
     bubbles_recompute(c);
+    split_bubbles(c);
     return 0;
 }
 
@@ -1110,6 +1229,7 @@ int orc_step(orc_ctx *c, int nsteps)
             coverage_update(c);
         }
         bubbles_recompute(c);
+        split_bubbles(c);
         check_invariant(c);
     }
     return c->err ? -1 : 0;
@@ -1169,7 +1289,8 @@ int orc_bubbles_set(orc_ctx *c, int n, const double *M, const int *root, const i
         c->balive[b] = alive[b];
     }
     bubbles_recompute(c);
-    return 0;
+    split_bubbles(c);
+    return (c->err & ERR_CAP) ? -1 : 0;
 }
 
 int orc_field_get(orc_ctx *c, int which, void *out)

@@ -88,6 +88,9 @@ int orc_window_J(orc_ctx *c, int T, double *J, double *dJ);
 /* Interface curvature of the current state (the kappa of the Laplace pressure
  * jump): kappa[x] for every interface cell x, 0 elsewhere. */
 int orc_curvature(orc_ctx *c, double *kappa);
+/* Bubble splitting of the current state (also part of every step and of particles_set,
+ * bubbles_set and create): returns the number of new bubbles, -1 with a full table. */
+int orc_split(orc_ctx *c);
 
 /* exposed pieces of the method for unit checks */
 void orc_equilibrium(double rho, const double u[3], double e[19]);

@@ -97,7 +97,7 @@ def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def make_config(w, max_particles=None, list_capacity=0, window=(0, 0), wall_u=None):
+def make_config(w, max_particles=None, list_capacity=0, window=(0, 0), wall_u=None, max_bubbles=0):
     """fsl_config from a workloads.Workload."""
     c = FslConfig()
     for a in range(3):
@@ -120,7 +120,7 @@ def make_config(w, max_particles=None, list_capacity=0, window=(0, 0), wall_u=No
     c.storage = int(w.storage)
     c.eps_c = float(w.eps_c)
     c.list_capacity = int(list_capacity)
-    c.max_bubbles = 0
+    c.max_bubbles = int(max_bubbles)
     c.window_steps, c.window_every = int(window[0]), int(window[1])
     c.sigma = float(getattr(w, "sigma", 0.0))
     if wall_u is not None:
@@ -138,7 +138,7 @@ class Sim:
     stream.  ``w`` is a workloads.Workload."""
 
     def __init__(self, w, device="cuda", max_particles=None, list_capacity=0, window=(0, 0),
-                 set_particles=True, wall_u=None):
+                 set_particles=True, wall_u=None, max_bubbles=0):
         import torch
 
         self.L = load_library()
@@ -146,7 +146,7 @@ class Sim:
             raise FslError("no HIP device")
         self.w = w
         self.N = w.cells
-        self.cfg = make_config(w, max_particles, list_capacity, window, wall_u)
+        self.cfg = make_config(w, max_particles, list_capacity, window, wall_u, max_bubbles)
         nbytes = self.L.fsl_workspace_bytes(ctypes.byref(self.cfg))
         if nbytes == 0:
             raise FslError("invalid configuration")

@@ -1,0 +1,223 @@
+"""Pins of the oracle's bubble splitting (bubble model, end of Sec. 2.2: a bubble is
+a connected region of gas, with a constant gas mass).
+
+The components are checked against scipy.ndimage.label with the D3Q19
+neighbourhood as its structuring element: a library routine independent of the
+oracle's flood fill.  The readings pinned here: face and edge neighbours connect,
+corner neighbours do not; the component with the lowest cell index keeps the id,
+the others take new ids in order of their lowest cell index; interface cells go
+with the component of their gas neighbours (the lowest when they differ); the gas
+mass is shared in proportion to the volumes of the parts, so each part keeps the
+density of the bubble, and the total gas mass is unchanged.
+"""
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle as O
+from paper_1712_07028_amd import workloads as W
+
+D3Q19 = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
+         if 0 < abs(dx) + abs(dy) + abs(dz) <= 2]
+STRUCT = np.zeros((3, 3, 3), bool)
+STRUCT[1, 1, 1] = True
+for _d in D3Q19:
+    STRUCT[_d[2] + 1, _d[1] + 1, _d[0] + 1] = True
+WQ = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+def ball(n, c, r):
+    z, y, x = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    return (x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2 <= r * r
+
+
+def interface_of(gas):
+    """Non-gas cells with a D3Q19 gas neighbour (no wrap: the gas stays inside)."""
+    return ndimage.binary_dilation(gas, structure=STRUCT) & ~gas
+
+
+def hand_state(n, gas, rho_g=1.0, phi_ifc=None, max_bubbles=64, particles=None, g=(0, 0, 0)):
+    """A liquid box at rest with the given gas cells (bubble id 1) and their closing
+    interface layer; returns the oracle and the arrays it was given (z, y, x)."""
+    w = W.Workload(name="split", n=n, trt=False, tau=0.8, g=g, zs=-1.0, steps=0,
+                   particles=particles, integrate=particles is not None)
+    o = O.Oracle(w, max_bubbles=max_bubbles)
+    ifc = interface_of(gas)
+    fl = np.full(gas.shape, O.LIQ, np.uint8)
+    fl[gas] = O.GAS
+    fl[ifc] = O.IFC
+    rng = np.random.Generator(np.random.PCG64(3))
+    phi = np.where(gas, 0.0, 1.0)
+    phi[ifc] = rng.uniform(0.2, 0.8, size=int(ifc.sum())) if phi_ifc is None else phi_ifc
+    bub = np.where(gas | ifc, 1, 0).astype(np.int32)
+    f = np.broadcast_to(WQ[:, None, None, None], (19,) + gas.shape).copy()
+    o.set(O.FLAGS, fl)
+    o.set(O.PHI, phi)
+    o.set(O.MASS, np.where(ifc, phi, 0.0))
+    o.set(O.BUBBLE_ID, bub)
+    o.set(O.F, f)
+    o.set(O.PID, np.full(gas.shape, -1, np.int32))
+    V = gas.sum() + (1.0 - phi[ifc]).sum()
+    return o, dict(flags=fl, phi=phi, gas=gas, ifc=ifc, M=rho_g * V, V=V)
+
+
+def expected_split(st):
+    """The split as the readings define it, from scipy's labels."""
+    gas, ifc, phi = st["gas"], st["ifc"], st["phi"]
+    lab, ncomp = ndimage.label(gas, structure=STRUCT)
+    flat = lab.ravel()
+    first = np.array([np.flatnonzero(flat == k + 1).min() for k in range(ncomp)])
+    order = np.argsort(first)                       # components by lowest cell index
+    cid = np.empty(ncomp, int)                      # component -> bubble id
+    cid[order] = [1] + list(range(2, ncomp + 1))
+    ids = np.zeros(gas.size, int)
+    ids[flat > 0] = cid[flat[flat > 0] - 1]
+    vol = np.zeros(ncomp + 2)
+    np.add.at(vol, ids[flat > 0], 1.0)
+    nz, ny, nx = gas.shape
+    for c in np.flatnonzero(ifc.ravel()):
+        x, y, z = c % nx, (c // nx) % ny, c // (nx * ny)
+        best = None
+        for dx, dy, dz in D3Q19:
+            i, j, k = x + dx, y + dy, z + dz
+            if 0 <= i < nx and 0 <= j < ny and 0 <= k < nz and lab[k, j, i]:
+                comp = lab[k, j, i] - 1
+                if best is None or first[comp] < first[best]:
+                    best = comp
+        ids[c] = 1 if best is None else cid[best]
+        vol[ids[c]] += 1.0 - phi.ravel()[c]
+    return ids, vol, ncomp
+
+
+def check_split(o, st):
+    ids, vol, ncomp = expected_split(st)
+    got = o.get(O.BUBBLE_ID).ravel()
+    sel = (st["gas"] | st["ifc"]).ravel()
+    np.testing.assert_array_equal(got[sel], ids[sel])
+    b = o.bubbles()
+    assert len(b) == ncomp + 1
+    rho = st["M"] / st["V"]
+    Mtot = 0.0
+    for k in range(1, ncomp + 1):
+        assert b[k]["alive"]
+        assert abs(b[k]["V"] - vol[k]) < 1e-12 * st["V"]
+        assert abs(b[k]["rho_g"] / rho - 1.0) < 1e-13
+        Mtot += b[k]["M"]
+    assert abs(Mtot / st["M"] - 1.0) < 1e-14
+    return ncomp
+
+
+def test_two_blobs_split_by_volume():
+    n = (20, 14, 24)
+    gas = ball(n, (9.3, 7.0, 6.0), 2.6) | ball(n, (10.0, 6.5, 16.0), 3.4)
+    o, st = hand_state(n, gas, rho_g=1.013)
+    o.bubbles_set([0.0, st["M"]], [0, 1], [0, 1])   # splits on setting the table
+    assert check_split(o, st) == 2
+    assert o.split() == 0                             # nothing left to split
+    o.close()
+
+
+@pytest.mark.parametrize("contact,parts", [((1, 1, 0), 1), ((1, 0, 1), 1), ((1, 1, 1), 2)])
+def test_neighbourhood_edges_connect_corners_do_not(contact, parts):
+    n = (16, 16, 16)
+    gas = np.zeros((16, 16, 16), bool)
+    gas[4:7, 4:7, 4:7] = True                         # cube 4..6
+    d = np.array(contact)
+    lo = 7 - (1 - d)                                  # touches the cube through the contact offset only
+    gas[lo[2]:lo[2] + 3, lo[1]:lo[1] + 3, lo[0]:lo[0] + 3] = True
+    lab, k = ndimage.label(gas, structure=STRUCT)
+    assert k == parts
+    o, st = hand_state(n, gas)
+    o.bubbles_set([0.0, st["M"]], [0, 1], [0, 1])
+    assert check_split(o, st) == parts
+    o.close()
+
+
+def test_three_parts_ids_by_lowest_cell_and_shared_interface():
+    n = (18, 12, 12)
+    gas = np.zeros((12, 12, 18), bool)
+    # three blocks in x with one-cell gaps (x = 6 and 11) whose interface cells
+    # touch two blocks each
+    gas[4:8, 4:8, 12:16] = True
+    gas[4:8, 4:8, 2:6] = True
+    gas[4:8, 4:8, 7:11] = True
+    o, st = hand_state(n, gas, rho_g=0.97)
+    o.bubbles_set([0.0, st["M"]], [0, 1], [0, 1])
+    assert check_split(o, st) == 3
+    ids = o.get(O.BUBBLE_ID)
+    # the block at x 2..5 holds the lowest cell index and keeps id 1; then x 7..10, 12..15
+    assert ids[4, 4, 2] == 1 and ids[4, 4, 7] == 2 and ids[4, 4, 12] == 3
+    # an interface cell between two parts goes with the lower one
+    assert ids[5, 5, 6] == 1 and ids[5, 5, 11] == 2
+    o.close()
+
+
+def test_full_table_is_an_error():
+    n = (16, 12, 12)
+    gas = ball(n, (4.0, 6.0, 6.0), 2.2) | ball(n, (11.0, 6.0, 6.0), 2.2)
+    o, st = hand_state(n, gas, max_bubbles=2)
+    with pytest.raises(ValueError):
+        o.bubbles_set([0.0, st["M"]], [0, 1], [0, 1])
+    o.close()
+
+
+def gas_mass_and_components(o, G0, t):
+    """Every root's gas cells form one component (scipy); the gas mass is constant."""
+    b = o.bubbles()
+    fl = o.get(O.FLAGS)
+    ids = o.get(O.BUBBLE_ID)
+    for r in (bb["id"] for bb in b if bb["alive"]):
+        g = (fl == O.GAS) & (ids == r)
+        if g.any():
+            assert ndimage.label(g, structure=STRUCT)[1] == 1, (t, r)
+    assert abs(sum(bb["M"] for bb in b if bb["alive"]) / G0 - 1.0) < 1e-13
+    return len(b)
+
+
+def test_conversions_close_a_gas_neck():
+    """Two gas balls joined by a one-cell neck whose middle interface cells are full:
+    they fill in the first step, the neck's gas cells become interface cells (cell
+    conversions) and the bubble splits."""
+    n = (26, 16, 18)
+    gas = ball(n, (6.0, 8.0, 9.0), 3.0) | ball(n, (19.0, 8.0, 9.0), 3.0)
+    gas[9, 8, 8:19] = True                            # the neck along x at y = 8, z = 9
+    ifc = interface_of(gas)
+    z, y, x = np.nonzero(ifc)
+    full = (x >= 11) & (x <= 14) & (abs(y - 8) <= 1) & (abs(z - 9) <= 1)
+    o, st = hand_state(n, gas, phi_ifc=np.where(full, 1.001, 0.5))
+    o.bubbles_set([0.0, st["M"]], [0, 1], [0, 1])
+    M0 = o.mass()[0]
+    G0 = st["M"]
+    split_at = None
+    for t in range(30):
+        o.step(1)
+        if gas_mass_and_components(o, G0, t) > 2 and split_at is None:
+            split_at = t
+    assert split_at is not None, "the neck never closed"
+    assert abs(o.mass()[0] / M0 - 1.0) < 1e-12
+    o.close()
+
+
+def test_particle_cuts_a_gas_neck():
+    """Two gas balls joined by a 3 x 3 neck; a sphere rising through the neck covers
+    its cross-section and the bubble splits (coverage removes the gas cells)."""
+    n = (26, 16, 20)
+    gas = ball(n, (5.0, 8.0, 9.0), 3.0) | ball(n, (20.0, 8.0, 9.0), 3.0)
+    gas[8:11, 7:10, 7:19] = True                      # the neck along x, y 7..9, z 8..10
+    p = W.Particles(x=np.array([[13.0, 8.0, 5.0]]), u=np.array([[0.0, 0.0, 0.12]]),
+                    omega=np.zeros((1, 3)), R=np.array([2.5]), rho_p=np.array([20.0]))
+    o, st = hand_state(n, gas, phi_ifc=0.5, particles=p)
+    o.bubbles_set([0.0, st["M"]], [0, 1], [0, 1])
+    o.particles_set(p)
+    M0 = o.mass()[0]
+    G0 = st["M"]
+    split_at = None
+    for t in range(50):
+        o.step(1)
+        if gas_mass_and_components(o, G0, t) > 2 and split_at is None:
+            split_at = t
+            zp = o.particles_get(1)["x"][0, 2]
+    assert split_at is not None, "the neck was never cut"
+    assert 6.5 < zp < 10.5, zp                        # the sphere sits in the neck
+    assert abs(o.mass()[0] / M0 - 1.0) < 1e-12
+    o.close()
