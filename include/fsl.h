@@ -114,7 +114,14 @@ int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, 
  * wall / moving-particle / free-surface reconstruction, moments, interface mass
  * exchange, collision (Eqs. LBE1, LBE2, fsk, bbrule, massExchange, massExchangeb),
  * momentum exchange (Eqs. netforce, torque), cell conversions, particle update
- * (Eq. lubrication, substeps) and the bubble model. */
+ * (Eq. lubrication, substeps) and the bubble model (end of Sec. 2.2): gas volumes
+ * and densities, merges, and splitting: where the gas of a bubble falls apart
+ * (D3Q19 neighbours of one root bubble), the part with the lowest cell index keeps
+ * the id, the others take the next unused ids in order of their lowest cell index,
+ * interface cells follow the part of their gas neighbours, and the gas mass is
+ * shared by volume.  A split that needs more ids than max_bubbles, or a state with
+ * more than 1024 separate gas parts, is reported as FSL_E_CAPACITY by the next
+ * synchronising call. */
 int fsl_step(fsl_ctx *ctx, int n);
 
 /* Replace the particle table with n spheres (arrays n x 3: centres in node
@@ -131,11 +138,13 @@ int fsl_particles_set(fsl_ctx *ctx, int n, const double *x, const double *u,
 int fsl_particles_get(fsl_ctx *ctx, int n, double *x, double *u, double *omega,
                       double *F, double *T);
 
-/* Copy up to cap bubble records to out; *n receives the table size.  Synchronises. */
+/* Copy up to cap bubble records to out; *n receives the number of ids in use
+ * (splits add ids).  Synchronises. */
 int fsl_bubbles_get(fsl_ctx *ctx, fsl_bubble *out, int cap, int *n);
 
-/* Import the bubble table (gas masses, merge roots, alive flags) for n ids and
- * recompute volumes and gas densities from the current fields. */
+/* Import the bubble table (gas masses, merge roots, alive flags) for n ids (the
+ * others become unused), recompute volumes and gas densities from the current
+ * fields and split bubbles whose gas is not connected. */
 int fsl_bubbles_set(fsl_ctx *ctx, int n, const double *M, const int *root, const int *alive);
 
 /* Field exchange for tests and checkpoints.  Host layouts:
@@ -173,9 +182,9 @@ void fsl_destroy(fsl_ctx *ctx);
  * phase of a step is bracketed by events; fsl_profile_get writes, for phase k < n
  * (0 = fused stream-collide kernel, 1 = cell conversions, 2 = bubble volumes,
  * 3 = particle pairs and forces, 4 = particle substeps, 5 = coverage update,
- * 6 = interface curvature, run only with sigma > 0), the summed milliseconds and
- * counts since the last call, resets them, synchronises and returns the number of
- * phases (7).  Off by default. */
+ * 6 = interface curvature, run only with sigma > 0, 7 = bubble splitting test and
+ * pass), the summed milliseconds and counts since the last call, resets them,
+ * synchronises and returns the number of phases (8).  Off by default. */
 int fsl_profile_enable(fsl_ctx *ctx, int on);
 int fsl_profile_get(fsl_ctx *ctx, double *ms, long long *count, int n);
 

@@ -241,7 +241,7 @@ class Sim:
         self._check(self.L.fsl_profile_enable(self.ctx, int(on)), "fsl_profile_enable")
 
     PHASES = ("stream_collide", "conversions", "bubbles", "particle_forces", "particle_substeps",
-              "coverage", "curvature")
+              "coverage", "curvature", "split")
 
     def profile_get(self):
         n = len(self.PHASES)

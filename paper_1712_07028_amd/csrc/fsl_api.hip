@@ -19,6 +19,7 @@
 #include "../../include/fsl.h"
 #include "k_init.hpp"
 #include "k_particles.hpp"
+#include "k_split.hpp"
 #include "k_stream_collide.hpp"
 #include "k_adjoint.hpp"
 
@@ -28,7 +29,7 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 constexpr int LIST_BLOCKS = 128;
-constexpr int NPROF = 7;
+constexpr int NPROF = 8;
 
 size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -37,6 +38,7 @@ struct Layout {
     size_t lF, lE0, lE, lNG, lNL, lCov, lUnc, uncRho, uncDec, merges, pairs;
     size_t counters, ctl, ptab, pacc, pFT, pFTp, pFl, pmir, gStart, gCount, gIdx, gBsum;
     size_t btab, bacc, broot, balive, rhog, kappa, ktf, klist, kcount, wallu, stage;
+    size_t slab, scomp, scid, spar, svol;  // bubble splitting
     size_t win;  // differentiation window storage
     size_t total;
     long long S;
@@ -128,6 +130,11 @@ Layout layout_of(const fsl_config *c) {
     L.klist = take((size_t)L.nKT * 4);
     L.kcount = take(c->sigma != 0.0 ? 4 : 0);
     L.wallu = take(18 * 4);
+    L.slab = take(L.S * 4);
+    L.scomp = take(SPLIT_MAXC * 4);
+    L.scid = take(SPLIT_MAXC * 4);
+    L.spar = take(SPLIT_MAXC * 4);
+    L.svol = take(SPLIT_MAXC * 8);
     L.stage = take(L.stageBytes);
     L.nTiles = ((c->n[0] + TX - 1) / TX) * ((c->n[1] + TY - 1) / TY) * c->n[2];
     L.winBytes = adjoint_window_bytes(c->window_steps, c->window_every, (size_t)L.S, c->max_particles,
@@ -145,6 +152,7 @@ struct fsl_ctx {
     Geom G;
     Phys Ph;
     Dev D;
+    SplitBuf SB;
     hipStream_t st;
     char *ws;
     char err[256];
@@ -266,10 +274,40 @@ template <int ST>
 int enqueue_bubbles(fsl_ctx *c, double *phi, int init) {
     ProfScope ps(c, 2);
     Dev &D = c->D;
-    hipLaunchKernelGGL(k_bubble_zero, dim3(1), dim3(256), 0, c->st, D);
+    hipLaunchKernelGGL(k_bubble_zero, dim3(1), dim3(256), 0, c->st, D, (const int *)nullptr);
     hipLaunchKernelGGL(k_bubble_accum, dim3(grid_for((c->G.N + 15) / 16, 256, 2048)), dim3(256), 0,
-                       c->st, c->G, D, (const double *)phi);
-    hipLaunchKernelGGL(k_bubble_finalize, dim3(1), dim3(64), 0, c->st, D, init);
+                       c->st, c->G, D, (const double *)phi, (const int *)nullptr);
+    hipLaunchKernelGGL(k_bubble_finalize, dim3(1), dim3(64), 0, c->st, D, init, (const int *)nullptr);
+    LAUNCHCHK(c);
+    return FSL_OK;
+}
+
+// bubble splitting at the end of a step (force = 0: labelling only where the local
+// test of a cell that left the gas fails) or of the current state (force = 1);
+// phi is the state's fill level.  Every kernel after the test reads the flag the
+// test leaves and returns at once when there is nothing to do.
+template <int ST>
+int enqueue_split(fsl_ctx *c, const double *phi, int force) {
+    ProfScope ps(c, 7);
+    const Dev &D = c->D;
+    const SplitBuf &B = c->SB;
+    const dim3 gl(LIST_BLOCKS), b(256), gn(grid_for(c->G.N, 256, 2048));
+    if (force) hipLaunchKernelGGL(k_split_force, dim3(1), dim3(64), 0, c->st, D);
+    else hipLaunchKernelGGL(k_split_test, gl, b, 0, c->st, c->G, D);
+    hipLaunchKernelGGL(k_split_clear, gl, b, 0, c->st, D);
+    hipLaunchKernelGGL(k_ccl_init, gn, b, 0, c->st, c->G, D, B);
+    hipLaunchKernelGGL(k_ccl_union, gn, b, 0, c->st, c->G, D, B);
+    hipLaunchKernelGGL(k_ccl_flatten, gn, b, 0, c->st, c->G, D, B);
+    hipLaunchKernelGGL(k_ccl_comps, gn, b, 0, c->st, c->G, D, B);
+    hipLaunchKernelGGL(k_split_plan, dim3(1), dim3(1024), 0, c->st, D, B);
+    hipLaunchKernelGGL(k_split_ifc, gn, b, 0, c->st, c->G, D, B, phi);
+    hipLaunchKernelGGL(k_split_gas, dim3(grid_for((c->G.N + 15) / 16, 256, 2048)), b, 0, c->st, c->G, D, B);
+    hipLaunchKernelGGL(k_split_mass, dim3(1), dim3(64), 0, c->st, D, B);
+    const int *gate = D.counters + C_SPLIT;  // 2: some bubble split, volumes again
+    hipLaunchKernelGGL(k_bubble_zero, dim3(1), dim3(256), 0, c->st, D, gate);
+    hipLaunchKernelGGL(k_bubble_accum, dim3(grid_for((c->G.N + 15) / 16, 256, 2048)), dim3(256), 0,
+                       c->st, c->G, D, phi, gate);
+    hipLaunchKernelGGL(k_bubble_finalize, dim3(1), dim3(64), 0, c->st, D, 0, gate);
     LAUNCHCHK(c);
     return FSL_OK;
 }
@@ -405,6 +443,8 @@ int enqueue_steps(fsl_ctx *c, int n) {
         }
         rc = enqueue_bubbles<ST>(c, D.phi_nxt, 0);
         if (rc) return rc;
+        rc = enqueue_split<ST>(c, D.phi_nxt, 0);
+        if (rc) return rc;
         std::swap(D.fA, D.fB);
         std::swap(D.phi_cur, D.phi_nxt);
     }
@@ -426,7 +466,9 @@ int enqueue_coverage_full(fsl_ctx *c) {
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(c->G.N, 256, 4096)), dim3(256), 0, c->st, Dv.claim,
                        c->G.N, CLAIM_NONE);
     LAUNCHCHK(c);
-    return enqueue_bubbles<ST>(c, Dv.phi_cur, 0);
+    rc = enqueue_bubbles<ST>(c, Dv.phi_cur, 0);
+    if (rc) return rc;
+    return enqueue_split<ST>(c, Dv.phi_cur, 1);
 }
 
 template <int ST>
@@ -438,7 +480,9 @@ int dispatch_init(fsl_ctx *c, const InitGeo &I) {
     hipLaunchKernelGGL(k_init_closure_mark, dim3(g), dim3(256), 0, c->st, c->G, D);
     hipLaunchKernelGGL(k_init_pdf<ST>, dim3(g), dim3(256), 0, c->st, c->G, c->Ph, D, I);
     LAUNCHCHK(c);
-    return enqueue_bubbles<ST>(c, D.phi_cur, 1);
+    int rc = enqueue_bubbles<ST>(c, D.phi_cur, 1);
+    if (rc) return rc;
+    return enqueue_split<ST>(c, D.phi_cur, 1);
 }
 
 template <typename Fn>
@@ -455,7 +499,7 @@ int read_error(fsl_ctx *c) {
     HIPCHK(c, hipMemcpyAsync(&e, c->D.err, 4, hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
     if (!e) return FSL_OK;
-    if (e & ERR_CAP) return fail(c, FSL_E_CAPACITY, "a conversion, event or pair list overflowed");
+    if (e & ERR_CAP) return fail(c, FSL_E_CAPACITY, "a list, the bubble table or the gas-part list overflowed");
     if (e & ERR_NAN) return fail(c, FSL_E_NUMERIC, "NaN density or velocity");
     if (e & ERR_VOL) return fail(c, FSL_E_NUMERIC, "a bubble volume collapsed to zero");
     if (e & ERR_LG) return fail(c, FSL_E_INVARIANT, "a liquid cell has a gas neighbour");
@@ -651,7 +695,9 @@ int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, 
     D.maxP = L.maxP;
     D.maxB = L.maxB;
     D.np = 0;
-    D.nb = cfg->n_gas_spheres + 1;
+    D.nb = L.maxB;  // kernels walk the whole table; unused ids hold no cells
+    c->SB = SplitBuf{(int *)(w + L.slab), (int *)(w + L.scomp), (int *)(w + L.scid), (int *)(w + L.spar),
+                     (double *)(w + L.svol)};
     c->Rmax = 0;
     c->ncell = 1;
     c->PG = PGrid{{1, 1, 1}, {(double)G.nx, (double)G.ny, (double)G.nz}, 2.0 / 3.0 + 1.0};
@@ -665,6 +711,14 @@ int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, 
     // control block, tables, accumulators
     hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, c->st, (double *)(w + L.ctl), 64LL, 0.0);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->st, D.counters, 64LL, 0);
+    {
+        const int used = cfg->n_gas_spheres + 1;  // bubble ids in use: atmosphere and gas spheres
+        if (hipMemcpyAsync(D.counters + C_BUSED, &used, 4, hipMemcpyHostToDevice, c->st) != hipSuccess ||
+            hipStreamSynchronize(c->st) != hipSuccess) {
+            delete c;
+            return FSL_E_HIP;
+        }
+    }
     if (L.nKT > 0)  // curvature tile flags: zero between steps
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(L.nKT)), dim3(256), 0, c->st, (int *)(w + L.ktf),
                            (long long)L.nKT, 0);
@@ -796,13 +850,16 @@ int fsl_particles_get(fsl_ctx *c, int n, double *x, double *u, double *omega, do
 
 int fsl_bubbles_get(fsl_ctx *c, fsl_bubble *out, int cap, int *n) {
     if (!c || (cap > 0 && !out)) return FSL_E_ARG;
-    const int nb = c->D.nb;
-    std::vector<double> tab((size_t)nb * B_STRIDE);
-    std::vector<int> root(nb), alive(nb);
+    const int nt = c->D.nb;
+    std::vector<double> tab((size_t)nt * B_STRIDE);
+    std::vector<int> root(nt), alive(nt);
+    int nb = 0;
     HIPCHK(c, hipMemcpyAsync(tab.data(), c->D.btab, tab.size() * 8, hipMemcpyDeviceToHost, c->st));
-    HIPCHK(c, hipMemcpyAsync(root.data(), c->D.broot, nb * 4, hipMemcpyDeviceToHost, c->st));
-    HIPCHK(c, hipMemcpyAsync(alive.data(), c->D.balive, nb * 4, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(root.data(), c->D.broot, nt * 4, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(alive.data(), c->D.balive, nt * 4, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(&nb, c->D.counters + C_BUSED, 4, hipMemcpyDeviceToHost, c->st));
     int rc = read_error(c);
+    nb = std::min(std::max(nb, 0), nt);
     if (n) *n = nb;
     for (int b = 0; b < nb && b < cap; ++b) {
         int r = b;
@@ -826,12 +883,27 @@ int fsl_bubbles_set(fsl_ctx *c, int n, const double *M, const int *root, const i
     if (!c || n < 1 || n > c->L.maxB || !M || !root || !alive) return fail(c, FSL_E_ARG, "bubbles_set: bad arguments");
     for (int b = 0; b < n; ++b)
         if (root[b] < 0 || root[b] >= n) return fail(c, FSL_E_ARG, "bubbles_set: bad root");
-    c->D.nb = n;
-    for (int b = 0; b < n; ++b)
-        HIPCHK(c, hipMemcpyAsync(c->D.btab + b * B_STRIDE + B_M, M + b, 8, hipMemcpyHostToDevice, c->st));
-    HIPCHK(c, hipMemcpyAsync(c->D.broot, root, n * 4, hipMemcpyHostToDevice, c->st));
-    HIPCHK(c, hipMemcpyAsync(c->D.balive, alive, n * 4, hipMemcpyHostToDevice, c->st));
-    int rc = by_storage(c, [&](auto st) { return enqueue_bubbles<decltype(st)::value>(c, c->D.phi_cur, 0); });
+    // ids from n on become unused: no mass, their own root, not alive
+    const int nt = c->L.maxB;
+    std::vector<double> tab((size_t)nt * B_STRIDE);
+    std::vector<int> rt(nt), al(nt, 0);
+    HIPCHK(c, hipMemcpyAsync(tab.data(), c->D.btab, tab.size() * 8, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    for (int b = 0; b < nt; ++b) {
+        rt[b] = b < n ? root[b] : b;
+        al[b] = b < n ? alive[b] : 0;
+        if (b >= n) std::fill(&tab[(size_t)b * B_STRIDE], &tab[(size_t)(b + 1) * B_STRIDE], 0.0);
+        else tab[(size_t)b * B_STRIDE + B_M] = M[b];
+    }
+    HIPCHK(c, hipMemcpyAsync(c->D.btab, tab.data(), tab.size() * 8, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->D.broot, rt.data(), nt * 4, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->D.balive, al.data(), nt * 4, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->D.counters + C_BUSED, &n, 4, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    int rc = by_storage(c, [&](auto st) {
+        int r = enqueue_bubbles<decltype(st)::value>(c, c->D.phi_cur, 0);
+        return r ? r : enqueue_split<decltype(st)::value>(c, c->D.phi_cur, 1);
+    });
     if (rc) return rc;
     return read_error(c);
 }

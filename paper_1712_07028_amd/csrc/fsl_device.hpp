@@ -43,12 +43,21 @@ constexpr unsigned ERR_LG = 1u, ERR_NAN = 2u, ERR_CAP = 4u, ERR_VOL = 8u;
 
 // conversion marks (one byte per cell, zero outside the conversion phase)
 constexpr uint8_t CV_F = 1, CV_E0 = 2, CV_E = 4, CV_NEWG = 8, CV_NEWL = 16;
+// a gas cell that left the gas phase in this step (became interface or was covered);
+// set until the splitting test at the end of the step
+constexpr uint8_t CV_GRM = 32;
+// a cell that entered the gas phase in this step (emptied or uncovered as gas)
+constexpr uint8_t CV_GAD = 64;
 
 // counters in the control block
 enum Counter {
     C_NF = 0, C_NE0, C_NE, C_NNG, C_NNL, C_NMERGE, C_NCOVER, C_NUNCOVER, C_NPAIRS, C_COVALL,
+    C_SPLIT,  // splitting pass: 1 = label the gas, 2 = some bubble splits
+    C_NCOMP,  // gas components listed by the splitting pass
     C_COUNT
 };
+// persistent slot (not reset per step): number of bubble ids in use
+constexpr int C_BUSED = 63;
 
 // particle table: 16 doubles per particle
 // P_OVL: 1 when the coverage update must resolve overlaps through claims (a sphere

@@ -275,8 +275,9 @@ __global__ void k_conv_fill(Geom G, Phys Ph, Dev D) {
         }
     }
     GRID_STRIDE(i, nF) D.cv[D.lF[i]] = 0;
-    GRID_STRIDE(i, nE0) D.cv[D.lE0[i]] = 0;
-    GRID_STRIDE(i, nG) D.cv[D.lNG[i]] = 0;
+    // emptied cells are new gas: marked for the splitting test
+    GRID_STRIDE(i, nE0) D.cv[D.lE0[i]] = (D.cv[D.lE0[i]] & CV_E) ? CV_GAD : 0;
+    GRID_STRIDE(i, nG) D.cv[D.lNG[i]] = CV_GRM;  // left the gas: for the splitting test
     GRID_STRIDE(i, nL) D.cv[D.lNL[i]] = 0;
 }
 
@@ -295,13 +296,16 @@ __global__ void k_bubble_merge(Dev D) {
 }
 
 // ---- bubble volumes: dense pass over the cell types ------------------------------
-__global__ void k_bubble_zero(Dev D) {
+// gate: null, or a flag that must read 2 (a bubble split) for the kernel to run
+__global__ void k_bubble_zero(Dev D, const int *gate) {
+    if (gate && *gate != 2) return;
     GRID_STRIDE(i, D.nb * BACC_STRIDE) D.bacc[i] = 0.0;
 }
 
 // V_b = #gas cells + sum over interface cells of (1 - phi), with centroid moments;
 // per-block LDS accumulation (FP64), one global atomic per block and component
-__global__ __launch_bounds__(256) void k_bubble_accum(Geom G, Dev D, const double *phi) {
+__global__ __launch_bounds__(256) void k_bubble_accum(Geom G, Dev D, const double *phi, const int *gate) {
+    if (gate && *gate != 2) return;
     __shared__ double acc[64 * BACC_STRIDE];
     __shared__ int root[64];
     const int nb = D.nb;
@@ -374,8 +378,8 @@ __global__ __launch_bounds__(256) void k_bubble_accum(Geom G, Dev D, const doubl
 // rho_g = M / V for every root bubble; per-id FP32 mirror for the boundary condition
 // with init set, the gas densities of the initial state are read from the
 // table's density slot and the constant gas masses M = rho_g V(0) are fixed
-__global__ void k_bubble_finalize(Dev D, int init) {
-    if (blockIdx.x) return;
+__global__ void k_bubble_finalize(Dev D, int init, const int *gate) {
+    if (blockIdx.x || (gate && *gate != 2)) return;
     for (int b = threadIdx.x; b < D.nb; b += blockDim.x) {
         double *t = D.btab + b * B_STRIDE;
         const double *a = D.bacc + b * BACC_STRIDE;

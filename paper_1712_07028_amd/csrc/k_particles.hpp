@@ -451,6 +451,7 @@ __global__ void k_cov_apply(Geom G, Phys Ph, Dev D, double *phi) {
         uint8_t f = D.flags[c];
         if (f == LIQ) unsafeAtomicAdd(D.ledger, cell_rho<ST>(G, D, Ph, D.fB, c));
         else if (f == IFC) unsafeAtomicAdd(D.ledger, D.m[c]);
+        else if (f == GAS) D.cv[c] = CV_GRM;  // left the gas: for the splitting test
         D.flags[c] = SOL;
         D.pid[c] = P;
         phi[c] = 0.0;
@@ -497,6 +498,7 @@ __global__ void k_unc_apply(Geom G, Phys Ph, Dev D, double *phi) {
         if (type == GAS) {
             D.bub[c] = (uint16_t)bub;
             phi[c] = 0.0;
+            D.cv[c] = CV_GAD;  // new gas: for the splitting test
             continue;
         }
         float u0 = 0.f, u1 = 0.f, u2 = 0.f;

@@ -58,7 +58,7 @@ def hand_state(n, gas, rho_g=1.0, phi_ifc=None, max_bubbles=64, particles=None, 
     o.set(O.F, f)
     o.set(O.PID, np.full(gas.shape, -1, np.int32))
     V = gas.sum() + (1.0 - phi[ifc]).sum()
-    return o, dict(flags=fl, phi=phi, gas=gas, ifc=ifc, M=rho_g * V, V=V)
+    return o, dict(flags=fl, phi=phi, gas=gas, ifc=ifc, M=rho_g * V, V=V, w=w)
 
 
 def expected_split(st):
