@@ -147,6 +147,23 @@ def surface_tension_rate(fsl, torch, w, steps, sigma=0.005):
             "curvature_ms": round(prof["curvature"][0] / max(prof["curvature"][1], 1), 4)}
 
 
+def split_pass_cost(fsl, torch, w, reps=3):
+    """The column's bubble-splitting labelling when it runs: a forced pass over the
+    state after 5 steps (setting the bubble table labels every gas cell)."""
+    s = fsl.Sim(w)
+    s.step(5)
+    s.sync()
+    b = s.bubbles()
+    s.profile(True)
+    s.profile_get()
+    for _ in range(reps):
+        s.bubbles_set([x["M"] for x in b], list(range(len(b))), [x["alive"] for x in b])
+    prof = s.profile_get()
+    s.close()
+    torch.cuda.empty_cache()
+    return round(prof["split"][0] / max(prof["split"][1], 1), 4)
+
+
 def cpu_baseline(w, steps):
     """The FP64 oracle on a bounded sample: the lowest 16 layers of the column."""
     import oracle
@@ -255,6 +272,7 @@ def main():
     forms = {}
     adjoint = {}
     surface = None
+    split = None
     if not args.no_forms:
         from paper_1712_07028_amd import workloads as W
 
@@ -277,6 +295,9 @@ def main():
             log("adjoint", adjoint[f"{n}^3"])
         surface = surface_tension_rate(fsl, torch, w.replace(storage=0), min(args.steps, 100))
         log("surface tension", surface)
+        split = {"step_ms": breakdown.get("split"),
+                 "labelling_pass_ms": split_pass_cost(fsl, torch, w.replace(storage=0))}
+        log("bubble splitting", split)
 
     if args.calibrate_copy_gib > 0:
         nbytes = int(args.calibrate_copy_gib * (1 << 30))
@@ -312,6 +333,8 @@ def main():
         out["adjoint"] = adjoint
     if surface:
         out["surface_tension"] = surface
+    if split:
+        out["bubble_splitting"] = split
     print(json.dumps(out), flush=True)
 
 

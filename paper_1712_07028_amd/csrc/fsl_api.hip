@@ -263,7 +263,7 @@ void launch_stream_collide(fsl_ctx *c, const Dev &Dv) {
                            c->tilesX, c->tilesY, c->nTiles);
 }
 
-template <int ST> int enqueue_steps(fsl_ctx *c, int n);
+template <int ST> int enqueue_steps(fsl_ctx *c, int n, int split = 1);
 template <int ST> int enqueue_integration(fsl_ctx *c);
 template <int ST> int enqueue_pair_forces(fsl_ctx *c);
 template <int ST> int enqueue_coverage_step(fsl_ctx *c);
@@ -294,17 +294,14 @@ int enqueue_split(fsl_ctx *c, const double *phi, int force) {
     const dim3 gl(LIST_BLOCKS), b(256), gn(grid_for(c->G.N, 256, 2048));
     if (force) hipLaunchKernelGGL(k_split_force, dim3(1), dim3(64), 0, c->st, D);
     else hipLaunchKernelGGL(k_split_test, gl, b, 0, c->st, c->G, D);
-    hipLaunchKernelGGL(k_split_clear, gl, b, 0, c->st, D);
     hipLaunchKernelGGL(k_ccl_init, gn, b, 0, c->st, c->G, D, B);
     hipLaunchKernelGGL(k_ccl_union, gn, b, 0, c->st, c->G, D, B);
     hipLaunchKernelGGL(k_ccl_flatten, gn, b, 0, c->st, c->G, D, B);
-    hipLaunchKernelGGL(k_ccl_comps, gn, b, 0, c->st, c->G, D, B);
     hipLaunchKernelGGL(k_split_plan, dim3(1), dim3(1024), 0, c->st, D, B);
     hipLaunchKernelGGL(k_split_ifc, gn, b, 0, c->st, c->G, D, B, phi);
     hipLaunchKernelGGL(k_split_gas, dim3(grid_for((c->G.N + 15) / 16, 256, 2048)), b, 0, c->st, c->G, D, B);
-    hipLaunchKernelGGL(k_split_mass, dim3(1), dim3(64), 0, c->st, D, B);
+    hipLaunchKernelGGL(k_split_mass, dim3(1), dim3(256), 0, c->st, D, B);
     const int *gate = D.counters + C_SPLIT;  // 2: some bubble split, volumes again
-    hipLaunchKernelGGL(k_bubble_zero, dim3(1), dim3(256), 0, c->st, D, gate);
     hipLaunchKernelGGL(k_bubble_accum, dim3(grid_for((c->G.N + 15) / 16, 256, 2048)), dim3(256), 0,
                        c->st, c->G, D, phi, gate);
     hipLaunchKernelGGL(k_bubble_finalize, dim3(1), dim3(64), 0, c->st, D, 0, gate);
@@ -421,8 +418,10 @@ void enqueue_curvature(fsl_ctx *c) {
                        (const double *)c->D.phi_cur, tf, (const int *)tl, (const int *)tc, L.ktx, L.kty);
 }
 
+// split = 0 leaves out the bubble-splitting test (a state without gas cells: the
+// differentiation window)
 template <int ST>
-int enqueue_steps(fsl_ctx *c, int n) {
+int enqueue_steps(fsl_ctx *c, int n, int split) {
     for (int s = 0; s < n; ++s) {
         Dev &D = c->D;
         hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, c->st, D);
@@ -443,8 +442,10 @@ int enqueue_steps(fsl_ctx *c, int n) {
         }
         rc = enqueue_bubbles<ST>(c, D.phi_nxt, 0);
         if (rc) return rc;
-        rc = enqueue_split<ST>(c, D.phi_nxt, 0);
-        if (rc) return rc;
+        if (split) {
+            rc = enqueue_split<ST>(c, D.phi_nxt, 0);
+            if (rc) return rc;
+        }
         std::swap(D.fA, D.fB);
         std::swap(D.phi_cur, D.phi_nxt);
     }
@@ -536,7 +537,7 @@ int window_forward(fsl_ctx *c, int T, int k, double *J) {
     const size_t st = (size_t)Q * c->G.S * 4, stride = adj_up(st) / 4;
     HIPCHK(c, hipMemcpyAsync(A.cp, D.fA, st, hipMemcpyDeviceToDevice, c->st));
     for (int t = 0; t < T; ++t) {
-        int rc = enqueue_steps<ST_F32>(c, 1);
+        int rc = enqueue_steps<ST_F32>(c, 1, 0);  // no gas in the window
         if (rc) return rc;
         if (D.np > 0) hipLaunchKernelGGL(k_win_J, dim3(1), dim3(256), 0, c->st, D, A.acc);
         if ((t + 1) % k == 0 && t + 1 < T)

@@ -137,11 +137,6 @@ __global__ void k_split_test(Geom G, Dev D) {
     }
 }
 
-__global__ void k_split_clear(Dev D) {
-    const int nG = list_len(D, C_NNG), nC = event_len(D, C_NCOVER);
-    const int nE = list_len(D, C_NE), nU = event_len(D, C_NUNCOVER);
-    GRID_STRIDE(i, nG + nC + nE + nU) D.cv[split_cell(D, i, nG, nC, nE)] = 0;
-}
 
 // labelling of the current state regardless of the test (initial state, new tables
 // or particles)
@@ -189,7 +184,12 @@ __device__ void lab_unite(int *lab, int a, int b) {
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < (n);              \
          c += (long long)gridDim.x * blockDim.x)
 
+// clears the marks the test read (cv is zero outside the conversion phase), then
+// starts the labelling: every gas cell its own part
 __global__ void k_ccl_init(Geom G, Dev D, SplitBuf B) {
+    const int nG = list_len(D, C_NNG), nC = event_len(D, C_NCOVER);
+    const int nE = list_len(D, C_NE), nU = event_len(D, C_NUNCOVER);
+    GRID_STRIDE(i, nG + nC + nE + nU) D.cv[split_cell(D, i, nG, nC, nE)] = 0;
     if (D.counters[C_SPLIT] == 0) return;
     CELL_STRIDE(c, G.N) if (D.flags[c] == GAS) B.lab[c] = (int)c;
 }
@@ -210,15 +210,17 @@ __global__ void k_ccl_union(Geom G, Dev D, SplitBuf B) {
     }
 }
 
+// every gas cell links straight to its part's lowest cell (a concurrent find only
+// ever sees a link to an ancestor); the parts' lowest cells are listed
 __global__ void k_ccl_flatten(Geom G, Dev D, SplitBuf B) {
     if (D.counters[C_SPLIT] == 0) return;
-    CELL_STRIDE(c, G.N) if (D.flags[c] == GAS) B.lab[c] = lab_find(B.lab, (int)c);
-}
-
-__global__ void k_ccl_comps(Geom G, Dev D, SplitBuf B) {
-    if (D.counters[C_SPLIT] == 0) return;
     CELL_STRIDE(c, G.N) {
-        if (D.flags[c] != GAS || B.lab[c] != (int)c) continue;
+        if (D.flags[c] != GAS) continue;
+        const int root = lab_find(B.lab, (int)c);
+        if (root != (int)c) {
+            __hip_atomic_store(B.lab + c, root, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            continue;
+        }
         const int s = atomicAdd(D.counters + C_NCOMP, 1);
         if (s < SPLIT_MAXC) B.comp[s] = (int)c;
         else atomicOr(D.err, ERR_CAP);
@@ -324,9 +326,12 @@ __global__ void k_split_gas(Geom G, Dev D, SplitBuf B) {
 }
 
 // gas masses of the new bubbles: M_part = M_root V_part / V_root, the root keeps
-// the rest (the root volumes are those of the state before the split)
+// the rest (the root volumes are those of the state before the split); the block
+// also clears the volume sums for the recount that follows
 __global__ void k_split_mass(Dev D, SplitBuf B) {
-    if (D.counters[C_SPLIT] != 2 || blockIdx.x || threadIdx.x) return;
+    if (D.counters[C_SPLIT] != 2 || blockIdx.x) return;
+    for (int i = threadIdx.x; i < D.nb * BACC_STRIDE; i += blockDim.x) D.bacc[i] = 0.0;
+    if (threadIdx.x) return;
     __shared__ double Mr[64], taken[64];
     for (int r = 0; r < D.maxB; ++r) {
         Mr[r] = D.btab[r * B_STRIDE + B_M];
