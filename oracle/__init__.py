@@ -51,6 +51,8 @@ class OrcConfig(ctypes.Structure):
         ("wall_u", ((ctypes.c_double * 3) * 2) * 3),
         ("n_threads", ctypes.c_int),
         ("sigma", ctypes.c_double),
+        ("freeslip", ctypes.c_int * 3),
+        ("open_atmosphere", ctypes.c_int),
     ]
 
 
@@ -154,6 +156,9 @@ class Oracle:
                         cfg.wall_u[a][s][d] = float(wall_u[a][s][d])
         cfg.n_threads = int(n_threads)
         cfg.sigma = float(getattr(w, "sigma", 0.0))
+        for a in range(3):
+            cfg.freeslip[a] = int(getattr(w, "freeslip", (0, 0, 0))[a])
+        cfg.open_atmosphere = int(bool(getattr(w, "open_atmosphere", False)))
         self.w = w
         self.N = w.cells
         self.L = lib()

@@ -117,6 +117,35 @@ static int nbr(const orc_ctx *c, int i, int j, int k, int dx, int dy, int dz, in
     return a + c->nx * (b + c->ny * d);
 }
 
+/* Free-slip faces (specular reflection at the half-way wall).  Reading: a link whose
+ * far end lies beyond faces of the box reflects specularly when every face it
+ * crosses is free-slip, and bounces back when any of them is no-slip.  The reflected
+ * link reaches cell (i,j,k) + d along q from the cell (i,j,k) + d' with the crossed
+ * components of d removed, travelling along q with the crossed components reversed.
+ * crossed_axes returns the bit set of the non-periodic axes that (i,j,k) + d leaves
+ * (bit a for axis a) and whether all of them slip. */
+static int crossed_axes(const orc_ctx *c, int i, int j, int k, int dx, int dy, int dz, int *all_slip)
+{
+    const int v[3] = {i + dx, j + dy, k + dz}, n[3] = {c->nx, c->ny, c->nz};
+    int m = 0;
+    for (int a = 0; a < 3; ++a)
+        if (!c->cfg.periodic[a] && (v[a] < 0 || v[a] >= n[a])) m |= 1 << a;
+    int slip = m != 0;
+    for (int a = 0; a < 3; ++a)
+        if (((m >> a) & 1) && !c->cfg.freeslip[a]) slip = 0;
+    *all_slip = slip;
+    return m;
+}
+
+/* direction q with the components of the axes in m reversed */
+static int mirror_dir(int q, int m)
+{
+    const int e[3] = {(m & 1) ? -CX[q] : CX[q], (m & 2) ? -CY[q] : CY[q], (m & 4) ? -CZ[q] : CZ[q]};
+    for (int p = 0; p < 19; ++p)
+        if (CX[p] == e[0] && CY[p] == e[1] && CZ[p] == e[2]) return p;
+    return q;
+}
+
 static void cell_ijk(const orc_ctx *c, int x, int *i, int *j, int *k)
 {
     *i = x % c->nx;
@@ -409,6 +438,15 @@ static void bubbles_recompute(orc_ctx *c)
     }
     for (int b = 0; b < c->nb; ++b) {
         if (c->broot[b] != b || !c->balive[b]) continue;
+        if (b == 0 && c->cfg.open_atmosphere) {
+            /* pressure outlet (reading): the gas above the pool keeps rho_g0 and its
+             * mass follows its volume */
+            c->brho[0] = c->cfg.rho_g0;
+            c->bM[0] = c->cfg.rho_g0 * c->bV[0];
+            if (c->bV[0] > 0.0)
+                for (int a = 0; a < 3; ++a) c->bcent[a] /= c->bV[0];
+            continue;
+        }
         if (c->bV[b] > 0.0) {
             c->brho[b] = c->bM[b] / c->bV[b];
             for (int a = 0; a < 3; ++a) c->bcent[3 * b + a] /= c->bV[b];
@@ -465,6 +503,7 @@ static int split_bubbles(orc_ctx *c)
     for (int x = 0; x < N; ++x) {
         if (lab[x] != x) continue;
         const int r = find_root(c, c->bub[x]);
+        if (r == 0 && c->cfg.open_atmosphere) continue;  /* every part stays at the outlet */
         if (!seen[r]) {
             seen[r] = 1;
             continue;
@@ -1000,8 +1039,7 @@ static void stream_collide(orc_ctx *c)
                 int have_kappa = 0;
                 fc[0] = c->f[x];
                 for (int q = 1; q < 19; ++q) {
-                    int face = -1;
-                    int s = nbr(c, i, j, k, -CX[q], -CY[q], -CZ[q], &face);
+                    int s = nbr(c, i, j, k, -CX[q], -CY[q], -CZ[q], NULL);
                     int sf = s >= 0 ? c->flag[s] : -1;
                     if (sf == LIQ || sf == IFC) {
                         fc[q] = c->f[(size_t)q * N + s];
@@ -1011,8 +1049,35 @@ static void stream_collide(orc_ctx *c)
                         post_moments(c, c->f, x, &rho_t, u_t);
                         have_t = 1;
                     }
-                    if (s < 0) { /* half-way wall, optionally moving (oracle-only option) */
-                        const double *uw = c->cfg.wall_u[face / 2][face % 2];
+                    int slip = 0, cross = s < 0 ? crossed_axes(c, i, j, k, -CX[q], -CY[q], -CZ[q], &slip) : 0;
+                    if (s < 0 && slip) {
+                        /* free slip: specular reflection from the cell beside x along the
+                         * wall; gas there gives the free-surface condition, a particle
+                         * node plain bounce-back */
+                        const int sp = nbr(c, i, j, k, (cross & 1) ? 0 : -CX[q], (cross & 2) ? 0 : -CY[q],
+                                           (cross & 4) ? 0 : -CZ[q], NULL);
+                        const int spf = c->flag[sp];
+                        if (spf == LIQ || spf == IFC) {
+                            fc[q] = c->f[(size_t)mirror_dir(q, cross) * N + sp];
+                        } else if (spf == GAS) {
+                            double rg = bubble_rho(c, c->bub[sp]);
+                            if (c->cfg.sigma != 0.0) {
+                                if (!have_kappa) {
+                                    kappa = curvature_at(c, i, j, k);
+                                    have_kappa = 1;
+                                }
+                                rg += 6.0 * c->cfg.sigma * kappa;
+                            }
+                            fc[q] = -c->f[(size_t)OPP[q] * N + x] + 2.0 * eq_plus(q, rg, u_t);
+                        } else {
+                            fc[q] = c->f[(size_t)OPP[q] * N + x];
+                        }
+                    } else if (s < 0) { /* half-way no-slip wall, optionally moving */
+                        /* the moving-wall term of the first crossed no-slip face */
+                        int a = 0;
+                        while (!((cross >> a) & 1) || c->cfg.freeslip[a]) ++a;
+                        const int v = a == 0 ? i - CX[q] : (a == 1 ? j - CY[q] : k - CZ[q]);
+                        const double *uw = c->cfg.wall_u[a][v < 0 ? 0 : 1];
                         double cu = CX[q] * uw[0] + CY[q] * uw[1] + CZ[q] * uw[2];
                         fc[q] = c->f[(size_t)OPP[q] * N + x] + 6.0 * W[q] * rho_t * cu;
                     } else if (sf == SOL) {
@@ -1048,10 +1113,20 @@ static void stream_collide(orc_ctx *c)
                     double dm = 0;
                     for (int q = 1; q < 19; ++q) {
                         int n = nbr(c, i, j, k, CX[q], CY[q], CZ[q], NULL);
-                        if (n < 0) continue;
+                        int qin = OPP[q];  /* the population arriving at x against c_q */
+                        if (n < 0) {
+                            /* across free-slip faces the partner is the cell beside x
+                             * along the wall, whose reflected population arrives here */
+                            int slip = 0;
+                            const int cross = crossed_axes(c, i, j, k, CX[q], CY[q], CZ[q], &slip);
+                            if (!slip) continue;
+                            n = nbr(c, i, j, k, (cross & 1) ? 0 : CX[q], (cross & 2) ? 0 : CY[q],
+                                    (cross & 4) ? 0 : CZ[q], NULL);
+                            qin = mirror_dir(OPP[q], cross);
+                        }
                         int nf = c->flag[n];
                         if (nf != LIQ && nf != IFC) continue;
-                        double d = c->f[(size_t)OPP[q] * N + n] - c->f[(size_t)q * N + x];
+                        double d = c->f[(size_t)qin * N + n] - c->f[(size_t)q * N + x];
                         if (nf == IFC) d *= 0.5 * (c->phi[n] + c->phi[x]);
                         dm += d;
                     }
@@ -1414,6 +1489,8 @@ int orc_window_J(orc_ctx *c, int T, double *J, double *dJ)
     const size_t N = (size_t)c->N;
     if (T < 0 || !J) return -1;
     if (c->cfg.integrate && c->np > 0) return -1;
+    for (int a = 0; a < 3; ++a)  /* the window's links are no-slip or periodic */
+        if (c->cfg.freeslip[a] && !c->cfg.periodic[a]) return -1;
     for (int x = 0; x < c->N; ++x)
         if (c->flag[x] == GAS || c->flag[x] == IFC) return -1;
     double *s = (double *)malloc(sizeof(double) * 19 * N);

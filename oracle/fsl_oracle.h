@@ -46,6 +46,10 @@ typedef struct {
     double wall_u[3][2][3];   /* velocity of each box face [axis][low/high][comp] */
     int n_threads;            /* OpenMP threads for the per-cell loops (0 = default) */
     double sigma;             /* surface tension (0: no Laplace pressure jump)  */
+    int freeslip[3];          /* 1 = the faces of a non-periodic axis reflect
+                                 specularly (free slip) instead of bouncing back */
+    int open_atmosphere;      /* 1 = bubble 0 (the gas above the pool) is held at
+                                 rho_g0 (pressure outlet) instead of a fixed mass */
 } orc_config;
 
 typedef struct {

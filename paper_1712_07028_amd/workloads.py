@@ -53,6 +53,8 @@ class Workload:
     storage: int = STORAGE_F32
     particles: Particles | None = None
     sigma: float = 0.0  # surface tension (0: no Laplace pressure jump)
+    freeslip: tuple = (0, 0, 0)  # 1: the faces of a non-periodic axis are free-slip walls
+    open_atmosphere: bool = False  # the gas above the pool held at rho_g0 (pressure outlet)
 
     @property
     def cells(self) -> int:
