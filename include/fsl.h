@@ -50,6 +50,7 @@ extern "C" {
 
 #define FSL_NOSLIP 0
 #define FSL_PERIODIC 1
+#define FSL_FREESLIP 2  /* both faces reflect specularly (set-up of Sec. 3.2) */
 
 #define FSL_SRT 0
 #define FSL_TRT 1
@@ -64,7 +65,16 @@ extern "C" {
 
 typedef struct {
     int n[3];                   /* box size in cells, each >= 1                       */
-    int boundary[3];            /* FSL_NOSLIP or FSL_PERIODIC per axis                */
+    int boundary[3];            /* FSL_NOSLIP, FSL_PERIODIC or FSL_FREESLIP per axis.
+                                   A link whose far end lies beyond faces of the box
+                                   reflects specularly when every face it crosses is
+                                   free-slip: it arrives from the cell beside the node
+                                   along the wall with the crossed components of its
+                                   direction reversed (gas there: the free-surface
+                                   condition; a particle node: bounce-back).  Any
+                                   no-slip face crossed: half-way bounce-back.  The
+                                   interface mass exchange pairs a cell with the cell
+                                   whose reflected populations it receives.          */
     int collision;              /* FSL_SRT or FSL_TRT                                 */
     double tau;                 /* relaxation time, lambda_+ = -1/tau (Sec. 2.1)      */
     double magic;               /* TRT constant Lambda (3/16 in the paper)            */
@@ -88,6 +98,9 @@ typedef struct {
                                    [axis][low, high][component]; the half-way
                                    bounce-back at a face takes the moving-wall form of
                                    Eq. bbrule (all zero: resting walls)                */
+    int open_atmosphere;        /* 1: bubble 0 (the gas above the pool) is held at
+                                   rho_g0, its mass following its volume, and is never
+                                   split: a pressure outlet (Sec. 3.2)               */
 } fsl_config;
 
 typedef struct {
@@ -199,8 +212,8 @@ int fsl_profile_get(fsl_ctx *ctx, double *ms, long long *count, int n);
  * checkpoints in the workspace; afterwards the state is the state after T steps.
  * Requirements (FSL_E_ARG otherwise): the configuration reserved the window
  * (cfg.window_steps >= T, cfg.window_every >= k, ceil(T/k) <= ceil(window_steps /
- * window_every)), FP32 storage, spheres kinematic (integrate = 0) and every
- * non-solid cell liquid, so that no cell type can change.
+ * window_every)), FP32 storage, spheres kinematic (integrate = 0), no free-slip
+ * faces, and every non-solid cell liquid, so that no cell type can change.
  *
  * fsl_window_backward returns dJ/dtau (total derivative, including lambda_- of the
  * TRT constraint) and dJ/dg[3], both multiplied by the seed dJ, by a reverse sweep

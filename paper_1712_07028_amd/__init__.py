@@ -38,6 +38,7 @@ class FslConfig(ctypes.Structure):
         ("window_steps", ctypes.c_int), ("window_every", ctypes.c_int),
         ("sigma", ctypes.c_double),
         ("wall_u", ((ctypes.c_double * 3) * 2) * 3),
+        ("open_atmosphere", ctypes.c_int),
     ]
 
 
@@ -102,7 +103,8 @@ def make_config(w, max_particles=None, list_capacity=0, window=(0, 0), wall_u=No
     c = FslConfig()
     for a in range(3):
         c.n[a] = int(w.n[a])
-        c.boundary[a] = int(w.periodic[a])
+        # 1 periodic, 2 free-slip, 0 no-slip
+        c.boundary[a] = 1 if w.periodic[a] else (2 if getattr(w, "freeslip", (0, 0, 0))[a] else 0)
         c.g[a] = float(w.g[a])
     c.collision = 1 if w.trt else 0
     c.tau = float(w.tau)
@@ -121,6 +123,7 @@ def make_config(w, max_particles=None, list_capacity=0, window=(0, 0), wall_u=No
     c.eps_c = float(w.eps_c)
     c.list_capacity = int(list_capacity)
     c.max_bubbles = int(max_bubbles)
+    c.open_atmosphere = int(bool(getattr(w, "open_atmosphere", False)))
     c.window_steps, c.window_every = int(window[0]), int(window[1])
     c.sigma = float(getattr(w, "sigma", 0.0))
     if wall_u is not None:

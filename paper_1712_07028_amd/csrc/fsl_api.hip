@@ -28,7 +28,7 @@ using namespace fsl;
 namespace {
 
 constexpr size_t ALIGN = 256;
-constexpr int LIST_BLOCKS = 128;
+constexpr int LIST_BLOCKS = 1024;  // list kernels: enough waves to hide the latency of their gathers
 constexpr int NPROF = 8;
 
 size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
@@ -52,7 +52,9 @@ int esize(int storage) { return storage == FSL_STORE_F32 ? 4 : 2; }
 bool valid(const fsl_config *c) {
     if (!c) return false;
     for (int a = 0; a < 3; ++a)
-        if (c->n[a] < 1 || (c->boundary[a] != FSL_NOSLIP && c->boundary[a] != FSL_PERIODIC)) return false;
+        if (c->n[a] < 1 || (c->boundary[a] != FSL_NOSLIP && c->boundary[a] != FSL_PERIODIC &&
+                            c->boundary[a] != FSL_FREESLIP))
+            return false;
     long long N = (long long)c->n[0] * c->n[1] * c->n[2];
     if (N >= (1LL << 31) - 4096) return false;
     if (!(c->tau > 0.5)) return false;
@@ -248,7 +250,12 @@ void set_phys(fsl_ctx *c) {
     for (int a = 0; a < 3; ++a)
         for (int sd = 0; sd < 2; ++sd)
             for (int d = 0; d < 3; ++d)
-                if (f.boundary[a] != FSL_PERIODIC && f.wall_u[a][sd][d] != 0.0) c->Ph.moving_walls = 1;
+                if (f.boundary[a] == FSL_NOSLIP && f.wall_u[a][sd][d] != 0.0) c->Ph.moving_walls = 1;
+    for (int a = 0; a < 3; ++a) {
+        c->Ph.slip[a] = f.boundary[a] == FSL_FREESLIP;
+        if (c->Ph.slip[a]) c->Ph.moving_walls = 1;
+    }
+    c->Ph.open_atm = f.open_atmosphere != 0;
     c->Ph.inv = 1.0f / c->Ph.scale;
 }
 
@@ -277,7 +284,8 @@ int enqueue_bubbles(fsl_ctx *c, double *phi, int init) {
     hipLaunchKernelGGL(k_bubble_zero, dim3(1), dim3(256), 0, c->st, D, (const int *)nullptr);
     hipLaunchKernelGGL(k_bubble_accum, dim3(grid_for((c->G.N + 15) / 16, 256, 2048)), dim3(256), 0,
                        c->st, c->G, D, (const double *)phi, (const int *)nullptr);
-    hipLaunchKernelGGL(k_bubble_finalize, dim3(1), dim3(64), 0, c->st, D, init, (const int *)nullptr);
+    hipLaunchKernelGGL(k_bubble_finalize, dim3(1), dim3(64), 0, c->st, D, init, (const int *)nullptr,
+                       c->Ph.open_atm);
     LAUNCHCHK(c);
     return FSL_OK;
 }
@@ -297,14 +305,14 @@ int enqueue_split(fsl_ctx *c, const double *phi, int force) {
     hipLaunchKernelGGL(k_ccl_init, gn, b, 0, c->st, c->G, D, B);
     hipLaunchKernelGGL(k_ccl_union, gn, b, 0, c->st, c->G, D, B);
     hipLaunchKernelGGL(k_ccl_flatten, gn, b, 0, c->st, c->G, D, B);
-    hipLaunchKernelGGL(k_split_plan, dim3(1), dim3(1024), 0, c->st, D, B);
+    hipLaunchKernelGGL(k_split_plan, dim3(1), dim3(1024), 0, c->st, D, B, c->Ph.open_atm);
     hipLaunchKernelGGL(k_split_ifc, gn, b, 0, c->st, c->G, D, B, phi);
     hipLaunchKernelGGL(k_split_gas, dim3(grid_for((c->G.N + 15) / 16, 256, 2048)), b, 0, c->st, c->G, D, B);
     hipLaunchKernelGGL(k_split_mass, dim3(1), dim3(256), 0, c->st, D, B);
     const int *gate = D.counters + C_SPLIT;  // 2: some bubble split, volumes again
     hipLaunchKernelGGL(k_bubble_accum, dim3(grid_for((c->G.N + 15) / 16, 256, 2048)), dim3(256), 0,
                        c->st, c->G, D, phi, gate);
-    hipLaunchKernelGGL(k_bubble_finalize, dim3(1), dim3(64), 0, c->st, D, 0, gate);
+    hipLaunchKernelGGL(k_bubble_finalize, dim3(1), dim3(64), 0, c->st, D, 0, gate, c->Ph.open_atm);
     LAUNCHCHK(c);
     return FSL_OK;
 }
@@ -363,7 +371,7 @@ int enqueue_pair_forces(fsl_ctx *c) {
         hipLaunchKernelGGL(k_gscan_apply, dim3(nb), dim3(256), 0, c->st, D, c->ncell, chunk, (const int *)bsum);
     }
     hipLaunchKernelGGL(k_grid_fill, dim3(grid_for(np)), dim3(256), 0, c->st, D, c->PG);
-    hipLaunchKernelGGL(k_pairs, dim3(grid_for(np)), dim3(256), 0, c->st, D, c->PG, c->L.pcap);
+    hipLaunchKernelGGL(k_pairs, dim3(grid_for((long long)np * 27)), dim3(256), 0, c->st, D, c->PG, c->L.pcap);
     hipLaunchKernelGGL(k_solid_pairs, dim3(grid_for(c->L.pcap, 4, 8192)), dim3(256), 0, c->st, c->G, D, c->L.pcap);
     hipLaunchKernelGGL(k_part_forces, dim3((np + 255) / 256), dim3(256), 0, c->st, D, c->cfg.integrate);
     LAUNCHCHK(c);
@@ -526,6 +534,8 @@ int window_forward(fsl_ctx *c, int T, int k, double *J) {
     if (T < 1 || k < 1 || T > A.Tmax || k > A.kmax || (T + k - 1) / k > A.ncp)
         return fail(c, FSL_E_ARG, "window_forward: T or k exceed the window reserved in the workspace");
     if (c->cfg.integrate && D.np > 0) return fail(c, FSL_E_ARG, "window_forward: spheres must be kinematic (integrate off)");
+    for (int a = 0; a < 3; ++a)
+        if (c->cfg.boundary[a] == FSL_FREESLIP) return fail(c, FSL_E_ARG, "window_forward: free-slip faces");
     int *bad = (int *)(A.acc + 32);
     hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, c->st, A.acc, 64LL, 0.0);
     hipLaunchKernelGGL(k_win_check, dim3(grid_for(c->G.N, 256, 2048)), dim3(256), 0, c->st, c->G, D, bad);
@@ -684,7 +694,7 @@ int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, 
         for (int a = 0; a < 3; ++a)
             for (int sd = 0; sd < 2; ++sd)
                 for (int d = 0; d < 3; ++d)
-                    wv[(a * 2 + sd) * 3 + d] = cfg->boundary[a] == FSL_PERIODIC ? 0.0f : (float)cfg->wall_u[a][sd][d];
+                    wv[(a * 2 + sd) * 3 + d] = cfg->boundary[a] != FSL_NOSLIP ? 0.0f : (float)cfg->wall_u[a][sd][d];
         if (hipMemcpyAsync(D.wallu, wv, sizeof wv, hipMemcpyHostToDevice, c->st) != hipSuccess ||
             hipStreamSynchronize(c->st) != hipSuccess) {
             delete c;

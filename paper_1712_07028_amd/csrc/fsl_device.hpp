@@ -121,7 +121,10 @@ struct Phys {
     double eps;        // conversion threshold slack
     float scale, inv;  // 16-bit storage scale and its inverse
     float s6;          // 6 sigma: density form of the Laplace jump 2 sigma kappa (rho = 3 p)
-    int moving_walls;  // a non-periodic face moves (velocities in Dev::wallu)
+    int moving_walls;  // some face moves (velocities in Dev::wallu) or slips: wall links
+                       // then take the general path
+    int slip[3];       // the faces of axis a are free-slip
+    int open_atm;      // bubble 0 is held at its density (pressure outlet)
 };
 
 struct Dev {

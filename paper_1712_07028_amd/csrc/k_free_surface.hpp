@@ -378,7 +378,9 @@ __global__ __launch_bounds__(256) void k_bubble_accum(Geom G, Dev D, const doubl
 // rho_g = M / V for every root bubble; per-id FP32 mirror for the boundary condition
 // with init set, the gas densities of the initial state are read from the
 // table's density slot and the constant gas masses M = rho_g V(0) are fixed
-__global__ void k_bubble_finalize(Dev D, int init, const int *gate) {
+// open: bubble 0 is a pressure outlet, held at the density in its table slot (the
+// initial rho_g0) with its mass following its volume
+__global__ void k_bubble_finalize(Dev D, int init, const int *gate, int open) {
     if (blockIdx.x || (gate && *gate != 2)) return;
     for (int b = threadIdx.x; b < D.nb; b += blockDim.x) {
         double *t = D.btab + b * B_STRIDE;
@@ -394,8 +396,10 @@ __global__ void k_bubble_finalize(Dev D, int init, const int *gate) {
         t[B_NGAS] = a[4];
         t[B_NIF] = a[5];
         if (!D.balive[b]) continue;
+        const bool outlet = b == 0 && open;
+        if (outlet) t[B_M] = t[B_RHO] * a[0];
         if (a[0] > 0.0) {
-            t[B_RHO] = t[B_M] / a[0];
+            if (!outlet) t[B_RHO] = t[B_M] / a[0];
             t[B_C] = a[1] / a[0];
             t[B_C + 1] = a[2] / a[0];
             t[B_C + 2] = a[3] / a[0];

@@ -165,29 +165,45 @@ __global__ void k_grid_fill(Dev D, PGrid PG) {
     }
 }
 
+// append the pair (a, b) of every active lane with pred to a list of pairs: one
+// atomic per wave (the ballot sees the active lanes only, so divergent callers are fine)
+__device__ __forceinline__ void wave_push2(bool pred, int a, int b, int *list, int *counter, int cap,
+                                           unsigned *err) {
+    const unsigned long long mask = __ballot(pred);
+    if (!mask) return;
+    const int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if ((int)lane_id() == leader) base = atomicAdd(counter, __popcll(mask));
+    base = __shfl(base, leader);
+    if (pred) {
+        const int slot = base + __popcll(mask & ((1ull << lane_id()) - 1ull));
+        if (slot < cap) {
+            list[2 * slot] = a;
+            list[2 * slot + 1] = b;
+        } else {
+            atomicOr(err, ERR_CAP);
+        }
+    }
+}
+
+// one thread per particle and neighbouring grid cell (27 per particle), so that the
+// dependent loads of the cell lists overlap across many threads
 __global__ void k_pairs(Dev D, PGrid PG, int pcap) {
-    GRID_STRIDE(P, D.np) {
+    GRID_STRIDE(idx, D.np * 27) {
+        const int P = idx / 27, d = idx - 27 * P;
         const double *x = D.ptab + (long long)P * P_STRIDE;
-        int c0 = pgrid_cell(PG, x, 0), c1 = pgrid_cell(PG, x, 1), c2 = pgrid_cell(PG, x, 2);
-        for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                    int a = c0 + dx, b = c1 + dy, e = c2 + dz;
-                    if (a < 0 || b < 0 || e < 0 || a >= PG.g[0] || b >= PG.g[1] || e >= PG.g[2]) continue;
-                    int cell = a + PG.g[0] * (b + PG.g[1] * e);
-                    for (int s = D.gridStart[cell]; s < D.gridStart[cell + 1]; ++s) {
-                        int Qp = D.gridIdx[s];
-                        if (Qp <= P) continue;
-                        const double *y = D.ptab + (long long)Qp * P_STRIDE;
-                        double d0 = y[0] - x[0], d1 = y[1] - x[1], d2 = y[2] - x[2];
-                        double gap = sqrt(d0 * d0 + d1 * d1 + d2 * d2) - x[P_R] - y[P_R];
-                        if (gap < PG.reach) {
-                            int k = atomicAdd(D.counters + C_NPAIRS, 1);
-                            if (k < pcap) D.pairs[k] = make_int2(P, Qp);
-                            else atomicOr(D.err, ERR_CAP);
-                        }
-                    }
-                }
+        const int a = pgrid_cell(PG, x, 0) + d % 3 - 1, b = pgrid_cell(PG, x, 1) + (d / 3) % 3 - 1,
+                  e = pgrid_cell(PG, x, 2) + d / 9 - 1;
+        if (a < 0 || b < 0 || e < 0 || a >= PG.g[0] || b >= PG.g[1] || e >= PG.g[2]) continue;
+        const int cell = a + PG.g[0] * (b + PG.g[1] * e);
+        for (int s = D.gridStart[cell]; s < D.gridStart[cell + 1]; ++s) {
+            const int Qp = D.gridIdx[s];
+            if (Qp <= P) continue;
+            const double *y = D.ptab + (long long)Qp * P_STRIDE;
+            const double d0 = y[0] - x[0], d1 = y[1] - x[1], d2 = y[2] - x[2];
+            const double gap = sqrt(d0 * d0 + d1 * d1 + d2 * d2) - x[P_R] - y[P_R];
+            wave_push2(gap < PG.reach, P, Qp, (int *)D.pairs, D.counters + C_NPAIRS, pcap, D.err);
+        }
     }
 }
 
@@ -412,18 +428,30 @@ __global__ __launch_bounds__(256) void k_cov_scan(Geom G, Dev D) {
         return;
     }
     // a sphere alone: only nodes whose inside test changed between the old and new
-    // positions can change owner
-    for (int s = threadIdx.x & 63; s < tot; s += 64) {
-        int i = lo[0] + s % ex, j = lo[1] + (s / ex) % ey, k = lo[2] + s / (ex * ey);
-        const bool in_new = inside(i, j, k, t + P_X, t[P_R]);
-        const bool in_old = inside(i, j, k, t + P_XOLD, t[P_R]);
-        if (in_new == in_old) continue;
-        const int c = i + G.nx * (j + G.ny * k);
-        const uint8_t f = D.flags[c];
-        if (in_new) {
-            if (f != SOL) push_event(D, D.lCov, C_NCOVER, c, P);
-        } else if (f == SOL && D.pid[c] == P) {
-            push_event(D, D.lUnc, C_NUNCOVER, c, P);
+    // positions can change owner.  Walked as (x, y) columns: the in-plane part of
+    // both squared distances is formed once per column, in the order of inside(), and
+    // a column outside both circles is skipped (adding dz^2 cannot bring it inside)
+    const double *xn = t + P_X, *xo = t + P_XOLD;
+    const double R2 = __dmul_rn(t[P_R], t[P_R]);
+    for (int s = threadIdx.x & 63; s < ex * ey; s += 64) {
+        const int i = lo[0] + s % ex, j = lo[1] + s / ex;
+        const double a0 = i - xn[0], a1 = j - xn[1], b0 = i - xo[0], b1 = j - xo[1];
+        const double sn = __dadd_rn(__dmul_rn(a0, a0), __dmul_rn(a1, a1));
+        const double so = __dadd_rn(__dmul_rn(b0, b0), __dmul_rn(b1, b1));
+        if (sn > R2 && so > R2) continue;
+        for (int k = lo[2]; k <= hi[2]; ++k) {
+            const double a2 = k - xn[2], b2 = k - xo[2];
+            const bool in_new = __dadd_rn(sn, __dmul_rn(a2, a2)) <= R2;
+            const bool in_old = __dadd_rn(so, __dmul_rn(b2, b2)) <= R2;
+            bool cov = false, unc = false;
+            const int c = i + G.nx * (j + G.ny * k);
+            if (in_new != in_old) {
+                const uint8_t f = D.flags[c];
+                cov = in_new && f != SOL;
+                unc = !in_new && f == SOL && D.pid[c] == P;
+            }
+            wave_push2(cov, c, P, D.lCov, D.counters + C_NCOVER, D.capEv, D.err);
+            wave_push2(unc, c, P, D.lUnc, D.counters + C_NUNCOVER, D.capEv, D.err);
         }
     }
 }
@@ -443,18 +471,26 @@ __global__ void k_cov_scan_dense(Geom G, Dev D) {
     }
 }
 
+// the ledger takes the covered mass summed per wave (one atomic per wave): every
+// wave of the block takes the same rounds, so the sums see whole waves
 template <int ST>
 __global__ void k_cov_apply(Geom G, Phys Ph, Dev D, double *phi) {
-    int n = event_len(D, C_NCOVER);
-    GRID_STRIDE(e, n) {
-        int c = D.lCov[2 * e], P = D.lCov[2 * e + 1];
-        uint8_t f = D.flags[c];
-        if (f == LIQ) unsafeAtomicAdd(D.ledger, cell_rho<ST>(G, D, Ph, D.fB, c));
-        else if (f == IFC) unsafeAtomicAdd(D.ledger, D.m[c]);
-        else if (f == GAS) D.cv[c] = CV_GRM;  // left the gas: for the splitting test
-        D.flags[c] = SOL;
-        D.pid[c] = P;
-        phi[c] = 0.0;
+    const int n = event_len(D, C_NCOVER);
+    for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const int e = base + threadIdx.x;
+        double led = 0.0;
+        if (e < n) {
+            const int c = D.lCov[2 * e], P = D.lCov[2 * e + 1];
+            const uint8_t f = D.flags[c];
+            if (f == LIQ) led = cell_rho<ST>(G, D, Ph, D.fB, c);
+            else if (f == IFC) led = D.m[c];
+            else if (f == GAS) D.cv[c] = CV_GRM;  // left the gas: for the splitting test
+            D.flags[c] = SOL;
+            D.pid[c] = P;
+            phi[c] = 0.0;
+        }
+        led = wave_sum(led);
+        if (lane_id() == 0 && led != 0.0) unsafeAtomicAdd(D.ledger, led);
     }
 }
 

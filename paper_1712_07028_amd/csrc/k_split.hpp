@@ -229,7 +229,7 @@ __global__ void k_ccl_flatten(Geom G, Dev D, SplitBuf B) {
 
 // parts in order of their lowest cell index: the first part of each root keeps it,
 // the others take the next unused ids
-__global__ __launch_bounds__(1024) void k_split_plan(Dev D, SplitBuf B) {
+__global__ __launch_bounds__(1024) void k_split_plan(Dev D, SplitBuf B, int open) {
     if (D.counters[C_SPLIT] == 0) return;
     __shared__ int sorted[SPLIT_MAXC];
     __shared__ unsigned char seen[64];
@@ -252,7 +252,9 @@ __global__ __launch_bounds__(1024) void k_split_plan(Dev D, SplitBuf B) {
         const int c = sorted[k];
         const int r = bubble_root(D, D.bub[c]);
         int id = -1;
-        if (!seen[r]) {
+        if (r == 0 && open) {
+            // every part of an open atmosphere stays at the outlet
+        } else if (!seen[r]) {
             seen[r] = 1;
         } else if (used < D.maxB) {
             id = used++;

@@ -240,6 +240,41 @@ __device__ __forceinline__ bool collide_store(const Phys &Ph, const float (&fi)[
     return rho == rho && u0 == u0 && u1 == u1 && u2 == u2;
 }
 
+// Specular reflection at free-slip faces: the link q of cell (x, y, z) whose source
+// lies beyond the faces of the axes marked o* arrives from the cell beside it along
+// the wall, with the crossed components of its direction reversed.  Gas there gives
+// the free-surface condition (Eq. fsk) with that cell's bubble; a particle node
+// gives plain bounce-back (fbb, the cell's own opposite population).
+__device__ __forceinline__ int mirror_q(int q, bool ox, bool oy, bool oz) {
+    const int ex = ox ? -cx(q) : cx(q), ey = oy ? -cy(q) : cy(q), ez = oz ? -cz(q) : cz(q);
+    int r = q;
+#pragma unroll
+    for (int p = 1; p < Q; ++p)
+        if (cx(p) == ex && cy(p) == ey && cz(p) == ez) r = p;
+    return r;
+}
+
+template <int ST>
+__device__ __noinline__ float slip_link(const Geom &G, const Phys &Ph, const Dev &D,
+                                        const uint8_t (&tile)[3][TY + 2][TX + 2], int lx, int ly, int x, int y,
+                                        int z, int c, int q, bool ox, bool oy, bool oz, float ut0, float ut1,
+                                        float ut2, float fbb) {
+    using SS = Store<ST>;
+    const int dx = ox ? 0 : cx(q), dy = oy ? 0 : cy(q), dz = oz ? 0 : cz(q);
+    const uint8_t sf = tile[1 - dz][ly + 1 - dy][lx + 1 - dx];
+    const int sp = wrapc(x - dx, G.nx) + G.nx * wrapc(y - dy, G.ny) + G.nx * G.ny * wrapc(z - dz, G.nz);
+    if (sf == LIQ || sf == IFC)
+        return SS::ld((const typename SS::T *)D.fA + mirror_q(q, ox, oy, oz) * G.S + (unsigned)sp, Ph.inv);
+    if (sf == GAS) {
+        const int bid = D.bub[sp];
+        const float rg = D.rhog[bid < D.maxB ? bid : 0] + (D.kappa ? Ph.s6 * D.kappa[c] : 0.f);
+        const float cu = cx(q) * ut0 + cy(q) * ut1 + cz(q) * ut2;
+        const float uu = ut0 * ut0 + ut1 * ut1 + ut2 * ut2;
+        return -fbb + 2.0f * wq(q) * ((rg - 1.0f) + rg * (4.5f * cu * cu - 1.5f * uu));
+    }
+    return fbb;
+}
+
 // One boundary cell of the fused step (a cell with an interface, gas or particle
 // next to it, or an interface cell).  INTERIOR: the tile and its halo lie inside
 // the box, so a source is the cell index minus a uniform offset (no wrap, no wall).
@@ -350,14 +385,22 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
                 const int o = opp(q);
                 if (!INTERIOR && ((wm >> q) & 1u)) {
                     // half-way bounce-back; a moving face adds 6 w_q rho_t (c_q . u_w)
-                    // (Eq. bbrule), the face being the first axis whose source lies
-                    // beyond a non-periodic face
+                    // (Eq. bbrule), the face being the first crossed no-slip face.  A
+                    // link that crosses free-slip faces only reflects specularly.
                     float add = 0.f;
                     if (MW) {
                         const int sx = x - cx(q), sy = y - cy(q), sz = z - cz(q);
+                        const bool ox = !G.per[0] && (sx < 0 || sx >= nx);
+                        const bool oy = !G.per[1] && (sy < 0 || sy >= ny);
+                        const bool oz = !G.per[2] && (sz < 0 || sz >= nz);
+                        if ((!ox || Ph.slip[0]) && (!oy || Ph.slip[1]) && (!oz || Ph.slip[2])) {
+                            fi[q] = slip_link<ST>(G, Ph, D, tile, lx, ly, x, y, z, c, q, ox, oy, oz, ut0, ut1, ut2,
+                                                  fo(o));
+                            continue;
+                        }
                         int a = 2, sd = sz < 0 ? 0 : 1;
-                        if (!G.per[0] && (sx < 0 || sx >= nx)) { a = 0; sd = sx < 0 ? 0 : 1; }
-                        else if (!G.per[1] && (sy < 0 || sy >= ny)) { a = 1; sd = sy < 0 ? 0 : 1; }
+                        if (ox && !Ph.slip[0]) { a = 0; sd = sx < 0 ? 0 : 1; }
+                        else if (oy && !Ph.slip[1]) { a = 1; sd = sy < 0 ? 0 : 1; }
                         const float *uw = D.wallu + (a * 2 + sd) * 3;
                         add = 6.0f * wq(q) * rho_t * (cx(q) * uw[0] + cy(q) * uw[1] + cz(q) * uw[2]);
                     }
@@ -418,6 +461,25 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
                     double d = (double)fi[opp(q)] - (double)fo(q);
                     if (nf == IFC) d *= 0.5 * (D.phi_cur[nbr(q)] + phx);
                     dm += d;
+                } else if (MW && !INTERIOR && nf == WALL) {
+                    // across free-slip faces the partner is the cell beside this one
+                    // along the wall: its reflected population arrives as fi[opp(q)]
+                    const int ex = x + cx(q), ey = y + cy(q), ez = z + cz(q);
+                    const bool ox = !G.per[0] && (ex < 0 || ex >= nx);
+                    const bool oy = !G.per[1] && (ey < 0 || ey >= ny);
+                    const bool oz = !G.per[2] && (ez < 0 || ez >= nz);
+                    if ((!ox || Ph.slip[0]) && (!oy || Ph.slip[1]) && (!oz || Ph.slip[2])) {
+                        const int dx = ox ? 0 : cx(q), dy = oy ? 0 : cy(q), dz = oz ? 0 : cz(q);
+                        const uint8_t pf = tile[1 + dz][ly + 1 + dy][lx + 1 + dx];
+                        if (pf == LIQ || pf == IFC) {
+                            double d = (double)fi[opp(q)] - (double)fo(q);
+                            if (pf == IFC) {
+                                const int pc = wrapc(x + dx, nx) + nx * wrapc(y + dy, ny) + nxy * wrapc(z + dz, nz);
+                                d *= 0.5 * (D.phi_cur[pc] + phx);
+                            }
+                            dm += d;
+                        }
+                    }
                 }
             }
             const double mnew = D.m[c] + dm;
