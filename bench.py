@@ -164,6 +164,39 @@ def split_pass_cost(fsl, torch, w, reps=3):
     return round(prof["split"][0] / max(prof["split"][1], 1), 4)
 
 
+def bubble_regimes(fsl, W, torch, steps=8000, every=50, z_stop=70.0):
+    """Single rising bubbles in the regimes of Table tab:Annaland (free-slip sides,
+    no-slip floor, pressure at the top): the bubble Reynolds number Re = u d / nu from
+    the centroid's rise velocity over the last third of the run, d the diameter of a
+    sphere of the bubble's volume, beside the paper's numbers."""
+    out = {}
+    for case, p in W.BUBBLE_REGIMES.items():
+        w = W.bubble_regime(case)
+        nu = (w.tau - 0.5) / 3.0
+        s = fsl.Sim(w)
+        track = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t = 0
+        while t < steps:
+            s.step(every)
+            t += every
+            b = s.bubbles()
+            track.append((t, b[1]["centroid"][2], b[1]["V"], len([x for x in b if x["alive"]])))
+            if b[1]["centroid"][2] > z_stop:
+                break
+        dt = time.perf_counter() - t0
+        s.close()
+        tr = np.array(track)
+        k = max(2, len(tr) // 3)
+        u = np.polyfit(tr[-k:, 0], tr[-k:, 1], 1)[0]
+        d = (6.0 * tr[-k:, 2].mean() / np.pi) ** (1.0 / 3.0)
+        out[case] = {"re": round(float(u * d / nu), 3), "re_paper": p["re_paper"], "re_fan": p["re_fan"],
+                     "u": float(u), "d": round(float(d), 3), "steps": int(t), "bubbles_alive": int(tr[-1, 3]),
+                     "mlups": round(w.cells * t / dt / 1e6, 1)}
+    return out
+
+
 def cpu_baseline(w, steps):
     """The FP64 oracle on a bounded sample: the lowest 16 layers of the column."""
     import oracle
@@ -196,6 +229,8 @@ def main():
     ap.add_argument("--adjoint-only", action="store_true",
                     help="time only the differentiation form (for kernel profiles)")
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--regimes-only", action="store_true",
+                    help="only the single rising bubbles of the bubble-regime table")
     ap.add_argument("--traffic", default=TRAFFIC_FILE,
                     help="JSON file with measured HBM bytes per stream-collide launch")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
@@ -215,6 +250,12 @@ def main():
         print("no HIP device", file=sys.stderr)
         sys.exit(1)
     fsl.load_library()
+
+    if args.regimes_only:
+        from paper_1712_07028_amd import workloads as W
+
+        print(json.dumps({"bubble_regimes": bubble_regimes(fsl, W, torch)}), flush=True)
+        return
 
     if args.adjoint_only:
         from paper_1712_07028_amd import workloads as W
@@ -273,6 +314,7 @@ def main():
     adjoint = {}
     surface = None
     split = None
+    regimes = None
     if not args.no_forms:
         from paper_1712_07028_amd import workloads as W
 
@@ -298,6 +340,8 @@ def main():
         split = {"step_ms": breakdown.get("split"),
                  "labelling_pass_ms": split_pass_cost(fsl, torch, w.replace(storage=0))}
         log("bubble splitting", split)
+        regimes = bubble_regimes(fsl, W, torch)
+        log("bubble regimes", regimes)
 
     if args.calibrate_copy_gib > 0:
         nbytes = int(args.calibrate_copy_gib * (1 << 30))
@@ -335,6 +379,8 @@ def main():
         out["surface_tension"] = surface
     if split:
         out["bubble_splitting"] = split
+    if regimes:
+        out["bubble_regimes"] = regimes
     print(json.dumps(out), flush=True)
 
 

@@ -45,7 +45,7 @@ extern "C" {
 #define FSL_E_ARG (-1)       /* invalid argument or configuration            */
 #define FSL_E_HIP (-2)       /* a HIP runtime call failed                     */
 #define FSL_E_CAPACITY (-3)  /* a conversion/event list or table overflowed   */
-#define FSL_E_NUMERIC (-4)   /* NaN/Inf density or a collapsed bubble volume  */
+#define FSL_E_NUMERIC (-4)   /* NaN/Inf density or velocity                   */
 #define FSL_E_INVARIANT (-5) /* a liquid cell has a gas neighbour             */
 
 #define FSL_NOSLIP 0

@@ -451,7 +451,10 @@ static void bubbles_recompute(orc_ctx *c)
             c->brho[b] = c->bM[b] / c->bV[b];
             for (int a = 0; a < 3; ++a) c->bcent[3 * b + a] /= c->bV[b];
         } else if (c->bM[b] > 0.0) {
-            c->err |= ERR_VOL;
+            /* reading: a bubble whose gas volume has vanished no longer exists; its
+             * gas mass leaves the system (the liquid mass ledger is not involved) */
+            c->balive[b] = 0;
+            c->bM[b] = 0.0;
         }
     }
 }
@@ -461,7 +464,8 @@ static void bubbles_recompute(orc_ctx *c)
  * they are D3Q19 neighbours (the neighbourhood of the merge rule) and belong to the
  * same root bubble.  When the gas cells of a root fall into several components, the
  * component holding the lowest cell index keeps the bubble; every other component,
- * in order of its lowest cell index, becomes a bubble with the next unused id.  An
+ * in order of its lowest cell index, becomes a bubble with the lowest id that is not
+ * alive (never used, or merged away: merges relabel the cells to their root).  An
  * interface cell of the root goes with the component of its gas neighbours of that
  * root (the one with the lowest cell index if they differ); one without such a
  * neighbour stays with the bubble.  The gas mass is shared in proportion to the
@@ -479,6 +483,7 @@ static int split_bubbles(orc_ctx *c)
     int *parent = (int *)xcalloc((size_t)MB, sizeof(int));
     double *Vn = (double *)xcalloc((size_t)MB, sizeof(double));
     unsigned char *seen = (unsigned char *)xcalloc((size_t)MB, 1);
+    unsigned char *isnew = (unsigned char *)xcalloc((size_t)MB, 1);  /* ids taken by this split */
     int created = 0;
     for (int x = 0; x < N; ++x) lab[x] = nid[x] = newb[x] = -1;
     /* components: flood fill from the lowest unlabelled gas cell */
@@ -508,12 +513,17 @@ static int split_bubbles(orc_ctx *c)
             seen[r] = 1;
             continue;
         }
-        if (c->nb >= MB) {
+        /* the lowest id that is not alive: never used, or merged away */
+        int b = 1;
+        while (b < MB && (c->balive[b] || isnew[b])) ++b;
+        if (b >= MB) {
             c->err |= ERR_CAP;
             break;
         }
-        nid[x] = c->nb++;
-        parent[nid[x]] = r;
+        nid[x] = b;
+        isnew[b] = 1;
+        if (b >= c->nb) c->nb = b + 1;
+        parent[b] = r;
         ++created;
     }
     if (created) {
@@ -540,13 +550,14 @@ static int split_bubbles(orc_ctx *c)
         }
         for (int x = 0; x < N; ++x)
             if (newb[x] >= 0) c->bub[x] = newb[x];
-        /* masses: each new part at the density of its bubble */
+        /* masses: each new part at the density of its bubble (new ids in increasing
+         * order, which is the order of the parts) */
         for (int r = 0; r < MB; ++r) {
             if (!seen[r]) continue;
             const double Mr = c->bM[r];
             double taken = 0.0;
-            for (int b = c->nb - created; b < c->nb; ++b) {
-                if (parent[b] != r) continue;
+            for (int b = 1; b < MB; ++b) {
+                if (!isnew[b] || parent[b] != r) continue;
                 c->bM[b] = Mr * Vn[b] / c->bV[r];
                 c->bV0[b] = Vn[b];
                 c->broot[b] = b;
@@ -564,6 +575,7 @@ static int split_bubbles(orc_ctx *c)
     free(parent);
     free(Vn);
     free(seen);
+    free(isnew);
     return created;
 }
 
@@ -1262,6 +1274,7 @@ static void conversions(orc_ctx *c)
         else if (c->flag[x] == GAS) c->phi[x] = 0.0;
     }
     /* bubble merge through emptied cells */
+    int merged = 0;
     for (int x = 0; x < c->N; ++x) {
         if (c->conv[x] != CV_E) continue;
         int i, j, k;
@@ -1275,8 +1288,14 @@ static void conversions(orc_ctx *c)
             c->broot[hi] = lo;
             c->bM[lo] += c->bM[hi];
             c->balive[hi] = 0;
+            merged = 1;
         }
     }
+    /* after a merge every gas and interface cell carries its root id, so that the
+     * merged ids hold no cells and can be taken again by a split */
+    if (merged)
+        for (int x = 0; x < c->N; ++x)
+            if (c->flag[x] == GAS || c->flag[x] == IFC) c->bub[x] = find_root(c, c->bub[x]);
     for (int x = 0; x < c->N; ++x) c->conv[x] = CV_NONE;
 }
 

@@ -329,6 +329,7 @@ int enqueue_conversions(fsl_ctx *c) {
     hipLaunchKernelGGL(k_conv_excess<ST>, g, b, 0, c->st, c->G, c->Ph, D);
     hipLaunchKernelGGL(k_conv_fill<ST>, g, b, 0, c->st, c->G, c->Ph, D);
     hipLaunchKernelGGL(k_bubble_merge, dim3(1), dim3(64), 0, c->st, D);
+    hipLaunchKernelGGL(k_bubble_relabel, dim3(grid_for(c->G.N, 256, 2048)), b, 0, c->st, c->G, D);
     LAUNCHCHK(c);
     return FSL_OK;
 }
@@ -510,7 +511,6 @@ int read_error(fsl_ctx *c) {
     if (!e) return FSL_OK;
     if (e & ERR_CAP) return fail(c, FSL_E_CAPACITY, "a list, the bubble table or the gas-part list overflowed");
     if (e & ERR_NAN) return fail(c, FSL_E_NUMERIC, "NaN density or velocity");
-    if (e & ERR_VOL) return fail(c, FSL_E_NUMERIC, "a bubble volume collapsed to zero");
     if (e & ERR_LG) return fail(c, FSL_E_INVARIANT, "a liquid cell has a gas neighbour");
     return fail(c, FSL_E_NUMERIC, "device error");
 }

@@ -54,6 +54,7 @@ enum Counter {
     C_NF = 0, C_NE0, C_NE, C_NNG, C_NNL, C_NMERGE, C_NCOVER, C_NUNCOVER, C_NPAIRS, C_COVALL,
     C_SPLIT,  // splitting pass: 1 = label the gas, 2 = some bubble splits
     C_NCOMP,  // gas components listed by the splitting pass
+    C_MERGED, // some bubbles merged in this step: cells are relabelled to their roots
     C_COUNT
 };
 // persistent slot (not reset per step): number of bubble ids in use

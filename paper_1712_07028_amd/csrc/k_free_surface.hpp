@@ -292,6 +292,18 @@ __global__ void k_bubble_merge(Dev D) {
         D.broot[hi] = lo;
         D.btab[lo * B_STRIDE + B_M] += D.btab[hi * B_STRIDE + B_M];
         D.balive[hi] = 0;
+        D.counters[C_MERGED] = 1;
+    }
+}
+
+// after a merge every gas and interface cell carries its root id, so that the merged
+// ids hold no cells and a split can take them again
+__global__ void k_bubble_relabel(Geom G, Dev D) {
+    if (D.counters[C_MERGED] == 0) return;
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < G.N;
+         c += (long long)gridDim.x * blockDim.x) {
+        const uint8_t f = D.flags[c];
+        if (f == GAS || f == IFC) D.bub[c] = (uint16_t)bubble_root(D, D.bub[c]);
     }
 }
 
@@ -404,7 +416,10 @@ __global__ void k_bubble_finalize(Dev D, int init, const int *gate, int open) {
             t[B_C + 1] = a[2] / a[0];
             t[B_C + 2] = a[3] / a[0];
         } else if (t[B_M] > 0.0) {
-            atomicOr(D.err, ERR_VOL);
+            // a bubble whose gas volume has vanished no longer exists; its gas mass
+            // leaves (the liquid mass ledger is not involved)
+            D.balive[b] = 0;
+            t[B_M] = 0.0;
         }
     }
     __syncthreads();

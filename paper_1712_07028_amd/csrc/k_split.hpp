@@ -228,11 +228,11 @@ __global__ void k_ccl_flatten(Geom G, Dev D, SplitBuf B) {
 }
 
 // parts in order of their lowest cell index: the first part of each root keeps it,
-// the others take the next unused ids
+// the others take the lowest ids that are not alive
 __global__ __launch_bounds__(1024) void k_split_plan(Dev D, SplitBuf B, int open) {
     if (D.counters[C_SPLIT] == 0) return;
     __shared__ int sorted[SPLIT_MAXC];
-    __shared__ unsigned char seen[64];
+    __shared__ unsigned char seen[64], taken[64];
     if (D.counters[C_NCOMP] > SPLIT_MAXC) {  // not every part listed: no split, error set
         if (threadIdx.x == 0) D.counters[C_SPLIT] = 1;
         return;
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(1024) void k_split_plan(Dev D, SplitBuf B, int open
         for (int j = 0; j < n; ++j) rank += B.comp[j] < v;
         sorted[rank] = v;
     }
-    for (int i = threadIdx.x; i < 64; i += blockDim.x) seen[i] = 0;
+    for (int i = threadIdx.x; i < 64; i += blockDim.x) seen[i] = taken[i] = 0;
     __syncthreads();
     if (threadIdx.x) return;
     int used = D.counters[C_BUSED], any = 0;
@@ -256,11 +256,19 @@ __global__ __launch_bounds__(1024) void k_split_plan(Dev D, SplitBuf B, int open
             // every part of an open atmosphere stays at the outlet
         } else if (!seen[r]) {
             seen[r] = 1;
-        } else if (used < D.maxB) {
-            id = used++;
-            any = 1;
         } else {
-            atomicOr(D.err, ERR_CAP);
+            // the lowest id that is not alive: never used, or merged away (merges
+            // relabel the cells to their roots)
+            int b = 1;
+            while (b < D.maxB && (D.balive[b] || taken[b])) ++b;
+            if (b < D.maxB) {
+                id = b;
+                taken[b] = 1;
+                used = max(used, b + 1);
+                any = 1;
+            } else {
+                atomicOr(D.err, ERR_CAP);
+            }
         }
         B.cid[k] = id;
         B.parent[k] = r;

@@ -179,3 +179,34 @@ def slab_of(w: Workload, nz: int) -> Workload:
                       rho_p=p.rho_p[keep])
     zs = w.zs if w.zs < nz else -1.0
     return w.replace(n=(w.n[0], w.n[1], nz), particles=p, zs=zs)
+
+
+# Bubble regimes of Table tab:Annaland (Sec. 3.2): viscosity mu [Pa s], surface
+# tension sigma [N/m] and gravity g [m/s^2] for a liquid of 1000 kg/m^3, on a grid of
+# dx = 1e-3 m and dt = 1e-4 s; the Reynolds numbers the paper gives (Eq. Fan and its
+# own simulations) are kept beside them for comparison.
+BUBBLE_REGIMES = {
+    "A_spherical": dict(mu=0.25, sigma=0.145, g=0.981, re_fan=1.66, re_paper=1.76),
+    "B_ellipsoidal": dict(mu=0.42, sigma=0.145, g=9.81, re_fan=4.18, re_paper=4.43),
+    "C_skirted": dict(mu=0.13211, sigma=0.014545, g=9.81, re_fan=18.56, re_paper=14.53),
+    "D_dimpled": dict(mu=0.75, sigma=0.014545, g=9.81, re_fan=1.58, re_paper=1.46),
+}
+
+
+def bubble_regime(case: str, n=(40, 40, 100), R=6.0, zs=98.0) -> Workload:
+    """A bubble of radius R at (n_x/2, n_y/2, 10) in a liquid column (the set-up of
+    Fig. bubbleSetup): free-slip sides, no-slip floor, the gas above the liquid held
+    at rho_g0 = 1 (pressure at the top).  Lattice units from dx = 1e-3 m, dt = 1e-4 s,
+    rho = 1000 kg/m^3: nu = mu/rho dt/dx^2, g dt^2/dx, sigma dt^2/(rho dx^3).  The
+    bubble starts at the liquid pressure at its centre plus the Laplace jump 2 sigma/R
+    (density form: times 3)."""
+    p = BUBBLE_REGIMES[case]
+    dx, dt, rho = 1e-3, 1e-4, 1000.0
+    nu = p["mu"] / rho * dt / dx ** 2
+    g = p["g"] * dt ** 2 / dx
+    sigma = p["sigma"] * dt ** 2 / (rho * dx ** 3)
+    zc = 10.0
+    rho_b = 1.0 + 3.0 * g * (zs - zc) + 6.0 * sigma / R
+    return Workload(name=f"regime_{case}", n=tuple(n), trt=True, tau=3.0 * nu + 0.5, g=(0.0, 0.0, -g), zs=zs,
+                    steps=0, gas_spheres=[((n[0] - 1) / 2.0, (n[1] - 1) / 2.0, zc, R, rho_b)], sigma=sigma,
+                    freeslip=(1, 1, 0), open_atmosphere=True)

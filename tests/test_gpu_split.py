@@ -151,3 +151,48 @@ def test_neck_cut_by_a_sphere():
     assert stepped(o, s, st["w"], 30, "coverage") is not None
     o.close()
     s.close()
+
+
+def copy_fields(o, s):
+    for fo, fg in ((O.FLAGS, fsl.FIELD_FLAGS), (O.F, fsl.FIELD_F), (O.MASS, fsl.FIELD_MASS),
+                   (O.PHI, fsl.FIELD_PHI), (O.BUBBLE_ID, fsl.FIELD_BUBBLE_ID), (O.PID, fsl.FIELD_PID)):
+        s.set(fg, o.get(fo))
+
+
+def test_split_takes_the_lowest_id_not_alive():
+    n = (20, 14, 24)
+    gas = ball(n, (9.3, 7.0, 6.0), 2.6) | ball(n, (10.0, 6.5, 16.0), 3.4)
+    o, st = hand_state(n, gas, rho_g=1.02)
+    s = fsl.Sim(st["w"])
+    copy_fields(o, s)
+    for x in (o, s):
+        x.bubbles_set([0.0, st["M"], 0.0, 0.0], [0, 1, 2, 3], [0, 1, 0, 0])
+    assert compare_bubbles(o, s) == 4
+    o.close()
+    s.close()
+
+
+def test_merge_relabels_cells_to_the_root():
+    n = (18, 12, 12)
+    gas = np.zeros((12, 12, 18), bool)
+    gas[4:8, 4:8, 2:6] = True
+    gas[4:8, 4:8, 7:11] = True
+    z, y, x = np.nonzero(interface_of(gas))
+    o, st = hand_state(n, gas, phi_ifc=np.where(x == 6, 0.0, 0.5))
+    ids = o.get(O.BUBBLE_ID)
+    X = np.arange(18)[None, None, :]
+    ids[(st["gas"] | st["ifc"]) & (X >= 7)] = 2
+    o.set(O.BUBBLE_ID, ids)
+    m1 = (st["gas"] & (X < 7)).sum() + (1.0 - st["phi"])[st["ifc"] & (X < 7)].sum()
+    s = fsl.Sim(st["w"])
+    copy_fields(o, s)
+    for x in (o, s):
+        x.bubbles_set([0.0, m1, st["V"] - m1], [0, 1, 2], [0, 1, 1])
+    o.step(1)
+    s.step(1)
+    s.sync()
+    compare_step(o, s, st["w"])
+    assert compare_bubbles(o, s, rtol=1e-6) == 3
+    assert set(np.unique(s.get(fsl.FIELD_BUBBLE_ID)[(s.get(fsl.FIELD_FLAGS) == fsl.GAS)])) == {1}
+    o.close()
+    s.close()

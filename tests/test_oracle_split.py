@@ -221,3 +221,47 @@ def test_particle_cuts_a_gas_neck():
     assert 6.5 < zp < 10.5, zp                        # the sphere sits in the neck
     assert abs(o.mass()[0] / M0 - 1.0) < 1e-12
     o.close()
+
+
+def test_split_takes_the_lowest_id_not_alive():
+    """Ids 2 and 3 exist in the table but are not alive: the part that splits off
+    takes id 2, not a new id 4."""
+    n = (20, 14, 24)
+    gas = ball(n, (9.3, 7.0, 6.0), 2.6) | ball(n, (10.0, 6.5, 16.0), 3.4)
+    o, st = hand_state(n, gas, rho_g=1.02)
+    o.bubbles_set([0.0, st["M"], 0.0, 0.0], [0, 1, 2, 3], [0, 1, 0, 0])
+    b = o.bubbles()
+    assert len(b) == 4 and b[2]["alive"] and not b[3]["alive"]
+    ids = o.get(O.BUBBLE_ID)
+    assert set(np.unique(ids[st["gas"]])) == {1, 2}
+    o.close()
+
+
+def test_merge_relabels_cells_to_the_root():
+    """Two bubbles (ids 1 and 2) separated by one layer of empty interface cells: the
+    layer empties, the bubbles merge (root 1, masses add) and every gas and interface
+    cell then carries id 1; id 2 is free again."""
+    n = (18, 12, 12)
+    gas = np.zeros((12, 12, 18), bool)
+    gas[4:8, 4:8, 2:6] = True
+    gas[4:8, 4:8, 7:11] = True
+    ifc = interface_of(gas)
+    z, y, x = np.nonzero(ifc)
+    layer = x == 6
+    o, st = hand_state(n, gas, phi_ifc=np.where(layer, 0.0, 0.5))
+    ids = o.get(O.BUBBLE_ID)
+    X = np.arange(18)[None, None, :]
+    ids[(st["gas"] | st["ifc"]) & (X >= 7)] = 2
+    o.set(O.BUBBLE_ID, ids)
+    m1 = (st["gas"] & (X < 7)).sum() + (1.0 - st["phi"])[st["ifc"] & (X < 7)].sum()
+    m2 = st["V"] - m1
+    o.bubbles_set([0.0, m1, m2], [0, 1, 2], [0, 1, 1])
+    assert len(o.bubbles()) == 3 and o.bubbles()[2]["alive"]
+    o.step(1)
+    b = o.bubbles()
+    fl, ids = o.get(O.FLAGS), o.get(O.BUBBLE_ID)
+    sel = (fl == O.GAS) | (fl == O.IFC)
+    assert set(np.unique(ids[sel])) == {1}
+    assert b[1]["alive"] and not b[2]["alive"]
+    assert abs(b[1]["M"] / st["V"] - 1.0) < 1e-14
+    o.close()
