@@ -245,6 +245,9 @@ __global__ __launch_bounds__(256) void k_solid_pairs(Geom G, Dev D, int pcap) {
                     const double e0 = i - to[P_X], e1 = j - to[P_X + 1], e2 = kk - to[P_X + 2];
                     if (e0 * e0 + e1 * e1 + e2 * e2 > ro) continue;
                 }
+                // a node of Pp lies inside Pp and a node of Po inside Po (coverage takes
+                // the same inside test), so cells that fail it need no loads
+                if (!inside(i, j, kk, tp + P_X, tp[P_R])) continue;
                 const int c = i + G.nx * (j + G.ny * kk);
                 if (D.flags[c] != SOL || D.pid[c] != Pp) continue;
                 const double rx = i - tp[P_X], ry = j - tp[P_X + 1], rz = kk - tp[P_X + 2];
@@ -254,6 +257,7 @@ __global__ __launch_bounds__(256) void k_solid_pairs(Geom G, Dev D, int pcap) {
                 const double uu = ur0 * ur0 + ur1 * ur1 + ur2 * ur2;
                 const double ox = i - to[P_X], oy = j - to[P_X + 1], oz = kk - to[P_X + 2];
                 for (int q = 1; q < Q; ++q) {
+                    if (!inside(i + cx(q), j + cy(q), kk + cz(q), to + P_X, to[P_R])) continue;
                     const int nb = nbr_idx(G, i, j, kk, q, 1);
                     if (nb < 0 || D.flags[nb] != SOL || D.pid[nb] != Po) continue;
                     const double cu = cx(q) * ur0 + cy(q) * ur1 + cz(q) * ur2;
