@@ -372,7 +372,7 @@ int enqueue_pair_forces(fsl_ctx *c) {
         hipLaunchKernelGGL(k_gscan_apply, dim3(nb), dim3(256), 0, c->st, D, c->ncell, chunk, (const int *)bsum);
     }
     hipLaunchKernelGGL(k_grid_fill, dim3(grid_for(np)), dim3(256), 0, c->st, D, c->PG);
-    hipLaunchKernelGGL(k_pairs, dim3(grid_for((long long)np * 27)), dim3(256), 0, c->st, D, c->PG, c->L.pcap);
+    hipLaunchKernelGGL(k_pairs, dim3(grid_for((long long)np * 27, 256, 2048)), dim3(256), 0, c->st, D, c->PG, c->L.pcap);
     hipLaunchKernelGGL(k_solid_pairs, dim3(grid_for(c->L.pcap, 4, 8192)), dim3(256), 0, c->st, c->G, D, c->L.pcap);
     hipLaunchKernelGGL(k_part_forces, dim3((np + 255) / 256), dim3(256), 0, c->st, D, c->cfg.integrate);
     LAUNCHCHK(c);

@@ -187,9 +187,21 @@ __device__ __forceinline__ void wave_push2(bool pred, int a, int b, int *list, i
 }
 
 // one thread per particle and neighbouring grid cell (27 per particle), so that the
-// dependent loads of the cell lists overlap across many threads
-__global__ void k_pairs(Dev D, PGrid PG, int pcap) {
-    GRID_STRIDE(idx, D.np * 27) {
+// dependent loads of the cell lists overlap across many threads.  Pairs are sparse
+// (about one per wave), so they are gathered per block in LDS and appended with one
+// atomic per block: one atomic per pair on the same counter serialises.
+constexpr int PAIR_BUF = 1024;
+
+__global__ __launch_bounds__(256) void k_pairs(Dev D, PGrid PG, int pcap) {
+    __shared__ int2 buf[PAIR_BUF];
+    __shared__ int cnt, base;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    const int total = D.np * 27;
+    // whole blocks take the same rounds, so every thread reaches the barriers below
+    for (int r = blockIdx.x * blockDim.x; r < total; r += gridDim.x * blockDim.x) {
+        const int idx = r + threadIdx.x;
+        if (idx >= total) continue;
         const int P = idx / 27, d = idx - 27 * P;
         const double *x = D.ptab + (long long)P * P_STRIDE;
         const int a = pgrid_cell(PG, x, 0) + d % 3 - 1, b = pgrid_cell(PG, x, 1) + (d / 3) % 3 - 1,
@@ -202,8 +214,24 @@ __global__ void k_pairs(Dev D, PGrid PG, int pcap) {
             const double *y = D.ptab + (long long)Qp * P_STRIDE;
             const double d0 = y[0] - x[0], d1 = y[1] - x[1], d2 = y[2] - x[2];
             const double gap = sqrt(d0 * d0 + d1 * d1 + d2 * d2) - x[P_R] - y[P_R];
-            wave_push2(gap < PG.reach, P, Qp, (int *)D.pairs, D.counters + C_NPAIRS, pcap, D.err);
+            if (gap >= PG.reach) continue;
+            const int k = atomicAdd(&cnt, 1);
+            if (k < PAIR_BUF) {
+                buf[k] = make_int2(P, Qp);
+            } else {  // the block's buffer is full: straight to the list
+                const int g = atomicAdd(D.counters + C_NPAIRS, 1);
+                if (g < pcap) D.pairs[g] = make_int2(P, Qp);
+                else atomicOr(D.err, ERR_CAP);
+            }
         }
+    }
+    __syncthreads();
+    const int n = min(cnt, PAIR_BUF);
+    if (threadIdx.x == 0) base = n ? atomicAdd(D.counters + C_NPAIRS, n) : 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        if (base + k < pcap) D.pairs[base + k] = buf[k];
+        else atomicOr(D.err, ERR_CAP);
     }
 }
 
