@@ -110,7 +110,7 @@ Layout layout_of(const fsl_config *c) {
     L.counters = take(64 * 4);
     L.ctl = take(64 * 8);  // [0] err word, [8] ledger, [16..] mass sums
     L.ptab = take((size_t)L.maxP * P_STRIDE * 8);
-    L.pacc = take((size_t)L.maxP * ACC_STRIDE * 8);
+    L.pacc = take((size_t)L.maxP * ACC_COPIES * ACC_STRIDE * 8);
     L.pFT = take((size_t)L.maxP * 6 * 8);
     L.pFTp = take((size_t)L.maxP * 6 * 8);
     L.pFl = take((size_t)L.maxP * 3 * 8);
@@ -577,8 +577,8 @@ int window_backward(fsl_ctx *c, double dJ, double *dJ_dtau, double *dJ_dg) {
     Dr.pacc = A.dummy;
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)A.nTiles * ADJ_NPART)), dim3(256), 0, c->st, A.part,
                        (long long)A.nTiles * ADJ_NPART, 0.0);
-    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)c->L.maxP * ACC_STRIDE)), dim3(256), 0, c->st, A.dummy,
-                       (long long)c->L.maxP * ACC_STRIDE, 0.0);
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)c->L.maxP * ACC_COPIES * ACC_STRIDE)), dim3(256), 0, c->st, A.dummy,
+                       (long long)c->L.maxP * ACC_COPIES * ACC_STRIDE, 0.0);
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(lat, 256, 8192)), dim3(256), 0, c->st, (int *)A.mu[0], lat, 0);
     int cur = 0;  // mu[cur] holds mu_{t+1}
     const int nseg = (T + k - 1) / k;
@@ -733,8 +733,8 @@ int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, 
     if (L.nKT > 0)  // curvature tile flags: zero between steps
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(L.nKT)), dim3(256), 0, c->st, (int *)(w + L.ktf),
                            (long long)L.nKT, 0);
-    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)L.maxP * ACC_STRIDE)), dim3(256), 0, c->st,
-                       D.pacc, (long long)L.maxP * ACC_STRIDE, 0.0);
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)L.maxP * ACC_COPIES * ACC_STRIDE)), dim3(256), 0, c->st,
+                       D.pacc, (long long)L.maxP * ACC_COPIES * ACC_STRIDE, 0.0);
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)L.maxP * 6)), dim3(256), 0, c->st, D.pFT,
                        (long long)L.maxP * 6, 0.0);
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)L.maxP * 6)), dim3(256), 0, c->st, D.pFTp,
@@ -813,8 +813,8 @@ int fsl_particles_set(fsl_ctx *c, int n, const double *x, const double *u, const
     Dev &D = c->D;
     D.np = n;
     c->have_prev = 0;
-    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)c->L.maxP * ACC_STRIDE)), dim3(256), 0, c->st,
-                       D.pacc, (long long)c->L.maxP * ACC_STRIDE, 0.0);
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)c->L.maxP * ACC_COPIES * ACC_STRIDE)), dim3(256), 0, c->st,
+                       D.pacc, (long long)c->L.maxP * ACC_COPIES * ACC_STRIDE, 0.0);
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)c->L.maxP * 6)), dim3(256), 0, c->st, D.pFT,
                        (long long)c->L.maxP * 6, 0.0);
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)c->L.maxP * 6)), dim3(256), 0, c->st, D.pFTp,

@@ -66,6 +66,13 @@ constexpr int C_BUSED = 63;
 enum PSlot { P_X = 0, P_U = 3, P_W = 6, P_R = 9, P_RHO = 10, P_XOLD = 11, P_OVL = 14, P_STRIDE = 16 };
 // particle accumulators: F(3) T(3) dm(1) pad -> 8 doubles
 constexpr int ACC_STRIDE = 8;
+// copies of each particle's accumulator: the waves that touch one sphere add into
+// different copies (by block), so their FP64 atomics do not queue on one cache line;
+// the force pass sums the copies in a fixed order
+constexpr int ACC_COPIES = 8;
+__host__ __device__ constexpr long long acc_at(int P, int copy) {
+    return ((long long)P * ACC_COPIES + copy) * ACC_STRIDE;
+}
 // bubble table: 16 doubles per id
 enum BSlot { B_M = 0, B_V = 1, B_RHO = 2, B_C = 3, B_V0 = 6, B_NGAS = 7, B_NIF = 8, B_STRIDE = 16 };
 // bubble accumulators: V, Vx, Vy, Vz, n_gas, n_iface

@@ -54,7 +54,7 @@ inline size_t adjoint_window_bytes(int T, int k, size_t S, int maxP, int nTiles)
     const int ncp = (T + k - 1) / k;
     const int nseg = (k < T ? k : T) - 1;
     return adj_up(st) * (ncp + nseg + 2) + adj_up((size_t)nTiles * ADJ_NPART * 8) + adj_up(64 * 8) +
-           adj_up((size_t)(maxP > 0 ? maxP : 1) * 16) + adj_up((size_t)(maxP > 0 ? maxP : 1) * ACC_STRIDE * 8);
+           adj_up((size_t)(maxP > 0 ? maxP : 1) * 16) + adj_up((size_t)(maxP > 0 ? maxP : 1) * ACC_COPIES * ACC_STRIDE * 8);
 }
 
 inline void adjoint_bind(AdjointState &A, char *base, size_t bytes, int T, int k, long long S, int maxP,

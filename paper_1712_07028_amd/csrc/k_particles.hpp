@@ -18,17 +18,22 @@ __global__ __launch_bounds__(256) void k_part_forces(Dev D, int integrate) {
     int P = blockIdx.x * blockDim.x + threadIdx.x;
     double dm = 0.0;
     if (P < D.np) {
-        double *a = D.pacc + (long long)P * ACC_STRIDE;
+        double *a = D.pacc + acc_at(P, 0);
         double *o = D.pFT + (long long)P * 6;
         double *op = D.pFTp + (long long)P * 6;
+        double s[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) s[k] = a[k];
+        for (int j = 1; j < ACC_COPIES; ++j)
+#pragma unroll
+            for (int k = 0; k < 7; ++k) s[k] += a[j * ACC_STRIDE + k];
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             op[k] = o[k];
-            o[k] = a[k];
+            o[k] = s[k];
         }
-        dm = a[6];
-#pragma unroll
-        for (int k = 0; k < ACC_STRIDE; ++k) a[k] = 0.0;
+        dm = s[6];
+        for (int k = 0; k < ACC_COPIES * ACC_STRIDE; ++k) a[k] = 0.0;
         if (integrate) {
             double *t = D.ptab + (long long)P * P_STRIDE;
             t[P_XOLD] = t[P_X];
@@ -300,7 +305,7 @@ __global__ __launch_bounds__(256) void k_solid_pairs(Geom G, Dev D, int pcap) {
                 }
             }
         }
-        double *dst = D.pacc + (long long)Po * ACC_STRIDE;
+        double *dst = D.pacc + acc_at(Po, k & (ACC_COPIES - 1));
         for (int a = 0; a < 6; ++a) {
             const double v = wave_sum(acc[a]);
             if (lane == 0 && v != 0.0) unsafeAtomicAdd(dst + a, v);

@@ -57,7 +57,7 @@ __device__ __noinline__ void acc_flush_v(double *pacc, int P, float fs0, float f
                          (double)fs2 + (ca2 * (1.0 / 9.0) + cd2 * (1.0 / 18.0))};
     const double a[7] = {F[0], F[1], F[2], ry * F[2] - rz * F[1], rz * F[0] - rx * F[2],
                          rx * F[1] - ry * F[0], (double)dm};
-    double *dst = pacc + (long long)P * ACC_STRIDE;
+    double *dst = pacc + acc_at(P, blockIdx.x & (ACC_COPIES - 1));
     for (int k = 0; k < 7; ++k) unsafeAtomicAdd(dst + k, a[k]);
 }
 __device__ __forceinline__ void acc_flush(const Dev &D, const LinkAcc &L, int x, int y, int z) {
@@ -137,7 +137,13 @@ __device__ __forceinline__ void acc_reduce_wave(const Dev &D, const LinkAcc &L, 
         const double dms = wave_total_f(mine ? L.dm : 0.f);
         const int q0 = wave_total_i(mine ? p0 : 0), q1 = wave_total_i(mine ? p1 : 0), q2 = wave_total_i(mine ? p2 : 0);
         const int s0 = wave_total_i(mine ? r0 : 0), s1 = wave_total_i(mine ? r1 : 0), s2 = wave_total_i(mine ? r2 : 0);
-        if ((int)lane_id() == leader) {
+        // the sums are uniform; lanes 0-6 each add one component, so one atomic
+        // instruction serves the segment (the fraction is the leader's particle's)
+        const float fl0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(L.fr[0]), leader));
+        const float fl1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(L.fr[1]), leader));
+        const float fl2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(L.fr[2]), leader));
+        const int ln = (int)lane_id();
+        if (ln < 7) {
             int a0, d0, a1, d1, a2, d2, ta, tb, tc, te, tf, tg;
             unpack2(q0, a0, d0);
             unpack2(q1, a1, d1);
@@ -152,17 +158,15 @@ __device__ __forceinline__ void acc_reduce_wave(const Dev &D, const LinkAcc &L, 
             const double Ta[3] = {T0s + (ta * (1.0 / 9.0) + tb * (1.0 / 18.0)),
                                   T1s + (tc * (1.0 / 9.0) + te * (1.0 / 18.0)),
                                   T2s + (tf * (1.0 / 9.0) + tg * (1.0 / 18.0))};
-            const double f0 = L.fr[0], f1 = L.fr[1], f2 = L.fr[2];
-            const double T[3] = {Ta[0] - (f1 * F[2] - f2 * F[1]), Ta[1] - (f2 * F[0] - f0 * F[2]),
-                                 Ta[2] - (f0 * F[1] - f1 * F[0])};
-            double *dst = D.pacc + (long long)k0 * ACC_STRIDE;
-            unsafeAtomicAdd(dst + 0, F[0]);
-            unsafeAtomicAdd(dst + 1, F[1]);
-            unsafeAtomicAdd(dst + 2, F[2]);
-            unsafeAtomicAdd(dst + 3, T[0]);
-            unsafeAtomicAdd(dst + 4, T[1]);
-            unsafeAtomicAdd(dst + 5, T[2]);
-            unsafeAtomicAdd(dst + 6, dms);
+            const double f0 = fl0, f1 = fl1, f2 = fl2;
+            const double v = ln == 0 ? F[0]
+                           : ln == 1 ? F[1]
+                           : ln == 2 ? F[2]
+                           : ln == 3 ? Ta[0] - (f1 * F[2] - f2 * F[1])
+                           : ln == 4 ? Ta[1] - (f2 * F[0] - f0 * F[2])
+                           : ln == 5 ? Ta[2] - (f0 * F[1] - f1 * F[0])
+                                     : dms;
+            unsafeAtomicAdd(D.pacc + acc_at(k0, blockIdx.x & (ACC_COPIES - 1)) + ln, v);
         }
         if (mine) key = -1;
     }
