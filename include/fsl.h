@@ -19,8 +19,8 @@
  * moving-wall bounce-back and momentum exchange.
  *
  * Conventions (shared with the oracle by specification):
- *   cell index     i + nx*(j + ny*k); node (i,j,k) sits at (i,j,k); no-slip walls
- *                  are half-way, at -1/2 and n-1/2 on non-periodic axes
+ *   cell index     i + nx*(j + ny*k); node (i,j,k) sits at (i,j,k); walls (no-slip
+ *                  or free-slip) are half-way, at -1/2 and n-1/2 on non-periodic axes
  *   directions     0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..18 = (+-1,+-1,0),
  *                  (+-1,0,+-1), (0,+-1,+-1) in sign order (+,+),(+,-),(-,+),(-,-)
  *   flag values    0 gas, 1 liquid, 2 interface, 3 particle-covered
@@ -130,11 +130,13 @@ int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, 
  * (Eq. lubrication, substeps) and the bubble model (end of Sec. 2.2): gas volumes
  * and densities, merges, and splitting: where the gas of a bubble falls apart
  * (D3Q19 neighbours of one root bubble), the part with the lowest cell index keeps
- * the id, the others take the next unused ids in order of their lowest cell index,
- * interface cells follow the part of their gas neighbours, and the gas mass is
- * shared by volume.  A split that needs more ids than max_bubbles, or a state with
- * more than 1024 separate gas parts, is reported as FSL_E_CAPACITY by the next
- * synchronising call. */
+ * the id, the others take the lowest ids that are not alive, in order of their
+ * lowest cell index, interface cells follow the part of their gas neighbours, and
+ * the gas mass is shared by volume.  After a merge every gas and interface cell
+ * carries its root id, so merged ids are free again.  A bubble whose gas volume
+ * vanishes no longer exists (its gas mass leaves).  A split that needs more live
+ * bubbles than max_bubbles, or a state with more than 1024 separate gas parts, is
+ * reported as FSL_E_CAPACITY by the next synchronising call. */
 int fsl_step(fsl_ctx *ctx, int n);
 
 /* Replace the particle table with n spheres (arrays n x 3: centres in node
