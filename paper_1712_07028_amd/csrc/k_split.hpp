@@ -4,7 +4,8 @@
 // Two gas cells are connected when they are D3Q19 neighbours (the neighbourhood of
 // the merge rule) and belong to the same root bubble.  Where the gas of a root falls
 // into several parts, the part holding the lowest cell index keeps the bubble and
-// the others, in order of their lowest cell index, take the next unused ids; an
+// the others, in order of their lowest cell index, take the lowest ids that are not
+// alive (merges relabel the cells to their roots, so merged ids are free); an
 // interface cell goes with the part of its gas neighbours (the lowest when they
 // differ) and stays with the bubble without any; the gas mass is shared in
 // proportion to the parts' volumes (gas cells plus 1 - phi of their interface
