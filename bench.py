@@ -10,8 +10,11 @@ bounded sample of the same workload on the host cores.
 
 Also reported: the storage forms (shifted binary16 / bfloat16 populations) on the
 same column with their error against the oracle on the 128^3 pool with 1,400
-spheres after 1,000 steps, and the differentiation form (adjoint MLUPS of the
-summed-drag window, 64^3 and 256^3).
+spheres after 1,000 steps; the differentiation form (adjoint MLUPS of the
+summed-drag window, 64^3 and 256^3); the column with surface tension (curvature
+pass); the bubble-splitting test and labelling pass; single rising bubbles in the
+four regimes of the bubble-regime table; and a plain device copy's bandwidth beside
+the roofline.
 """
 from __future__ import annotations
 
@@ -197,6 +200,25 @@ def bubble_regimes(fsl, W, torch, steps=8000, every=50, z_stop=70.0):
     return out
 
 
+def copy_bandwidth(torch, gib=2.0, reps=5):
+    """A plain device copy of a large buffer on the same GPU, for context beside the
+    roofline: bytes read plus bytes written over the copy time (HIP events)."""
+    n = int(gib * (1 << 30))
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return round(2.0 * n / (ms / 1e3) / 1e9, 1)
+
+
 def cpu_baseline(w, steps):
     """The FP64 oracle on a bounded sample: the lowest 16 layers of the column."""
     import oracle
@@ -305,7 +327,8 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
             "kernel": "k_stream_collide", "kernel_ms": round(avg_s * 1e3, 4),
-            "algorithmic_bytes_per_launch": int(alg_bytes), "active_cells": n_active}
+            "algorithmic_bytes_per_launch": int(alg_bytes), "active_cells": n_active,
+            "copy_GBs": copy_bandwidth(torch)}
     breakdown = {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()}
     log(f"{mlups:.0f} MLUPS, stream-collide {avg_s * 1e3:.3f} ms, {achieved:.0f} GB/s, "
         f"breakdown ms/step {breakdown}")
