@@ -46,6 +46,8 @@ def workload(name, storage):
 
     if name == "column":
         w = W.bubble_column_large()
+    elif name == "column_nospheres":
+        w = W.bubble_column_large().replace(particles=None, name="column512x512x1024_bubble40_no_spheres")
     elif name == "bed128":
         w = W.bubble_bed_128()
     elif name == "pool32":
@@ -256,8 +258,9 @@ def main():
     ap.add_argument("--traffic", default=TRAFFIC_FILE,
                     help="JSON file with measured HBM bytes per stream-collide launch")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
-                    help="after the run, copy a buffer of this many GiB three times (plain "
-                         "device copy of known size, for scaling hardware byte counters)")
+                    help="after the run, copy a buffer of this many GiB three times with the "
+                         "runtime's copy and three times 4 bytes per lane (device copies of known "
+                         "size, for scaling hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -372,9 +375,14 @@ def main():
         b2 = torch.empty_like(a)
         for _ in range(3):
             b2.copy_(a)
+        # the same bytes moved with 4 bytes per lane: views one float off the
+        # allocation's alignment keep torch's elementwise kernel from vectorising
+        a32, b32 = a.view(torch.float32)[1:], b2.view(torch.float32)[1:]
+        for _ in range(3):
+            torch.mul(a32, 1.0, out=b32)
         torch.cuda.synchronize()
-        log(f"copy calibration: 3 copies of {nbytes} bytes")
-        del a, b2
+        log(f"copy calibration: 3 copies of {nbytes} bytes, then 3 of {nbytes - 4} bytes 4 bytes per lane")
+        del a, b2, a32, b32
         torch.cuda.empty_cache()
 
     cpu = None
