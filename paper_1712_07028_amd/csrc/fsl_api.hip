@@ -39,6 +39,7 @@ struct Layout {
     size_t counters, ctl, ptab, pacc, pFT, pFTp, pFl, pmir, gStart, gCount, gIdx, gBsum;
     size_t btab, bacc, broot, balive, rhog, kappa, ktf, klist, kcount, wallu, stage;
     size_t slab, scomp, scid, spar, svol;  // bubble splitting
+    size_t rhow;  // densities of the general path's cells for the next launch
     size_t win;  // differentiation window storage
     size_t total;
     long long S;
@@ -115,6 +116,7 @@ Layout layout_of(const fsl_config *c) {
     L.pFTp = take((size_t)L.maxP * 6 * 8);
     L.pFl = take((size_t)L.maxP * 3 * 8);
     L.pmir = take((size_t)L.maxP * 64);
+    L.rhow = take(c->max_particles > 0 ? (size_t)L.S * 8 : 0);
     L.gStart = take((size_t)(L.ncellMax + 1) * 4);
     L.gCount = take((size_t)L.ncellMax * 4);
     L.gIdx = take((size_t)L.maxP * 4);
@@ -164,6 +166,8 @@ struct fsl_ctx {
     int tilesX, tilesY, nTiles;
     int profiling;
     int have_prev;  // a previous step's hydrodynamic force exists (particle update)
+    int stamp;      // stamp of the next stream-collide launch (>= 1)
+    int rhow_ok;    // entries stamped stamp - 1 hold the densities of the populations in A
     std::vector<hipEvent_t> evpool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> evlog;
     double prof_ms[NPROF];
@@ -438,11 +442,22 @@ int enqueue_steps(fsl_ctx *c, int n, int split) {
             ProfScope ps(c, 6);
             enqueue_curvature(c);
         }
+        D.st_prev = c->rhow_ok ? c->stamp - 1 : -1;
+        D.st_cur = c->stamp;
         {
             ProfScope ps(c, 0);
             launch_stream_collide<ST>(c, D);
         }
         LAUNCHCHK(c);
+        if (++c->stamp >= (1 << 30)) {  // restart the stamps on entries that all read 0
+            c->stamp = 1;
+            c->rhow_ok = 0;
+            if (D.rhow)
+                hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * c->G.S, 256, 8192)), dim3(256), 0, c->st,
+                                   (int *)D.rhow, 2 * c->G.S, 0);
+        } else {
+            c->rhow_ok = 1;
+        }
         int rc = enqueue_conversions<ST>(c);
         if (rc) return rc;
         if (D.np > 0) {
@@ -574,6 +589,7 @@ int window_backward(fsl_ctx *c, double dJ, double *dJ_dtau, double *dJ_dg) {
     const size_t stride = adj_up((size_t)Q * c->G.S * 4) / 4;
     const long long lat = (long long)Q * c->G.S;
     Dev Dr = c->D;
+    Dr.st_prev = Dr.st_cur = -1;  // recomputed segments neither use nor leave stored densities
     Dr.pacc = A.dummy;
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((long long)A.nTiles * ADJ_NPART)), dim3(256), 0, c->st, A.part,
                        (long long)A.nTiles * ADJ_NPART, 0.0);
@@ -688,6 +704,13 @@ int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, 
     D.rhog = (float *)(w + L.rhog);
     D.kappa = cfg->sigma != 0.0 ? (float *)(w + L.kappa) : nullptr;
     D.wallu = (float *)(w + L.wallu);
+    D.rhow = cfg->max_particles > 0 ? (int2 *)(w + L.rhow) : nullptr;
+    D.st_prev = D.st_cur = -1;
+    c->stamp = 1;
+    c->rhow_ok = 0;
+    if (D.rhow)  // stamp 0 never matches a launch
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * L.S, 256, 8192)), dim3(256), 0, c->st, (int *)D.rhow,
+                           2 * L.S, 0);
     {
         // face velocities (a periodic axis has no face)
         float wv[18];
@@ -792,6 +815,7 @@ int fsl_particles_set(fsl_ctx *c, int n, const double *x, const double *u, const
                       const double *R, const double *rho_p) {
     if (!c || n < 0 || n > c->cfg.max_particles || (n > 0 && (!x || !R || !rho_p)))
         return fail(c, FSL_E_ARG, "particles_set: bad arguments");
+    c->rhow_ok = 0;  // the stored densities may not match the populations any more
     c->adj.ready = 0;
     std::vector<double> tab((size_t)std::max(n, 1) * P_STRIDE, 0.0);
     double Rmax = 0;
@@ -892,6 +916,7 @@ int fsl_bubbles_get(fsl_ctx *c, fsl_bubble *out, int cap, int *n) {
 
 int fsl_bubbles_set(fsl_ctx *c, int n, const double *M, const int *root, const int *alive) {
     if (!c || n < 1 || n > c->L.maxB || !M || !root || !alive) return fail(c, FSL_E_ARG, "bubbles_set: bad arguments");
+    c->rhow_ok = 0;  // the stored densities may not match the populations any more
     for (int b = 0; b < n; ++b)
         if (root[b] < 0 || root[b] >= n) return fail(c, FSL_E_ARG, "bubbles_set: bad root");
     // ids from n on become unused: no mass, their own root, not alive
@@ -980,6 +1005,7 @@ int fsl_fields_get(fsl_ctx *c, int field, void *host) {
 
 int fsl_fields_set(fsl_ctx *c, int field, const void *host) {
     if (!c || !host) return FSL_E_ARG;
+    c->rhow_ok = 0;  // the stored densities may not match the populations any more
     c->adj.ready = 0;
     const long long N = c->G.N;
     Dev &D = c->D;
@@ -1090,16 +1116,19 @@ int fsl_profile_get(fsl_ctx *c, double *ms, long long *count, int n) {
 
 int fsl_window_forward(fsl_ctx *c, int T, int k, double *J) {
     if (!c) return FSL_E_ARG;
+    c->rhow_ok = 0;  // the stored densities may not match the populations any more
     return window_forward(c, T, k, J);
 }
 
 int fsl_window_backward(fsl_ctx *c, double dJ, double *dJ_dtau, double dJ_dg[3]) {
     if (!c) return FSL_E_ARG;
+    c->rhow_ok = 0;  // the stored densities may not match the populations any more
     return window_backward(c, dJ, dJ_dtau, dJ_dg);
 }
 
 int fsl_params_set(fsl_ctx *c, double tau, const double g[3]) {
     if (!c || !(tau > 0.5) || !g) return fail(c, FSL_E_ARG, "params_set: tau must exceed 1/2");
+    c->rhow_ok = 0;  // the stored densities may not match the populations any more
     if (c->cfg.collision == FSL_TRT && !(tau != 0.5)) return fail(c, FSL_E_ARG, "params_set: bad tau");
     c->cfg.tau = tau;
     for (int a = 0; a < 3; ++a) c->cfg.g[a] = g[a];

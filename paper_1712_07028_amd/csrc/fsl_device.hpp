@@ -157,6 +157,12 @@ struct Dev {
     float *rhog;                     // FP32 gas density per bubble id (through root)
     float *kappa;                    // interface curvature (null without surface tension)
     float *wallu;                    // face velocities [axis][low, high][component]
+    // density of each liquid/interface cell that took the general path, as computed
+    // from its populations by the launch stamped .y (null without particles); a
+    // launch reads entries stamped st_prev (< 0: none) and writes them stamped st_cur
+    // (< 0: none)
+    int2 *rhow;
+    int st_prev, st_cur;
     int cap;                         // conversion list capacity
     int capEv;                       // coverage event list capacity
     int maxP, maxB;

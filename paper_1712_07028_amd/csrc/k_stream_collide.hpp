@@ -326,12 +326,28 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
             if (!INTERIOR) wm |= (uint32_t)(sf == WALL) << q;
         }
         const uint32_t miss = gm | sm | wm;
-        const bool needOwn = (fl == IFC) || gm || sm || (MW && wm);
+        const bool needOwn = (fl == IFC) || gm || (MW && wm);
         float fi[Q];
         // density and velocity of this cell at t from its own populations, which are
         // then reloaded where a rule needs one (a compiler barrier keeps the two
-        // groups of loads apart, so that both arrays are never live together)
+        // groups of loads apart, so that both arrays are never live together).  A
+        // cell whose only missing links lead to particles needs the density alone
+        // (Eq. bbrule): the previous launch stored it when it took this path too.
         float rho_t = 1.0f, ut0 = 0.f, ut1 = 0.f, ut2 = 0.f;
+        if (!needOwn && sm) {
+            bool have = false;
+            if (D.rhow != nullptr && D.st_prev >= 0) {
+                const int2 e = D.rhow[c];
+                have = e.y == D.st_prev;
+                rho_t = __int_as_float(e.x);
+            }
+            if (!have) {
+                double r = 0.0;
+#pragma unroll 1
+                for (int q = 0; q < Q; ++q) r += (double)SS::ld(A + q * S + (unsigned)c, inv);
+                rho_t = 1.0f + (float)r;
+            }
+        }
         if (needOwn) {
             float fa[Q];
 #pragma unroll
@@ -494,6 +510,10 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
             isE = !isF && phin <= Ph.eps;
         }
 
+        // the density of the populations stored below (the collision keeps the
+        // mass), for the next launch
+        if (D.rhow != nullptr && D.st_cur >= 0)
+            D.rhow[c] = make_int2(__float_as_int(1.0f + (float)drho_d), D.st_cur);
         if (!collide_store<ST>(Ph, fi, M, B, S, (unsigned)c)) atomicOr(D.err, ERR_NAN);
     }
 
@@ -604,7 +624,7 @@ __device__ __forceinline__ void lean_cell(const Geom &G, const Phys &Ph, const D
 // boundary work (bounce-back, free surface, mass exchange, forces, lists) is not
 // repeated by every wave that holds one such cell.
 template <int ST, bool MW>
-__global__ __launch_bounds__(256) void k_stream_collide(Geom G, Phys Ph, Dev D, int tilesX,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MW ? 1 : 5))) void k_stream_collide(Geom G, Phys Ph, Dev D, int tilesX,
                                                         int tilesY, int nTiles) {
     __shared__ uint8_t tile[3][TY + 2][TX + 2];
     __shared__ unsigned long long w3[3 * (TY + 2)], w1[3 * (TY + 2)];
