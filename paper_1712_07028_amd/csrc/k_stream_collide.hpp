@@ -326,7 +326,7 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
             if (!INTERIOR) wm |= (uint32_t)(sf == WALL) << q;
         }
         const uint32_t miss = gm | sm | wm;
-        const bool needOwn = (fl == IFC) || gm || (MW && wm);
+        bool needOwn = (fl == IFC) || gm || (MW && wm);
         float fi[Q];
         // density and velocity of this cell at t from its own populations, which are
         // then reloaded where a rule needs one (a compiler barrier keeps the two
@@ -341,12 +341,7 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
                 have = e.y == D.st_prev;
                 rho_t = __int_as_float(e.x);
             }
-            if (!have) {
-                double r = 0.0;
-#pragma unroll 1
-                for (int q = 0; q < Q; ++q) r += (double)SS::ld(A + q * S + (unsigned)c, inv);
-                rho_t = 1.0f + (float)r;
-            }
+            needOwn = !have;
         }
         if (needOwn) {
             float fa[Q];
