@@ -1,0 +1,55 @@
+"""The hot path at the benchmark's full size: the 512 x 512 x 1024 bubble column with
+10^5 spheres (R = 5), in the launch configuration the benchmark times.
+
+The oracle cannot hold this box, so properties that hold at any size are checked:
+the ledger mass is conserved (FP64 sums over 2 x 10^8 liquid cells), every bubble's
+volume equals its gas cells plus the empty part of its interface cells (the bubble
+model's definition, recounted on the host from the cell fields), and the run reports
+no error (a liquid cell next to gas, a NaN, a list overflow).
+"""
+import numpy as np
+import pytest
+
+import paper_1712_07028_amd as fsl
+from paper_1712_07028_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    fsl.load_library()
+
+
+def test_column_full_size_properties():
+    w = W.bubble_column_large()
+    print(f"full-size column {w.n}, {w.particles.n} spheres", flush=True)
+    s = fsl.Sim(w)
+    M0 = s.mass()[0]
+    s.step(30)
+    s.sync()
+    M1 = s.mass()[0]
+    print("ledger mass drift", (M1 - M0) / M0, flush=True)
+    assert abs(M1 - M0) / M0 < 1e-10
+    flags = s.get(fsl.FIELD_FLAGS)
+    bid = s.get(fsl.FIELD_BUBBLE_ID)
+    phi = s.get(fsl.FIELD_PHI)
+    bubbles = s.bubbles()
+    s.close()
+    gas, ifc = flags == fsl.GAS, flags == fsl.IFC
+    assert ((flags == fsl.LIQ) | ifc).sum() > 2 * 10**8
+    gid = bid[gas]
+    iid, iphi = bid[ifc], phi[ifc]
+    alive = [b for b in bubbles if b["alive"]]
+    assert len(alive) >= 2  # the gas above the pool and the rising bubble
+    for b in alive:
+        V = float((gid == b["id"]).sum()) + float((1.0 - iphi[iid == b["id"]]).sum())
+        print("bubble", b["id"], "V", b["V"], "recount", V, flush=True)
+        assert abs(V - b["V"]) <= 1e-9 * V
+    # every gas and interface cell belongs to a live bubble
+    live = np.array([b["id"] for b in alive])
+    assert np.isin(gid, live).all() and np.isin(iid, live).all()
