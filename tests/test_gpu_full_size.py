@@ -53,3 +53,48 @@ def test_column_full_size_properties():
     # every gas and interface cell belongs to a live bubble
     live = np.array([b["id"] for b in alive])
     assert np.isin(gid, live).all() and np.isin(iid, live).all()
+
+
+def test_column_full_size_sampled_cells():
+    """Sampled outputs at full size: 64 random liquid cells whose 3 x 3 x 3 block is
+    liquid take the plain pull and collision; the oracle steps each block as a periodic
+    3^3 window from the library's populations, and its centre must agree."""
+    import oracle as O
+
+    O.build(force=False)
+    w = W.bubble_column_large()
+    s = fsl.Sim(w)
+    s.step(3)
+    s.sync()
+    flags = s.get(fsl.FIELD_FLAGS)
+    nz, ny, nx = flags.shape
+    rng = np.random.Generator(np.random.PCG64(5))
+    picks = []
+    for _ in range(100000):
+        if len(picks) == 64:
+            break
+        z, y, x = (int(rng.integers(1, n - 1)) for n in (nz, ny, nx))
+        if (flags[z - 1:z + 2, y - 1:y + 2, x - 1:x + 2] == fsl.LIQ).all():
+            picks.append((z, y, x))
+    assert len(picks) == 64
+    del flags
+    F = s.get(fsl.FIELD_F)  # 19 x 2.7e8 FP64 values on the host (41 GB)
+    wins = [F[:, z - 1:z + 2, y - 1:y + 2, x - 1:x + 2].copy() for z, y, x in picks]
+    del F
+    s.step(1)
+    s.sync()
+    F = s.get(fsl.FIELD_F)
+    got = [F[:, z, y, x].copy() for z, y, x in picks]
+    del F
+    s.close()
+    ws = w.replace(name="window3", n=(3, 3, 3), zs=-1.0, periodic=(1, 1, 1), gas_spheres=[], particles=None)
+    worst = 0.0
+    for win, g in zip(wins, got):
+        o = O.Oracle(ws)
+        o.set(O.F, win)
+        o.step(1)
+        ref = o.get(O.F)[:, 1, 1, 1]
+        o.close()
+        worst = max(worst, float((np.abs(g - ref) / np.abs(ref)).max()))
+    print("sampled cells: worst relative population error", worst, flush=True)
+    assert worst < 1e-6
