@@ -16,6 +16,10 @@ FLAGS = [
     "-munsafe-fp-atomics",
     # packed FP32 instructions stay off (plain scalar float code only)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the kernels index their per-cell population arrays with constants only, so
+    # they live in scalar registers; promoting them to vector values instead makes
+    # every conditional update copy the whole vector (and spill)
+    "-mllvm", "-disable-promote-alloca-to-vector",
     "-Wall", "-Werror=return-type",
 ]
 

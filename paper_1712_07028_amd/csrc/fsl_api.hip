@@ -39,7 +39,8 @@ struct Layout {
     size_t counters, ctl, ptab, pacc, pFT, pFTp, pFl, pmir, gStart, gCount, gIdx, gBsum;
     size_t btab, bacc, broot, balive, rhog, kappa, ktf, klist, kcount, wallu, stage;
     size_t slab, scomp, scid, spar, svol;  // bubble splitting
-    size_t rhow;  // densities of the general path's cells for the next launch
+    size_t rhow;  // densities of the liquid and interface cells for the next launch
+    size_t glist;  // tiles of the general path of the stream-collide step
     size_t win;  // differentiation window storage
     size_t total;
     long long S;
@@ -143,6 +144,7 @@ Layout layout_of(const fsl_config *c) {
     L.nTiles = ((c->n[0] + TX - 1) / TX) * ((c->n[1] + TY - 1) / TY) * c->n[2];
     L.winBytes = adjoint_window_bytes(c->window_steps, c->window_every, (size_t)L.S, c->max_particles,
                                       L.nTiles);
+    L.glist = take((size_t)L.nTiles * 4);
     L.win = take(L.winBytes);
     L.total = o;
     return L;
@@ -263,15 +265,23 @@ void set_phys(fsl_ctx *c) {
     c->Ph.inv = 1.0f / c->Ph.scale;
 }
 
-// one lattice update of every cell
+// one lattice update of every cell: the marching pass over the liquid cells, then the
+// general path over the tiles it listed (interface cells, liquid cells next to gas or
+// a moving or slipping face)
+template <int ST, bool MW>
+void launch_stream_collide_mw(fsl_ctx *c, const Dev &Dv) {
+    int *glist = (int *)(c->ws + c->L.glist), *ngen = Dv.counters + C_NGEN;
+    const int nChunks = (c->G.nz + NZC - 1) / NZC;
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->st, ngen, 1LL, 0);
+    hipLaunchKernelGGL((k_stream_collide<ST, MW>), dim3(c->tilesX * c->tilesY * nChunks), dim3(256), 0, c->st,
+                       c->G, c->Ph, Dv, c->tilesX, c->tilesY, nChunks, glist, ngen);
+    hipLaunchKernelGGL((k_general<ST, MW>), dim3(std::min(c->nTiles, 4096)), dim3(256), 0, c->st, c->G, c->Ph, Dv,
+                       c->tilesX, c->tilesY, (const int *)glist, (const int *)ngen);
+}
 template <int ST>
 void launch_stream_collide(fsl_ctx *c, const Dev &Dv) {
-    if (c->Ph.moving_walls)
-        hipLaunchKernelGGL((k_stream_collide<ST, true>), dim3(c->nTiles), dim3(256), 0, c->st, c->G, c->Ph, Dv,
-                           c->tilesX, c->tilesY, c->nTiles);
-    else
-        hipLaunchKernelGGL((k_stream_collide<ST, false>), dim3(c->nTiles), dim3(256), 0, c->st, c->G, c->Ph, Dv,
-                           c->tilesX, c->tilesY, c->nTiles);
+    if (c->Ph.moving_walls) launch_stream_collide_mw<ST, true>(c, Dv);
+    else launch_stream_collide_mw<ST, false>(c, Dv);
 }
 
 template <int ST> int enqueue_steps(fsl_ctx *c, int n, int split = 1);
@@ -441,6 +451,11 @@ int enqueue_steps(fsl_ctx *c, int n, int split) {
         if (D.kappa) {  // curvature of the interface at t for the Laplace jump
             ProfScope ps(c, 6);
             enqueue_curvature(c);
+        }
+        if (!c->rhow_ok && D.rhow) {  // densities of the current populations for rho_w
+            hipLaunchKernelGGL(k_rhow_fill<ST>, dim3(grid_for(c->G.N, 256, 8192)), dim3(256), 0, c->st, c->G,
+                               c->Ph, D, c->stamp - 1);
+            c->rhow_ok = 1;
         }
         D.st_prev = c->rhow_ok ? c->stamp - 1 : -1;
         D.st_cur = c->stamp;

@@ -55,6 +55,7 @@ enum Counter {
     C_SPLIT,  // splitting pass: 1 = label the gas, 2 = some bubble splits
     C_NCOMP,  // gas components listed by the splitting pass
     C_MERGED, // some bubbles merged in this step: cells are relabelled to their roots
+    C_NGEN,   // tiles listed for the general path of the stream-collide step
     C_COUNT
 };
 // persistent slot (not reset per step): number of bubble ids in use
@@ -150,17 +151,17 @@ struct Dev {
     unsigned *err;
     double *ledger;                  // [0] ledger
     double *ptab, *pacc, *pFT, *pFTp, *pFl; // particles (pFTp: previous step's F, T)
-    float4 *pmir;                    // FP32 mirror per particle: anchor, fraction, u, omega
+    float4 *pmir;                    // FP32 mirror per particle (PMir: anchor, fraction, u, omega)
     int *gridStart, *gridCount, *gridIdx;
     double *btab, *bacc;
     int *broot, *balive;
     float *rhog;                     // FP32 gas density per bubble id (through root)
     float *kappa;                    // interface curvature (null without surface tension)
     float *wallu;                    // face velocities [axis][low, high][component]
-    // density of each liquid/interface cell that took the general path, as computed
-    // from its populations by the launch stamped .y (null without particles); a
-    // launch reads entries stamped st_prev (< 0: none) and writes them stamped st_cur
-    // (< 0: none)
+    // (density, launch stamp) of every liquid and interface cell, as computed from its
+    // populations by the launch stamped .y (null without particles): Eq. bbrule's
+    // rho_w for the next launch, which reads entries stamped st_prev (< 0: none) and
+    // writes them stamped st_cur (< 0: none)
     int2 *rhow;
     int st_prev, st_cur;
     int cap;                         // conversion list capacity
@@ -168,6 +169,18 @@ struct Dev {
     int maxP, maxB;
     int np, nb;
 };
+
+// FP32 mirror of a particle for the kernels that need its rigid-body velocity at a node:
+// anchor a = floor(x_P) (exact integers), fraction x_P - a, u_P, omega_P; 12 floats in
+// the first three float4 of the particle's 64-byte record
+struct PMir {
+    float ax, ay, az, fx, fy, fz, ux, uy, uz, wx, wy, wz;
+};
+__device__ __forceinline__ PMir pmir_load(const float4 *pmir, int P) {
+    const float4 *m = pmir + 4LL * P;
+    const float4 a = m[0], b = m[1], c = m[2];
+    return PMir{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+}
 
 // ---- small helpers ---------------------------------------------------------------
 __device__ __forceinline__ int wrapc(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }

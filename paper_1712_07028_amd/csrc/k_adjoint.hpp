@@ -172,12 +172,11 @@ __device__ __forceinline__ void adj_cell(const Geom &G, const Phys &Ph, const De
     // rigid-body velocity of particle P at this node (the same for all its links,
     // since c_q . (omega x c_q) = 0)
     auto node_velocity = [&](int P, float &u0, float &u1, float &u2) {
-        const float4 *pm = D.pmir + 4LL * P;
-        const float4 an = pm[0], fr = pm[1], up = pm[2], wp = pm[3];
-        const float rx = ((float)x - an.x) - fr.x, ry = ((float)y - an.y) - fr.y, rz = ((float)z - an.z) - fr.z;
-        u0 = up.x + (wp.y * rz - wp.z * ry);
-        u1 = up.y + (wp.z * rx - wp.x * rz);
-        u2 = up.z + (wp.x * ry - wp.y * rx);
+        const PMir m = pmir_load(D.pmir, P);
+        const float rx = ((float)x - m.ax) - m.fx, ry = ((float)y - m.ay) - m.fy, rz = ((float)z - m.az) - m.fz;
+        u0 = m.ux + (m.wy * rz - m.wz * ry);
+        u1 = m.uy + (m.wz * rx - m.wx * rz);
+        u2 = m.uz + (m.wx * ry - m.wy * rx);
     };
 
     // links: bit q of sm / wm = the pull source x - c_q is solid / a wall; the

@@ -74,10 +74,11 @@ __global__ void k_part_mirror(Dev D) {
         const double *t = D.ptab + (long long)P * P_STRIDE;
         float4 *m = D.pmir + 4LL * P;
         double a0 = floor(t[P_X]), a1 = floor(t[P_X + 1]), a2 = floor(t[P_X + 2]);
-        m[0] = make_float4((float)a0, (float)a1, (float)a2, 0.f);
-        m[1] = make_float4((float)(t[P_X] - a0), (float)(t[P_X + 1] - a1), (float)(t[P_X + 2] - a2), 0.f);
-        m[2] = make_float4((float)t[P_U], (float)t[P_U + 1], (float)t[P_U + 2], 0.f);
-        m[3] = make_float4((float)t[P_W], (float)t[P_W + 1], (float)t[P_W + 2], 0.f);
+        // PMir order: anchor, fraction, u, omega
+        m[0] = make_float4((float)a0, (float)a1, (float)a2, (float)(t[P_X] - a0));
+        m[1] = make_float4((float)(t[P_X + 1] - a1), (float)(t[P_X + 2] - a2), (float)t[P_U], (float)t[P_U + 1]);
+        m[2] = make_float4((float)t[P_U + 2], (float)t[P_W], (float)t[P_W + 1], (float)t[P_W + 2]);
+        m[3] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
 }
 
@@ -609,6 +610,9 @@ __global__ void k_unc_apply(Geom G, Phys Ph, Dev D, double *phi) {
             u2 = (float)(t[P_U + 2] + (t[P_W] * ry - t[P_W + 1] * rx));
         }
         store_equilibrium<ST>(G, Ph, D.fB, c, rb - 1.0, u0, u1, u2);
+        // the density of the stored populations, for rho_w (Eq. bbrule) in the next launch
+        if (D.rhow != nullptr && D.st_cur >= 0)
+            D.rhow[c] = make_int2(__float_as_int((float)cell_rho<ST>(G, D, Ph, D.fB, c)), D.st_cur);
         unsafeAtomicAdd(D.ledger, -rb);
         phi[c] = 1.0;
         if (type == IFC) {

@@ -201,9 +201,9 @@ __device__ __forceinline__ Moments cell_moments(const float (&h)[Q]) {
 // h*_0 = sum_q h_q - sum_{q>0} h*_q with the stored moving values summed in FP64:
 // in exact arithmetic it is the same population, and FP32 rounding of the weights
 // then cannot bias the mass.  Returns false on a NaN density or velocity.
-template <int ST>
+template <int ST, bool NT = false>
 __device__ __forceinline__ bool collide_store(const Phys &Ph, const float (&fi)[Q], const Moments &M,
-                                              typename Store<ST>::T *B, long long S, unsigned c) {
+                                              typename Store<ST>::T *B, long long S, unsigned c, bool store = true) {
     using SS = Store<ST>;
     using T = typename SS::T;
     const float inv = Ph.inv, sc = Ph.scale;
@@ -219,6 +219,7 @@ __device__ __forceinline__ bool collide_store(const Phys &Ph, const float (&fi)[
     const float lp = Ph.lp, lm = Ph.lm;
     const float ap = 1.0f + 0.5f * lp, am = 1.0f + 0.5f * lm;
     double sp[9];
+    T out[Q];
     int k = 0;
 #pragma unroll
     for (int q = 1; q < Q; q += 1) {
@@ -235,12 +236,20 @@ __device__ __forceinline__ bool collide_store(const Phys &Ph, const float (&fi)[
         const float hm = 0.5f * (fi[q] - fi[o]) - em;
         const float even = lp * hp + ap * Fp, odd = lm * hm + am * Fm;
         const T vq = SS::enc(fi[q] + even + odd, sc), vo = SS::enc(fi[o] + even - odd, sc);
-        sp[k++] = (double)SS::dec(vq, inv) + (double)SS::dec(vo, inv);
-        B[q * S + c] = vq;
-        B[o * S + c] = vo;
+        sp[k] = (double)SS::dec(vq, inv) + (double)SS::dec(vo, inv);
+        out[q] = vq;
+        out[o] = vo;
+        ++k;
     }
     const double sout = (((sp[0] + sp[1]) + (sp[2] + sp[3])) + ((sp[4] + sp[5]) + (sp[6] + sp[7]))) + sp[8];
-    SS::st(B + c, (float)(M.drho - sout), sc);
+    out[0] = SS::enc((float)(M.drho - sout), sc);
+    if (store) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (NT) __builtin_nontemporal_store(out[q], B + q * S + c);
+            else B[q * S + c] = out[q];
+        }
+    }
     return rho == rho && u0 == u0 && u1 == u1 && u2 == u2;
 }
 
@@ -380,16 +389,15 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
             // because c_q . (omega x c_q) = 0, so one velocity serves all links
             float un0 = 0.f, un1 = 0.f, un2 = 0.f;
             auto node_velocity = [&](int P) {
-                const float4 *pm = D.pmir + 4LL * P;
-                const float4 an = pm[0], fr = pm[1], up = pm[2], wp = pm[3];
-                acc.an[0] = an.x; acc.an[1] = an.y; acc.an[2] = an.z;
-                acc.fr[0] = fr.x; acc.fr[1] = fr.y; acc.fr[2] = fr.z;
-                const float rx = ((float)x - an.x) - fr.x;
-                const float ry = ((float)y - an.y) - fr.y;
-                const float rz = ((float)z - an.z) - fr.z;
-                un0 = up.x + (wp.y * rz - wp.z * ry);
-                un1 = up.y + (wp.z * rx - wp.x * rz);
-                un2 = up.z + (wp.x * ry - wp.y * rx);
+                const PMir m = pmir_load(D.pmir, P);
+                acc.an[0] = m.ax; acc.an[1] = m.ay; acc.an[2] = m.az;
+                acc.fr[0] = m.fx; acc.fr[1] = m.fy; acc.fr[2] = m.fz;
+                const float rx = ((float)x - m.ax) - m.fx;
+                const float ry = ((float)y - m.ay) - m.fy;
+                const float rz = ((float)z - m.az) - m.fz;
+                un0 = m.ux + (m.wy * rz - m.wz * ry);
+                un1 = m.uy + (m.wz * rx - m.wx * rz);
+                un2 = m.uz + (m.wx * ry - m.wy * rx);
             };
             if ((unsigned)P0 < (unsigned)D.np) {
                 acc.P = P0;
@@ -555,126 +563,553 @@ __device__ __forceinline__ void stage_flag_tile(const Geom &G, const uint8_t *fl
     }
 }
 
-// Per row of the staged tile (3 planes x 6 rows of 66 cells): w3 bit i is set when
-// one of the columns i, i+1, i+2 (the cells x-1, x, x+1 of lane i) is neither liquid
-// nor a resting wall, w1 bit i when column i+1 (the cell x of lane i) is neither.
-// One ballot per row; the caller syncs before and after.
-__device__ __forceinline__ void build_row_masks(const uint8_t (&tile)[3][TY + 2][TX + 2],
-                                                unsigned long long (&w3)[3 * (TY + 2)],
-                                                unsigned long long (&w1)[3 * (TY + 2)], bool wall_ok) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int r = wv; r < 3 * (TY + 2); r += 4) {
-        const int lz = r / (TY + 2), ly = r - lz * (TY + 2);
-        const uint8_t a = tile[lz][ly][lane], b = tile[lz][ly][TX + (lane & 1)];
-        const unsigned long long lo = __ballot(a != LIQ && !(a == WALL && wall_ok));
-        const unsigned long long hi = __ballot(lane < 2 && b != LIQ && !(b == WALL && wall_ok)) & 3ull;
-        const unsigned long long s1 = (lo >> 1) | (hi << 63);
-        const unsigned long long s2 = (lo >> 2) | (hi << 62);
-        if (lane == 0) {
-            w3[r] = lo | s1 | s2;
-            w1[r] = s1;
-        }
-    }
-}
-
-// tile t of the launch: XCD-contiguous ranges when the tile count allows
+// tile t of a launch over the tiles of the box: XCD-contiguous ranges when the tile
+// count allows
 __device__ __forceinline__ int tile_of_block(int b, int nTiles) {
     return (nTiles % 8 == 0) ? (b % 8) * (nTiles / 8) + b / 8 : b;
 }
 
-// A liquid cell whose 18 neighbours are liquid or beyond a wall: plain pull
-// (Eq. LBE1) with half-way bounce-back at walls, then the collision (Eq. LBE2).
+// Exact integer counts of the constant parts 2 w_q c_q of Delta j (Eq.
+// momentum_transfer in shifted populations), in units of 1/18 (axis links 2,
+// diagonal links 1): three components packed 10 bits apart, each |v| < 512
+__host__ __device__ constexpr int kpack(int a, int b, int c) { return a + 1024 * b + 1048576 * c; }
+__device__ __forceinline__ int sext10(int v) { return v >= 512 ? v - 1024 : v; }
+__device__ __forceinline__ void kunpack(int p, int &a, int &b, int &c) {
+    a = sext10(p & 1023);
+    p = (p - a) / 1024;
+    b = sext10(p & 1023);
+    c = (p - b) / 1024;
+}
+__device__ __forceinline__ int kconst(int q) {
+    const int m = q <= 6 ? 2 : 1;
+    return kpack(-cx(q) * m, -cy(q) * m, -cz(q) * m);
+}
+
+// ---- the marching kernel ------------------------------------------------------------
+// A block takes a 64 x 4 column of cells through NZC consecutive planes.  Each wave
+// takes one row of the column; each lane one x.  The cell types and the particle ids
+// of the particle nodes of four planes (z-1 .. z+2) stay in LDS rings, refilled one
+// plane ahead from loads issued a plane earlier, so that a plane costs one barrier.
+constexpr int NZC = 16;
+#ifndef WPE_MARCH
+#define WPE_MARCH 4
+#endif
+constexpr int HX = TX + 2, HY = TY + 2;  // a staged plane: 6 rows of 66 cells
+
+// bitmasks of a staged row (cells x0-1 .. x0+64): bit l of a "3" mask is set when one
+// of the cells x-1, x, x+1 of lane l is of the kind, of a "1" mask when the cell x is.
+// nf: not liquid or interface (gas, particle node, wall); bad: gas and, with moving
+// or slipping faces, walls.
+enum { MK_NF3 = 0, MK_NF1, MK_BAD3, MK_BAD1, MK_N };
+
+struct MarchLds {
+    uint8_t ft[4][HY][HX];              // cell types, slot z & 3
+    int pt[4][HY][HX];                  // particle ids (particle nodes only), slot z & 3
+    unsigned long long mk[4][MK_N][HY]; // row masks, slot z & 3
+    int genflag[2];                     // the plane holds cells for the general path
+    // each lane's link sums for one particle over the planes of the march: force and
+    // torque about the particle's centre (Eqs. netforce, torque, momentum_transfer) in
+    // FP64, and the mass that moving bounce-back added (paid by the ledger)
+    double acc[7][256];
+    int accP[256];
+};
+
+// Staging of the ring: wave wv loads rows wv and wv + 4 (waves 0, 1) of a plane, lane l
+// the cell x0-1+l and lanes 0, 1 also x0+63+l.  The lane's column and row offsets
+// (periodic faces wrapped, -1 beyond a non-periodic face) are fixed for the march; a
+// plane adds a uniform offset.  Indices fit 32 bits (the box holds < 2^31 cells).
+struct StageIdx {
+    int xm, xe;  // column of the lane's main and extra cell, or -1
+    int yo[2];   // (row y) * nx of the wave's two rows, or -1
+};
+__device__ __forceinline__ int stage_wrap(int v, int n, int per) {
+    return (v >= 0 && v < n) ? v : (per ? wrapc(v, n) : -1);
+}
+__device__ __forceinline__ StageIdx stage_idx(const Geom &G, int x0, int y0) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    StageIdx s;
+    s.xm = stage_wrap(x0 - 1 + lane, G.nx, G.per[0]);
+    s.xe = lane < 2 ? stage_wrap(x0 + 63 + lane, G.nx, G.per[0]) : -1;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int r = wv + 4 * k;
+        const int yy = r < HY ? stage_wrap(y0 - 1 + r, G.ny, G.per[1]) : -1;
+        s.yo[k] = yy >= 0 ? yy * G.nx : -1;
+    }
+    return s;
+}
+// the plane offset z * nx * ny, or -1 beyond a non-periodic face
+__device__ __forceinline__ int stage_zo(const Geom &G, int z) {
+    const int zz = stage_wrap(z, G.nz, G.per[2]);
+    return zz >= 0 ? zz * G.nx * G.ny : -1;
+}
+
+// the rows of a plane that wave wv stages
+struct RowPre {
+    int f[2];  // cell types: lane's main cell (bits 0-7), extra cell (bits 8-15)
+    int p[2];  // particle id of the main cell (particle nodes), -1 otherwise
+    int pe[2]; // ... of the extra cell
+};
+
+__device__ __forceinline__ void pre_flags(const uint8_t *flags, const StageIdx &I, RowPre &R, int zo) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const bool row = I.yo[k] >= 0 && zo >= 0;
+        const int v = (row && I.xm >= 0) ? flags[I.xm + I.yo[k] + zo] : WALL;
+        const int e = (row && I.xe >= 0) ? flags[I.xe + I.yo[k] + zo] : WALL;
+        R.f[k] = v | (e << 8);
+    }
+}
+
+// particle ids of the particle nodes among the rows whose types R holds
+__device__ __forceinline__ void pre_pids(const int *pid, const StageIdx &I, RowPre &R, int zo) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        R.p[k] = (R.f[k] & 0xff) == SOL ? pid[I.xm + I.yo[k] + zo] : -1;
+        R.pe[k] = ((R.f[k] >> 8) & 0xff) == SOL ? pid[I.xe + I.yo[k] + zo] : -1;
+    }
+}
+
+// write the staged rows of a plane into ring slot sl and form their masks (ballots
+// over the wave's registers); the caller syncs before the slot is read
+__device__ __forceinline__ void pre_store(MarchLds &L, const RowPre &R, int sl, bool wall_bad) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int r = wv + 4 * k;
+        if (r >= HY) continue;  // uniform over the wave
+        const int a = R.f[k] & 0xff, b = (R.f[k] >> 8) & 0xff;
+        L.ft[sl][r][lane] = (uint8_t)a;
+        L.pt[sl][r][lane] = R.p[k];
+        if (lane < 2) {
+            L.ft[sl][r][64 + lane] = (uint8_t)b;
+            L.pt[sl][r][64 + lane] = R.pe[k];
+        }
+        const bool hl = lane < 2;
+        const unsigned long long nlo = __ballot(a != LIQ && a != IFC);
+        const unsigned long long nhi = __ballot(hl && b != LIQ && b != IFC) & 3ull;
+        const unsigned long long blo = __ballot(a == GAS || (wall_bad && a == WALL));
+        const unsigned long long bhi = __ballot(hl && (b == GAS || (wall_bad && b == WALL))) & 3ull;
+        if (lane == 0) {
+            const unsigned long long n1 = (nlo >> 1) | (nhi << 63), n2 = (nlo >> 2) | (nhi << 62);
+            const unsigned long long b1 = (blo >> 1) | (bhi << 63), b2 = (blo >> 2) | (bhi << 62);
+            L.mk[sl][MK_NF3][r] = nlo | n1 | n2;
+            L.mk[sl][MK_NF1][r] = n1;
+            L.mk[sl][MK_BAD3][r] = blo | b1 | b2;
+            L.mk[sl][MK_BAD1][r] = b1;
+        }
+    }
+}
+
+// D3Q19 neighbourhood of lane l in row ly of the plane in slot s0 (planes z-1, z+1 in
+// slots sm, sp): the OR of the masks of kind K3 (x-1..x+1) and K1 (x) over the 3 x 3
+// square of the plane and the plus shape of the planes beside it
+template <int K3, int K1>
+__device__ __forceinline__ bool nbr_any(const MarchLds &L, int sm, int s0, int sp, int ly, int lx) {
+    const unsigned long long m = L.mk[s0][K3][ly] | L.mk[s0][K3][ly + 1] | L.mk[s0][K3][ly + 2] |
+                                 L.mk[sm][K3][ly + 1] | L.mk[sp][K3][ly + 1] | L.mk[sm][K1][ly] |
+                                 L.mk[sm][K1][ly + 2] | L.mk[sp][K1][ly] | L.mk[sp][K1][ly + 2];
+    return (m >> lx) & 1ull;
+}
+
+// one lane's sums (in LDS) straight to its particle (a lane that moves on to another
+// particle), then cleared
+__device__ __forceinline__ void macc_atomic(const Dev &D, MarchLds &L, int t) {
+    double *dst = D.pacc + acc_at(L.accP[t], blockIdx.x & (ACC_COPIES - 1));
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        unsafeAtomicAdd(dst + k, L.acc[k][t]);
+        L.acc[k][t] = 0.0;
+    }
+}
+
+// FP64 wave sum with DPP on the two 32-bit halves (same pattern as wave_total_f)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_add_d(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xF, false);
+    return v + __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double wave_total_d(double v) {
+    v = dpp_add_d<0xB1, 0xF>(v);
+    v = dpp_add_d<0x4E, 0xF>(v);
+    v = dpp_add_d<0x141, 0xF>(v);
+    v = dpp_add_d<0x140, 0xF>(v);
+    v = dpp_add_d<0x142, 0xA>(v);
+    v = dpp_add_d<0x143, 0xC>(v);
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// the lanes' remaining sums at the end of a march, segmented by particle: one FP64
+// atomic instruction per (wave, particle).  Every lane of the wave must be active.
+__device__ __forceinline__ void macc_wave_flush(const Dev &D, const MarchLds &L) {
+    const int t = threadIdx.x;
+    int key = L.accP[t];
+    const double a0 = L.acc[0][t], a1 = L.acc[1][t], a2 = L.acc[2][t], a3 = L.acc[3][t], a4 = L.acc[4][t],
+                 a5 = L.acc[5][t], a6 = L.acc[6][t];
+    while (true) {
+        const unsigned long long act = __ballot(key >= 0);
+        if (!act) break;
+        const int leader = __ffsll((long long)act) - 1;
+        const int k0 = __builtin_amdgcn_readlane(key, leader);
+        const bool mine = key == k0;
+        const double s0 = wave_total_d(mine ? a0 : 0.0), s1 = wave_total_d(mine ? a1 : 0.0),
+                     s2 = wave_total_d(mine ? a2 : 0.0), s3 = wave_total_d(mine ? a3 : 0.0),
+                     s4 = wave_total_d(mine ? a4 : 0.0), s5 = wave_total_d(mine ? a5 : 0.0),
+                     s6 = wave_total_d(mine ? a6 : 0.0);
+        const int ln = (int)lane_id();
+        if (ln < 7) {
+            const double v = ln == 0 ? s0 : ln == 1 ? s1 : ln == 2 ? s2 : ln == 3 ? s3 : ln == 4 ? s4 : ln == 5 ? s5 : s6;
+            unsafeAtomicAdd(D.pacc + acc_at(k0, blockIdx.x & (ACC_COPIES - 1)) + ln, v);
+        }
+        if (mine) key = -1;
+    }
+}
+
+// density of a cell's own populations (a cell whose density from the launch before
+// is not stored): kept out of line, so that its loads never share registers with
+// the pulled populations
+template <int ST>
+__device__ __noinline__ float own_density(const void *A, long long S, int c, float inv) {
+    using SS = Store<ST>;
+    const typename SS::T *p = (const typename SS::T *)A;
+    float fa[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fa[q] = SS::ld(p + q * S + (unsigned)c, inv);
+    return 1.0f + (float)cell_moments(fa).drho;
+}
+
+// One cell of a row in the marching pass: a liquid cell whose neighbours are liquid,
+// interface, particle nodes or resting walls (act).  Pull streaming (Eq. LBE1); a
+// source beyond a resting wall gives half-way bounce-back, a particle node the
+// moving-wall rule (Eq. bbrule) with rho_w the density of the cell at t and u_w the
+// particle's rigid-body velocity, and its momentum exchange (Eqs. netforce, torque,
+// momentum_transfer) joins the lane's sums; then the collision (Eq. LBE2).  Lanes with
+// store set and act clear (gas and particle nodes of the row) write values that no
+// rule reads, so that every row of every population is written whole and once;
+// interface cells and lanes outside the box leave their words to the general path.
 template <int ST, bool INTERIOR>
-__device__ __forceinline__ void lean_cell(const Geom &G, const Phys &Ph, const Dev &D,
-                                          const uint8_t (&tile)[3][TY + 2][TX + 2], int lx, int ly, int x,
-                                          int y, int z) {
+__device__ __forceinline__ void march_cell(const Geom &G, const Phys &Ph, const Dev &D, MarchLds &L,
+                                           int sm1, int s0, int sp1, int lx, int ly, int x, int y, int z,
+                                           bool act, bool store, bool nbnf, const void *Av, void *Bv,
+                                           long long S, const StageIdx &SI, RowPre &R, int zo2) {
     using SS = Store<ST>;
     using T = typename SS::T;
     const int nx = G.nx, ny = G.ny, nz = G.nz, nxy = nx * ny;
-    const int c = x + nx * y + nxy * z;
-    const T *A = (const T *)D.fA;
-    T *B = (T *)D.fB;
-    const long long S = G.S;
+    const int c = store ? x + nx * y + nxy * z : 0;
+    const T *A = (const T *)Av;
+    T *B = (T *)Bv;
+    const float inv = Ph.inv;
+    auto slot = [&](int q) { return cz(q) == 1 ? sm1 : (cz(q) == -1 ? sp1 : s0); };  // plane z - c_z
+    auto src = [&](int q) -> int {
+        if (INTERIOR) return c - (cx(q) + cy(q) * nx + cz(q) * nxy);
+        const int sx = wrapc(x - cx(q), nx), sy = wrapc(y - cy(q), ny), sz = wrapc(z - cz(q), nz);
+        return sx + nx * sy + nxy * sz;
+    };
+    // bounce-back sources: particle nodes (sm) and, outside the interior, walls
+    uint32_t sm = 0, wm = 0;
+    if (act && nbnf) {
+#pragma unroll
+        for (int q = 1; q < Q; ++q) {
+            const uint8_t sf = L.ft[slot(q)][ly + 1 - cy(q)][lx + 1 - cx(q)];
+            sm |= (uint32_t)(sf == SOL) << q;
+            if (!INTERIOR) wm |= (uint32_t)(sf == WALL) << q;
+        }
+    }
+    const uint32_t bb = sm | wm;
+    // the particle P of the first particle-node link (in direction order) and the
+    // links it owns, from the staged ids, before the global loads are issued
+    auto links_of_first = [&](uint32_t rest, int &P) -> uint32_t {
+        P = -1;
+        uint32_t msk = 0;
+        bool found = false;
+#pragma unroll
+        for (int q = 1; q < Q; ++q) {
+            const bool b = (rest >> q) & 1u;
+            const int p = L.pt[slot(q)][ly + 1 - cy(q)][lx + 1 - cx(q)];
+            if (b && !found) P = p;
+            found = found || b;
+            msk |= (uint32_t)(b && p == P) << q;
+        }
+        return msk;
+    };
+    int P = -1;
+    const uint32_t msk = sm ? links_of_first(sm, P) : 0u;
+    const bool okP = (unsigned)P < (unsigned)D.np;
+    // rho_w of Eq. bbrule: the density of this cell at t, as the launch before stored it
+    int2 e = make_int2(0, -1);
+    if (sm && D.rhow != nullptr && D.st_prev >= 0) e = D.rhow[c];
+    PMir pm{};
+    if (sm && okP) pm = pmir_load(D.pmir, P);
+    // every lane issues every load (no branches): a bounce-back link reads the cell's
+    // own opposite population, a pull its source, a lane without a cell the first word
+    // of the plane (its value is not used)
     float fi[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const T *p;
-        if (INTERIOR || q == 0) {
-            p = A + q * S + (unsigned)(c - (cx(q) + cy(q) * nx + cz(q) * nxy));
-        } else {
-            const bool wall = tile[1 - cz(q)][ly + 1 - cy(q)][lx + 1 - cx(q)] == WALL;
-            const int s = wrapc(x - cx(q), nx) + nx * wrapc(y - cy(q), ny) + nxy * wrapc(z - cz(q), nz);
-            p = wall ? A + opp(q) * S + (unsigned)c : A + q * S + (unsigned)s;
+        const bool b = (bb >> q) & 1u;
+        const T *base = b ? A + opp(q) * S : A + q * S;
+        const unsigned idx = act ? (unsigned)(b ? c : src(q)) : 0u;
+        const float v = SS::ld(base + idx, inv);
+        fi[q] = act ? v : 0.f;
+    }
+    // particle ids of plane z+2 for the ring (its cell types were loaded before)
+    pre_pids(D.pid, SI, R, zo2);
+    if (sm) {
+        const float rho_t = (D.st_prev >= 0 && e.y == D.st_prev) ? __int_as_float(e.x)
+                                                                 : own_density<ST>(Av, S, c, inv);
+        const float r6 = 6.0f * rho_t;
+        // the links mk of particle Pk (mirror m): moving-wall rule and momentum exchange
+        const int t = threadIdx.x;
+        auto particle_links = [&](int Pk, uint32_t mk, const PMir &m) {
+            if (Pk != L.accP[t]) {
+                if (L.accP[t] >= 0) macc_atomic(D, L, t);
+                L.accP[t] = Pk;
+            }
+            // rigid-body velocity at the node: c_q . u_w at the link midpoint equals
+            // c_q . (u_P + omega x (x - x_P)) because c_q . (omega x c_q) = 0
+            const float rx = ((float)x - m.ax) - m.fx, ry = ((float)y - m.ay) - m.fy, rz = ((float)z - m.az) - m.fz;
+            const float un0 = m.ux + (m.wy * rz - m.wz * ry);
+            const float un1 = m.uy + (m.wz * rx - m.wx * rz);
+            const float un2 = m.uz + (m.wx * ry - m.wy * rx);
+            // Delta j = -c_q (h*_qbar + h_q + 2 w_q): the shifted parts in FP32, the
+            // constants 2 w_q c_q as an exact integer count k in units of 1/18
+            float f0 = 0.f, f1 = 0.f, f2 = 0.f, dm = 0.f;
+            int k = 0;
+#pragma unroll
+            for (int q = 1; q < Q; ++q) {  // predicated, not branched
+                const bool b = (mk >> q) & 1u;
+                const float cu = cx(q) * un0 + cy(q) * un1 + cz(q) * un2;
+                const float add = b ? wq(q) * r6 * cu : 0.f;
+                const float s2 = b ? 2.0f * fi[q] + add : 0.f;  // h*_qbar + (h*_qbar + add)
+                if (cx(q)) f0 -= cx(q) * s2;
+                if (cy(q)) f1 -= cy(q) * s2;
+                if (cz(q)) f2 -= cz(q) * s2;
+                k += b ? kconst(q) : 0;
+                dm += add;
+                fi[q] += add;
+            }
+            int k0, k1, k2;
+            kunpack(k, k0, k1, k2);
+            const double F0 = (double)f0 + k0 * (1.0 / 18.0), F1 = (double)f1 + k1 * (1.0 / 18.0),
+                         F2 = (double)f2 + k2 * (1.0 / 18.0);
+            const double dx = rx, dy = ry, dz = rz;
+            L.acc[0][t] += F0;
+            L.acc[1][t] += F1;
+            L.acc[2][t] += F2;
+            L.acc[3][t] += dy * F2 - dz * F1;
+            L.acc[4][t] += dz * F0 - dx * F2;
+            L.acc[5][t] += dx * F1 - dy * F0;
+            L.acc[6][t] += (double)dm;
+        };
+        if (okP) particle_links(P, msk, pm);
+        else atomicOr(D.err, ERR_LG);  // not a particle: plain bounce-back
+        // links into further particles (rare): one particle at a time
+        uint32_t rest = sm & ~msk;
+        while (rest) {
+            int Pk;
+            const uint32_t mk = links_of_first(rest, Pk);
+            rest &= ~mk;
+            if ((unsigned)Pk >= (unsigned)D.np) {
+                atomicOr(D.err, ERR_LG);
+                continue;
+            }
+            particle_links(Pk, mk, pmir_load(D.pmir, Pk));
         }
-        fi[q] = SS::ld(p, Ph.inv);
     }
     const Moments M = cell_moments(fi);
-    if (!collide_store<ST>(Ph, fi, M, B, S, (unsigned)c)) atomicOr(D.err, ERR_NAN);
+    if (D.rhow != nullptr && D.st_cur >= 0 && store) {
+        // (density, launch stamp) as one 8-byte word: the stamp of the launch for a
+        // liquid cell, none for the row's other cells
+        const unsigned long long w = (unsigned long long)(unsigned)__float_as_int(1.0f + (float)M.drho) |
+                                     ((unsigned long long)(unsigned)(act ? D.st_cur : -1) << 32);
+        __builtin_nontemporal_store(w, (unsigned long long *)(D.rhow + c));
+    }
+    if (!collide_store<ST, true>(Ph, fi, M, B, S, (unsigned)c, store) && act) atomicOr(D.err, ERR_NAN);
 }
 
-// The fused step of one 64 x 4 tile of a plane: the cell types of the tile and its
-// halo are staged in LDS; lean cells (liquid, with liquid or wall neighbours only)
-// take the plain path in place; the other liquid and interface cells of the tile
-// are compacted into a list and handled by as few waves as they fill, so that the
-// boundary work (bounce-back, free surface, mass exchange, forces, lists) is not
-// repeated by every wave that holds one such cell.
+// tiles of the march: blocks go to the eight XCDs round-robin; each XCD takes whole
+// chunks of NZC planes (every eighth chunk), all tile columns of a chunk in turn
+__device__ __forceinline__ void march_of_block(int b, int nCols, int nChunks, int &col, int &chunk) {
+    if (nChunks % 8 == 0) {
+        const int i = b >> 3;
+        col = i % nCols;
+        chunk = (b & 7) + 8 * (i / nCols);
+    } else {
+        col = b % nCols;
+        chunk = b / nCols;
+    }
+}
+
+// The fused step (Eqs. LBE1, LBE2, bbrule, netforce, torque, momentum_transfer) for the
+// liquid cells of a 64 x 4 column through NZC planes.  Interface cells and liquid
+// cells next to gas or a moving or slipping face are left to k_general: each plane of
+// the column that holds one is appended to the list gen.
 template <int ST, bool MW>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MW ? 1 : 5))) void k_stream_collide(Geom G, Phys Ph, Dev D, int tilesX,
-                                                        int tilesY, int nTiles) {
-    __shared__ uint8_t tile[3][TY + 2][TX + 2];
-    __shared__ unsigned long long w3[3 * (TY + 2)], w1[3 * (TY + 2)];
-    __shared__ uint8_t list[TX * TY];
-    __shared__ int wcount[4];
-
-    const int t = tile_of_block(blockIdx.x, nTiles);
-    const int x0 = (t % tilesX) * TX;
-    const int rest = t / tilesX;
-    const int y0 = (rest % tilesY) * TY;
-    const int z = rest / tilesY;
-    const bool interior = x0 >= 1 && x0 + TX + 1 <= G.nx && y0 >= 1 && y0 + TY + 1 <= G.ny && z >= 1 &&
-                          z + 2 <= G.nz;
-    stage_flag_tile(G, D.flags, tile, x0, y0, z, interior);
-    __syncthreads();
-    build_row_masks(tile, w3, w1, !MW);
-    __syncthreads();
-
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE_MARCH))) void k_stream_collide(
+    Geom G, Phys Ph, Dev D, int tilesX, int tilesY, int nChunks, int *gen, int *ngen) {
+    __shared__ MarchLds L;
+    int col, chunk;
+    march_of_block(blockIdx.x, tilesX * tilesY, nChunks, col, chunk);
+    const int x0 = (col % tilesX) * TX, y0 = (col / tilesX) * TY;
+    const int zs = chunk * NZC, ze = min(zs + NZC, G.nz);
+    const bool intXY = x0 >= 1 && x0 + TX + 1 <= G.nx && y0 >= 1 && y0 + TY + 1 <= G.ny;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int lx = lane, ly = wv;
     const int x = x0 + lx, y = y0 + ly;
     const bool inb = x < G.nx && y < G.ny;
-    const uint8_t fl = inb ? tile[1][ly + 1][lx + 1] : WALL;
-    // any neighbour of the wave's cells that is neither liquid nor a wall (same
-    // plane: the 3 x 3 square; planes z +- 1: the plus shape)
-    constexpr int R6 = TY + 2;
-    const unsigned long long nb = w3[R6 + ly + 1] | w3[R6 + ly] | w3[R6 + ly + 2] | w3[ly + 1] |
-                                  w3[2 * R6 + ly + 1] | w1[ly] | w1[ly + 2] | w1[2 * R6 + ly] |
-                                  w1[2 * R6 + ly + 2];
-    const bool lean = inb && fl == LIQ && !((nb >> lx) & 1ull);
-    if (lean) {
-        if (interior) lean_cell<ST, true>(G, Ph, D, tile, lx, ly, x, y, z);
-        else lean_cell<ST, false>(G, Ph, D, tile, lx, ly, x, y, z);
-    }
 
-    // the tile's boundary cells, in lane order
-    const bool need = inb && !lean && (fl == LIQ || fl == IFC);
-    const unsigned long long m = __ballot(need);
-    if (lane == 0) wcount[wv] = (int)__popcll(m);
-    __syncthreads();
-    int base = 0, total = 0;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        const int n = wcount[w];
-        base += w < wv ? n : 0;
-        total += n;
+    // planes zs-1 .. zs+1 into the ring
+    const StageIdx SI = stage_idx(G, x0, y0);
+    RowPre R;
+    for (int p = zs - 1; p <= zs + 1; ++p) {
+        const int zo = stage_zo(G, p);
+        pre_flags(D.flags, SI, R, zo);
+        pre_pids(D.pid, SI, R, zo);
+        pre_store(L, R, p & 3, MW);
     }
-    if (need) list[base + (int)__popcll(m & ((1ull << lane) - 1ull))] = (uint8_t)threadIdx.x;
+    if (threadIdx.x < 2) L.genflag[threadIdx.x] = 0;
+    L.accP[threadIdx.x] = -1;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) L.acc[k][threadIdx.x] = 0.0;
     __syncthreads();
-    if (wv * 64 < total) {
-        const bool has = (int)threadIdx.x < total;
-        const int e = has ? list[threadIdx.x] : 0;
-        const int ex = e & (TX - 1), ey = e >> 6;
-        if (interior) sc_cell<ST, true, MW>(G, Ph, D, tile, ex, ey, x0 + ex, y0 + ey, z, has);
-        else sc_cell<ST, false, MW>(G, Ph, D, tile, ex, ey, x0 + ex, y0 + ey, z, has);
+
+    for (int z = zs; z < ze; ++z) {
+        // the ring's next plane z+2: cell types now, particle ids once the pulls of this
+        // plane are issued
+        const int zo2 = stage_zo(G, z + 2);
+        pre_flags(D.flags, SI, R, zo2);
+        const int s0 = z & 3, sm1 = (z - 1) & 3, sp1 = (z + 1) & 3;
+        // values the compiler would otherwise keep for the whole march (per-direction
+        // address terms of the lane, plane bases): recomputed in every plane instead
+        int xl = x, yl = y;
+        long long Sl = G.S;
+        __asm__ volatile("" : "+v"(xl), "+v"(yl));
+        __asm__ volatile("" : "+s"(Sl));
+        const void *Av = D.fA;
+        void *Bv = D.fB;
+        const uint8_t fl = inb ? L.ft[s0][ly + 1][lx + 1] : WALL;
+        const bool nbnf = nbr_any<MK_NF3, MK_NF1>(L, sm1, s0, sp1, ly, lx);
+        const bool nbbad = nbr_any<MK_BAD3, MK_BAD1>(L, sm1, s0, sp1, ly, lx);
+        const bool gen_c = inb && (fl == IFC || (fl == LIQ && nbbad));
+        const bool act = inb && fl == LIQ && !nbbad;
+        if (__ballot(gen_c) && lane == 0) L.genflag[z & 1] = 1;
+        if (__ballot(act)) {
+            if (intXY && z >= 1 && z + 2 <= G.nz)
+                march_cell<ST, true>(G, Ph, D, L, sm1, s0, sp1, lx, ly, xl, yl, z, act, inb && !gen_c, nbnf, Av,
+                                     Bv, Sl, SI, R, zo2);
+            else
+                march_cell<ST, false>(G, Ph, D, L, sm1, s0, sp1, lx, ly, xl, yl, z, act, inb && !gen_c, nbnf, Av,
+                                      Bv, Sl, SI, R, zo2);
+        } else {
+            pre_pids(D.pid, SI, R, zo2);
+        }
+        pre_store(L, R, (z + 2) & 3, MW);
+        __syncthreads();
+        if (threadIdx.x == 0 && L.genflag[z & 1]) {
+            L.genflag[z & 1] = 0;
+            const int slot = atomicAdd(ngen, 1);
+            gen[slot] = col + tilesX * tilesY * z;  // list capacity: every tile of the box
+        }
+    }
+    if (D.np > 0) macc_wave_flush(D, L);
+}
+
+// Row masks of the staged tile for the general path's selection (gas and, with moving
+// or slipping faces, walls).  One ballot per row; the caller syncs before and after.
+__device__ __forceinline__ void build_bad_masks(const uint8_t (&tile)[3][TY + 2][TX + 2],
+                                                unsigned long long (&b3)[3 * (TY + 2)],
+                                                unsigned long long (&b1)[3 * (TY + 2)], bool wall_bad) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int r = wv; r < 3 * (TY + 2); r += 4) {
+        const int lz = r / (TY + 2), ly = r - lz * (TY + 2);
+        const uint8_t a = tile[lz][ly][lane], b = tile[lz][ly][TX + (lane & 1)];
+        const unsigned long long lo = __ballot(a == GAS || (wall_bad && a == WALL));
+        const unsigned long long hi = __ballot(lane < 2 && (b == GAS || (wall_bad && b == WALL))) & 3ull;
+        if (lane == 0) {
+            const unsigned long long s1 = (lo >> 1) | (hi << 63), s2 = (lo >> 2) | (hi << 62);
+            b3[r] = lo | s1 | s2;
+            b1[r] = s1;
+        }
+    }
+}
+
+// The general path: interface cells and liquid cells next to gas or a moving or
+// slipping face, for the tiles (64 x 4 of one plane) that k_stream_collide listed.
+// A tile's cells are compacted and handled by as few waves as they fill (sc_cell).
+template <int ST, bool MW>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MW ? 1 : 5))) void k_general(
+    Geom G, Phys Ph, Dev D, int tilesX, int tilesY, const int *gen, const int *ngen) {
+    __shared__ uint8_t tile[3][TY + 2][TX + 2];
+    __shared__ unsigned long long b3[3 * (TY + 2)], b1[3 * (TY + 2)];
+    __shared__ uint8_t list[TX * TY];
+    __shared__ int wcount[4];
+    const int n = *ngen;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int t = gen[i];
+        const int x0 = (t % tilesX) * TX;
+        const int rest = t / tilesX;
+        const int y0 = (rest % tilesY) * TY;
+        const int z = rest / tilesY;
+        const bool interior = x0 >= 1 && x0 + TX + 1 <= G.nx && y0 >= 1 && y0 + TY + 1 <= G.ny && z >= 1 &&
+                              z + 2 <= G.nz;
+        stage_flag_tile(G, D.flags, tile, x0, y0, z, interior);
+        __syncthreads();
+        build_bad_masks(tile, b3, b1, MW);
+        __syncthreads();
+        const int lx = lane, ly = wv;
+        const bool inb = x0 + lx < G.nx && y0 + ly < G.ny;
+        const uint8_t fl = inb ? tile[1][ly + 1][lx + 1] : WALL;
+        constexpr int R6 = TY + 2;
+        const unsigned long long bad = b3[R6 + ly + 1] | b3[R6 + ly] | b3[R6 + ly + 2] | b3[ly + 1] |
+                                       b3[2 * R6 + ly + 1] | b1[ly] | b1[ly + 2] | b1[2 * R6 + ly] |
+                                       b1[2 * R6 + ly + 2];
+        const bool g = inb && (fl == IFC || (fl == LIQ && ((bad >> lx) & 1ull)));
+        const unsigned long long m = __ballot(g);
+        if (lane == 0) wcount[wv] = (int)__popcll(m);
+        __syncthreads();
+        int base = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int k = wcount[w];
+            base += w < wv ? k : 0;
+            total += k;
+        }
+        if (g) list[base + (int)__popcll(m & ((1ull << lane) - 1ull))] = (uint8_t)threadIdx.x;
+        __syncthreads();
+        if (wv * 64 < total) {
+            const bool has = (int)threadIdx.x < total;
+            const int e = has ? list[threadIdx.x] : 0;
+            const int ex = e & (TX - 1), ey = e >> 6;
+            if (interior) sc_cell<ST, true, MW>(G, Ph, D, tile, ex, ey, x0 + ex, y0 + ey, z, has);
+            else sc_cell<ST, false, MW>(G, Ph, D, tile, ex, ey, x0 + ex, y0 + ey, z, has);
+        }
+        __syncthreads();
+    }
+}
+
+// (density, stamp) of every liquid and interface cell from its populations in A, for
+// the first launch after the populations were set from outside
+template <int ST>
+__global__ void k_rhow_fill(Geom G, Phys Ph, Dev D, int stamp) {
+    using SS = Store<ST>;
+    const typename SS::T *A = (const typename SS::T *)D.fA;
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < G.N;
+         c += (long long)gridDim.x * blockDim.x) {
+        const uint8_t f = D.flags[c];
+        int2 w = make_int2(0, -1);
+        if (f == LIQ || f == IFC) {
+            float fa[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) fa[q] = SS::ld(A + q * G.S + c, Ph.inv);
+            w = make_int2(__float_as_int(1.0f + (float)cell_moments(fa).drho), stamp);
+        }
+        D.rhow[c] = w;
     }
 }
 
