@@ -783,6 +783,24 @@ __device__ __noinline__ float own_density(const void *A, long long S, int c, flo
     return 1.0f + (float)cell_moments(fa).drho;
 }
 
+// Source offsets of a lane's pulls: the cell x - c_q is c + dx[c_x] + dy[c_y] + dz[c_z]
+// with dx[1] the step to x-1 and dx[-1] the step to x+1 (and so on), wrapped at periodic
+// faces.  Beyond a non-periodic face the step is 0: that pull reads the cell itself,
+// and the link takes bounce-back instead.  dx is per lane, dy per wave row, dz per plane.
+struct SrcOff {
+    int xm, xp, ym, yp, zm, zp;
+};
+template <int Q_>
+__device__ __forceinline__ int src_off(const SrcOff &o) {
+    return (cx(Q_) == 1 ? o.xm : cx(Q_) == -1 ? o.xp : 0) + (cy(Q_) == 1 ? o.ym : cy(Q_) == -1 ? o.yp : 0) +
+           (cz(Q_) == 1 ? o.zm : cz(Q_) == -1 ? o.zp : 0);
+}
+__device__ __forceinline__ int step_to(int v, int d, int n, int per, int stride) {
+    const int w = v + d;
+    if (w >= 0 && w < n) return d * stride;
+    return per ? (wrapc(w, n) - v) * stride : 0;
+}
+
 // One cell of a row in the marching pass: a liquid cell whose neighbours are liquid,
 // interface, particle nodes or resting walls (act).  Pull streaming (Eq. LBE1); a
 // source beyond a resting wall gives half-way bounce-back, a particle node the
@@ -792,79 +810,78 @@ __device__ __noinline__ float own_density(const void *A, long long S, int c, flo
 // store set and act clear (gas and particle nodes of the row) write values that no
 // rule reads, so that every row of every population is written whole and once;
 // interface cells and lanes outside the box leave their words to the general path.
-template <int ST, bool INTERIOR>
+template <int ST>
 __device__ __forceinline__ void march_cell(const Geom &G, const Phys &Ph, const Dev &D, MarchLds &L,
-                                           int sm1, int s0, int sp1, int lx, int ly, int x, int y, int z,
-                                           bool act, bool store, bool nbnf, const void *Av, void *Bv,
-                                           long long S, const StageIdx &SI, RowPre &R, int zo2) {
+                                           int sm1, int s0, int sp1, int lx, int ly, int x, int y, int z, int c,
+                                           const SrcOff &so, bool act, bool store, bool nbnf, const void *Av,
+                                           void *Bv, long long S, const StageIdx &SI, RowPre &R, int zo2) {
     using SS = Store<ST>;
     using T = typename SS::T;
-    const int nx = G.nx, ny = G.ny, nz = G.nz, nxy = nx * ny;
-    const int c = store ? x + nx * y + nxy * z : 0;
     const T *A = (const T *)Av;
     T *B = (T *)Bv;
     const float inv = Ph.inv;
     auto slot = [&](int q) { return cz(q) == 1 ? sm1 : (cz(q) == -1 ? sp1 : s0); };  // plane z - c_z
-    auto src = [&](int q) -> int {
-        if (INTERIOR) return c - (cx(q) + cy(q) * nx + cz(q) * nxy);
-        const int sx = wrapc(x - cx(q), nx), sy = wrapc(y - cy(q), ny), sz = wrapc(z - cz(q), nz);
-        return sx + nx * sy + nxy * sz;
-    };
-    // bounce-back sources: particle nodes (sm) and, outside the interior, walls
+    // bounce-back sources: particle nodes (sm) and walls (wm)
     uint32_t sm = 0, wm = 0;
     if (act && nbnf) {
 #pragma unroll
         for (int q = 1; q < Q; ++q) {
             const uint8_t sf = L.ft[slot(q)][ly + 1 - cy(q)][lx + 1 - cx(q)];
             sm |= (uint32_t)(sf == SOL) << q;
-            if (!INTERIOR) wm |= (uint32_t)(sf == WALL) << q;
+            wm |= (uint32_t)(sf == WALL) << q;
         }
     }
     const uint32_t bb = sm | wm;
-    // the particle P of the first particle-node link (in direction order) and the
-    // links it owns, from the staged ids, before the global loads are issued
-    auto links_of_first = [&](uint32_t rest, int &P) -> uint32_t {
-        P = -1;
-        uint32_t msk = 0;
-        bool found = false;
+    // the particle P of the first particle-node link (in direction order) and whether
+    // any other such link leads elsewhere, from the staged ids
+    int P = -1;
+    bool multi = false;
+    if (sm) {
+#pragma unroll
+        for (int q = Q - 1; q >= 1; --q) {
+            const int p = L.pt[slot(q)][ly + 1 - cy(q)][lx + 1 - cx(q)];
+            P = ((sm >> q) & 1u) ? p : P;
+        }
+        unsigned diff = 0;
 #pragma unroll
         for (int q = 1; q < Q; ++q) {
-            const bool b = (rest >> q) & 1u;
             const int p = L.pt[slot(q)][ly + 1 - cy(q)][lx + 1 - cx(q)];
-            if (b && !found) P = p;
-            found = found || b;
-            msk |= (uint32_t)(b && p == P) << q;
+            diff |= ((sm >> q) & 1u) ? (unsigned)(p ^ P) : 0u;
         }
-        return msk;
-    };
-    int P = -1;
-    const uint32_t msk = sm ? links_of_first(sm, P) : 0u;
+        multi = diff != 0u;
+    }
     const bool okP = (unsigned)P < (unsigned)D.np;
     // rho_w of Eq. bbrule: the density of this cell at t, as the launch before stored it
     int2 e = make_int2(0, -1);
     if (sm && D.rhow != nullptr && D.st_prev >= 0) e = D.rhow[c];
     PMir pm{};
     if (sm && okP) pm = pmir_load(D.pmir, P);
-    // every lane issues every load (no branches): a bounce-back link reads the cell's
-    // own opposite population, a pull its source, a lane without a cell the first word
-    // of the plane (its value is not used)
+    // pulls (every lane loads; a lane without a cell reads a neighbour's word and drops it)
     float fi[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const bool b = (bb >> q) & 1u;
-        const T *base = b ? A + opp(q) * S : A + q * S;
-        const unsigned idx = act ? (unsigned)(b ? c : src(q)) : 0u;
-        const float v = SS::ld(base + idx, inv);
-        fi[q] = act ? v : 0.f;
+#define FSL_PULL(QQ)                                                                   \
+    {                                                                                  \
+        const float v = SS::ld(A + QQ * S + (unsigned)(c + src_off<QQ>(so)), inv);    \
+        fi[QQ] = act ? v : 0.f;                                                        \
     }
+    FSL_PULL(0) FSL_PULL(1) FSL_PULL(2) FSL_PULL(3) FSL_PULL(4) FSL_PULL(5) FSL_PULL(6)
+    FSL_PULL(7) FSL_PULL(8) FSL_PULL(9) FSL_PULL(10) FSL_PULL(11) FSL_PULL(12) FSL_PULL(13)
+    FSL_PULL(14) FSL_PULL(15) FSL_PULL(16) FSL_PULL(17) FSL_PULL(18)
+#undef FSL_PULL
     // particle ids of plane z+2 for the ring (its cell types were loaded before)
     pre_pids(D.pid, SI, R, zo2);
+    // bounce-back links take the cell's own opposite population instead
+    if (bb) {
+#pragma unroll
+        for (int q = 1; q < Q; ++q)
+            if ((bb >> q) & 1u) fi[q] = SS::ld(A + opp(q) * S + (unsigned)c, inv);
+    }
     if (sm) {
         const float rho_t = (D.st_prev >= 0 && e.y == D.st_prev) ? __int_as_float(e.x)
                                                                  : own_density<ST>(Av, S, c, inv);
-        const float r6 = 6.0f * rho_t;
-        // the links mk of particle Pk (mirror m): moving-wall rule and momentum exchange
         const int t = threadIdx.x;
+        // the links mk of particle Pk (mirror m): moving-wall rule and momentum exchange.
+        // With rho u = rho_w u_w the link adds a_q = 6 w_q c_q . rho u to the bounced
+        // population, and Delta j = -c_q (h*_qbar + h_q + 2 w_q) with h_q = h*_qbar + a_q.
         auto particle_links = [&](int Pk, uint32_t mk, const PMir &m) {
             if (Pk != L.accP[t]) {
                 if (L.accP[t] >= 0) macc_atomic(D, L, t);
@@ -873,30 +890,42 @@ __device__ __forceinline__ void march_cell(const Geom &G, const Phys &Ph, const 
             // rigid-body velocity at the node: c_q . u_w at the link midpoint equals
             // c_q . (u_P + omega x (x - x_P)) because c_q . (omega x c_q) = 0
             const float rx = ((float)x - m.ax) - m.fx, ry = ((float)y - m.ay) - m.fy, rz = ((float)z - m.az) - m.fz;
-            const float un0 = m.ux + (m.wy * rz - m.wz * ry);
-            const float un1 = m.uy + (m.wz * rx - m.wx * rz);
-            const float un2 = m.uz + (m.wx * ry - m.wy * rx);
-            // Delta j = -c_q (h*_qbar + h_q + 2 w_q): the shifted parts in FP32, the
-            // constants 2 w_q c_q as an exact integer count k in units of 1/18
-            float f0 = 0.f, f1 = 0.f, f2 = 0.f, dm = 0.f;
-            int k = 0;
+            const float ru0 = rho_t * (m.ux + (m.wy * rz - m.wz * ry));
+            const float ru1 = rho_t * (m.uy + (m.wz * rx - m.wx * rz));
+            const float ru2 = rho_t * (m.uz + (m.wx * ry - m.wy * rx));
+            // a_q for axis links (6 w = 1/3) and diagonal links (6 w = 1/6)
+            const float ax = ru0 * (1.0f / 3.0f), ay = ru1 * (1.0f / 3.0f), az = ru2 * (1.0f / 3.0f);
+            const float hxy_p = (ru0 + ru1) * (1.0f / 6.0f), hxy_m = (ru0 - ru1) * (1.0f / 6.0f);
+            const float hxz_p = (ru0 + ru2) * (1.0f / 6.0f), hxz_m = (ru0 - ru2) * (1.0f / 6.0f);
+            const float hyz_p = (ru1 + ru2) * (1.0f / 6.0f), hyz_m = (ru1 - ru2) * (1.0f / 6.0f);
+            auto aq = [&](int q) -> float {  // 6 w_q c_q . rho u
+                if (q <= 6) return (cx(q) ? cx(q) * ax : 0.f) + (cy(q) ? cy(q) * ay : 0.f) + (cz(q) ? cz(q) * az : 0.f);
+                if (cz(q) == 0) return cx(q) == cy(q) ? cx(q) * hxy_p : cx(q) * hxy_m;
+                if (cy(q) == 0) return cx(q) == cz(q) ? cx(q) * hxz_p : cx(q) * hxz_m;
+                return cy(q) == cz(q) ? cy(q) * hyz_p : cy(q) * hyz_m;
+            };
+            // sum over the links of -c_q (h*_qbar + h_q), FP32
+            float f0 = 0.f, f1 = 0.f, f2 = 0.f;
 #pragma unroll
-            for (int q = 1; q < Q; ++q) {  // predicated, not branched
+            for (int q = 1; q < Q; ++q) {
                 const bool b = (mk >> q) & 1u;
-                const float cu = cx(q) * un0 + cy(q) * un1 + cz(q) * un2;
-                const float add = b ? wq(q) * r6 * cu : 0.f;
-                const float s2 = b ? 2.0f * fi[q] + add : 0.f;  // h*_qbar + (h*_qbar + add)
+                const float a = b ? aq(q) : 0.f;
+                const float s2 = b ? 2.0f * fi[q] + a : 0.f;
                 if (cx(q)) f0 -= cx(q) * s2;
                 if (cy(q)) f1 -= cy(q) * s2;
                 if (cz(q)) f2 -= cz(q) * s2;
-                k += b ? kconst(q) : 0;
-                dm += add;
-                fi[q] += add;
+                fi[q] += a;
             }
-            int k0, k1, k2;
-            kunpack(k, k0, k1, k2);
-            const double F0 = (double)f0 + k0 * (1.0 / 18.0), F1 = (double)f1 + k1 * (1.0 / 18.0),
-                         F2 = (double)f2 + k2 * (1.0 / 18.0);
+            // the constant parts 2 w_q c_q as exact counts (units of 1/18) from the link
+            // mask: axis links count 2, diagonal links 1; and the added mass sum a_q
+            // (bit q set for the directions with c_q = -1 and = +1 along each axis)
+            const int kx = 2 * (__popc(mk & 0x4u) - __popc(mk & 0x2u)) + __popc(mk & 0x6600u) - __popc(mk & 0x1980u);
+            const int ky = 2 * (__popc(mk & 0x10u) - __popc(mk & 0x8u)) + __popc(mk & 0x60500u) - __popc(mk & 0x18280u);
+            const int kz = 2 * (__popc(mk & 0x40u) - __popc(mk & 0x20u)) + __popc(mk & 0x55000u) - __popc(mk & 0x2a800u);
+            // sum_q a_q = rho u . sum_q 6 w_q c_q = -(rho u . k) / 6 with k = -sum c_q m_q
+            const float dm = -(ru0 * (float)kx + ru1 * (float)ky + ru2 * (float)kz) * (1.0f / 6.0f);
+            const double F0 = (double)f0 + kx * (1.0 / 18.0), F1 = (double)f1 + ky * (1.0 / 18.0),
+                         F2 = (double)f2 + kz * (1.0 / 18.0);
             const double dx = rx, dy = ry, dz = rz;
             L.acc[0][t] += F0;
             L.acc[1][t] += F1;
@@ -906,19 +935,29 @@ __device__ __forceinline__ void march_cell(const Geom &G, const Phys &Ph, const 
             L.acc[5][t] += dx * F1 - dy * F0;
             L.acc[6][t] += (double)dm;
         };
-        if (okP) particle_links(P, msk, pm);
-        else atomicOr(D.err, ERR_LG);  // not a particle: plain bounce-back
-        // links into further particles (rare): one particle at a time
-        uint32_t rest = sm & ~msk;
-        while (rest) {
-            int Pk;
-            const uint32_t mk = links_of_first(rest, Pk);
-            rest &= ~mk;
-            if ((unsigned)Pk >= (unsigned)D.np) {
-                atomicOr(D.err, ERR_LG);
-                continue;
+        if (!multi && okP) {
+            particle_links(P, sm, pm);
+        } else {
+            // links into more than one particle, or an inconsistent owner (rare): one
+            // particle at a time
+            uint32_t rest = sm;
+            while (rest) {
+                const int q0 = __ffs(rest) - 1;
+                int Pk = -1;
+#pragma unroll
+                for (int q = 1; q < Q; ++q)
+                    if (q == q0) Pk = L.pt[slot(q)][ly + 1 - cy(q)][lx + 1 - cx(q)];
+                uint32_t mk = 0;
+#pragma unroll
+                for (int q = 1; q < Q; ++q)
+                    mk |= (uint32_t)(((rest >> q) & 1u) && L.pt[slot(q)][ly + 1 - cy(q)][lx + 1 - cx(q)] == Pk) << q;
+                rest &= ~mk;
+                if ((unsigned)Pk >= (unsigned)D.np) {  // not a particle: plain bounce-back
+                    atomicOr(D.err, ERR_LG);
+                    continue;
+                }
+                particle_links(Pk, mk, pmir_load(D.pmir, Pk));
             }
-            particle_links(Pk, mk, pmir_load(D.pmir, Pk));
         }
     }
     const Moments M = cell_moments(fi);
@@ -957,7 +996,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE_MARCH))
     march_of_block(blockIdx.x, tilesX * tilesY, nChunks, col, chunk);
     const int x0 = (col % tilesX) * TX, y0 = (col / tilesX) * TY;
     const int zs = chunk * NZC, ze = min(zs + NZC, G.nz);
-    const bool intXY = x0 >= 1 && x0 + TX + 1 <= G.nx && y0 >= 1 && y0 + TY + 1 <= G.ny;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int lx = lane, ly = wv;
     const int x = x0 + lx, y = y0 + ly;
@@ -989,6 +1027,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE_MARCH))
         int xl = x, yl = y;
         long long Sl = G.S;
         __asm__ volatile("" : "+v"(xl), "+v"(yl));
+        // the lane's cell for addresses (lanes beyond the box take the last one)
+        const int xc = min(xl, G.nx - 1), yc = min(yl, G.ny - 1);
         __asm__ volatile("" : "+s"(Sl));
         const void *Av = D.fA;
         void *Bv = D.fB;
@@ -999,12 +1039,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE_MARCH))
         const bool act = inb && fl == LIQ && !nbbad;
         if (__ballot(gen_c) && lane == 0) L.genflag[z & 1] = 1;
         if (__ballot(act)) {
-            if (intXY && z >= 1 && z + 2 <= G.nz)
-                march_cell<ST, true>(G, Ph, D, L, sm1, s0, sp1, lx, ly, xl, yl, z, act, inb && !gen_c, nbnf, Av,
-                                     Bv, Sl, SI, R, zo2);
-            else
-                march_cell<ST, false>(G, Ph, D, L, sm1, s0, sp1, lx, ly, xl, yl, z, act, inb && !gen_c, nbnf, Av,
-                                      Bv, Sl, SI, R, zo2);
+            const int nxy = G.nx * G.ny;
+            SrcOff so;
+            so.xm = step_to(xc, -1, G.nx, G.per[0], 1);
+            so.xp = step_to(xc, 1, G.nx, G.per[0], 1);
+            so.ym = step_to(yc, -1, G.ny, G.per[1], G.nx);
+            so.yp = step_to(yc, 1, G.ny, G.per[1], G.nx);
+            so.zm = step_to(z, -1, G.nz, G.per[2], nxy);
+            so.zp = step_to(z, 1, G.nz, G.per[2], nxy);
+            const int c = xc + G.nx * yc + nxy * z;
+            march_cell<ST>(G, Ph, D, L, sm1, s0, sp1, lx, ly, xl, yl, z, c, so, act, inb && !gen_c, nbnf, Av, Bv, Sl,
+                           SI, R, zo2);
         } else {
             pre_pids(D.pid, SI, R, zo2);
         }
