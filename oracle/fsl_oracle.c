@@ -62,7 +62,7 @@ static void init_lattice_tables(void)
 }
 
 enum { GAS = 0, LIQ = 1, IFC = 2, SOL = 3 };
-enum { ERR_LG = 1u, ERR_NAN = 2u, ERR_CAP = 4u, ERR_VOL = 8u, ERR_ARG = 16u };
+enum { ERR_LG = 1u, ERR_NAN = 2u, ERR_CAP = 4u, ERR_VOL = 8u, ERR_ARG = 16u, ERR_PART = 32u };
 enum { CV_NONE = 0, CV_F = 1, CV_E0 = 2, CV_E = 3, CV_NEWG = 4, CV_NEWL = 5 };
 
 struct orc_ctx {
@@ -725,10 +725,39 @@ static void coverage_update(orc_ctx *c)
 }
 
 /* ---- particles ---------------------------------------------------------------- */
+/* Sphere positions this implementation covers: coverage, pair search and lever arms
+ * take node coordinates without wrapping, so on a periodic axis a sphere and its links
+ * must stay clear of the faces (centre in [R + 1, n - R - 2]); on a walled axis the
+ * centre lies in the box (faces at -1/2 and n - 1/2).  Every component finite. */
+static int position_ok(const orc_ctx *c, const double *x, double R)
+{
+    for (int a = 0; a < 3; ++a) {
+        double v = x[a];
+        if (!isfinite(v)) return 0;
+        if (c->cfg.periodic[a]) {
+            if (v < R + 1.0 || v > c->cfg.n[a] - R - 2.0) return 0;
+        } else if (v < -0.5 || v > c->cfg.n[a] - 0.5) {
+            return 0;
+        }
+    }
+    return 1;
+}
+
 int orc_particles_set(orc_ctx *c, int n, const double *x, const double *u,
                       const double *omega, const double *R, const double *rho_p)
 {
     if (n < 0 || n > c->cfg.max_particles) { c->err |= ERR_ARG; return -1; }
+    for (int P = 0; P < n; ++P) {
+        if (!(R[P] > 0.0) || !(rho_p[P] > 0.0) || !position_ok(c, x + 3 * P, R[P])) {
+            c->err |= ERR_ARG;
+            return -1;
+        }
+        for (int a = 0; a < 3; ++a)
+            if ((u && !isfinite(u[3 * P + a])) || (omega && !isfinite(omega[3 * P + a]))) {
+                c->err |= ERR_ARG;
+                return -1;
+            }
+    }
     c->np = n;
     c->have_prev = 0;
     for (int P = 0; P < n; ++P) {
@@ -842,6 +871,8 @@ static void particles_integrate(orc_ctx *c)
         c->pTp[k] = c->pT[k];
     }
     c->have_prev = 1;
+    for (int P = 0; P < np; ++P)
+        if (!position_ok(c, c->px + 3 * P, c->pR[P])) c->err |= ERR_PART;
 }
 
 /* ---- one lattice step ----------------------------------------------------------- */

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+
+#include <cmath>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -117,7 +119,7 @@ Layout layout_of(const fsl_config *c) {
     L.pFTp = take((size_t)L.maxP * 6 * 8);
     L.pFl = take((size_t)L.maxP * 3 * 8);
     L.pmir = take((size_t)L.maxP * 64);
-    L.rhow = take(c->max_particles > 0 ? (size_t)L.S * 8 : 0);
+    L.rhow = take(c->max_particles > 0 ? (size_t)L.S * 4 : 0);
     L.gStart = take((size_t)(L.ncellMax + 1) * 4);
     L.gCount = take((size_t)L.ncellMax * 4);
     L.gIdx = take((size_t)L.maxP * 4);
@@ -169,7 +171,7 @@ struct fsl_ctx {
     int profiling;
     int have_prev;  // a previous step's hydrodynamic force exists (particle update)
     int stamp;      // stamp of the next stream-collide launch (>= 1)
-    int rhow_ok;    // entries stamped stamp - 1 hold the densities of the populations in A
+    int rhow_ok;    // the density words of stamp - 1 hold the densities of the populations in A
     std::vector<hipEvent_t> evpool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> evlog;
     double prof_ms[NPROF];
@@ -468,8 +470,8 @@ int enqueue_steps(fsl_ctx *c, int n, int split) {
             c->stamp = 1;
             c->rhow_ok = 0;
             if (D.rhow)
-                hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * c->G.S, 256, 8192)), dim3(256), 0, c->st,
-                                   (int *)D.rhow, 2 * c->G.S, 0);
+                hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(c->G.S, 256, 8192)), dim3(256), 0, c->st,
+                                   (int *)D.rhow, c->G.S, (int)RHOW_NONE);
         } else {
             c->rhow_ok = 1;
         }
@@ -542,6 +544,8 @@ int read_error(fsl_ctx *c) {
     if (e & ERR_CAP) return fail(c, FSL_E_CAPACITY, "a list, the bubble table or the gas-part list overflowed");
     if (e & ERR_NAN) return fail(c, FSL_E_NUMERIC, "NaN density or velocity");
     if (e & ERR_LG) return fail(c, FSL_E_INVARIANT, "a liquid cell has a gas neighbour");
+    if (e & ERR_PART)
+        return fail(c, FSL_E_INVARIANT, "a sphere centre left the box or came closer than R + 1 to a periodic face");
     return fail(c, FSL_E_NUMERIC, "device error");
 }
 
@@ -566,6 +570,8 @@ int window_forward(fsl_ctx *c, int T, int k, double *J) {
     if (c->cfg.integrate && D.np > 0) return fail(c, FSL_E_ARG, "window_forward: spheres must be kinematic (integrate off)");
     for (int a = 0; a < 3; ++a)
         if (c->cfg.boundary[a] == FSL_FREESLIP) return fail(c, FSL_E_ARG, "window_forward: free-slip faces");
+    // the adjoint transposes resting walls only (plain bounce-back)
+    if (c->Ph.moving_walls) return fail(c, FSL_E_ARG, "window_forward: moving box faces");
     int *bad = (int *)(A.acc + 32);
     hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, c->st, A.acc, 64LL, 0.0);
     hipLaunchKernelGGL(k_win_check, dim3(grid_for(c->G.N, 256, 2048)), dim3(256), 0, c->st, c->G, D, bad);
@@ -719,13 +725,13 @@ int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, 
     D.rhog = (float *)(w + L.rhog);
     D.kappa = cfg->sigma != 0.0 ? (float *)(w + L.kappa) : nullptr;
     D.wallu = (float *)(w + L.wallu);
-    D.rhow = cfg->max_particles > 0 ? (int2 *)(w + L.rhow) : nullptr;
+    D.rhow = cfg->max_particles > 0 ? (unsigned *)(w + L.rhow) : nullptr;
     D.st_prev = D.st_cur = -1;
     c->stamp = 1;
     c->rhow_ok = 0;
-    if (D.rhow)  // stamp 0 never matches a launch
-        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(2 * L.S, 256, 8192)), dim3(256), 0, c->st, (int *)D.rhow,
-                           2 * L.S, 0);
+    if (D.rhow)  // no density held
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(L.S, 256, 8192)), dim3(256), 0, c->st, (int *)D.rhow, L.S,
+                           (int)RHOW_NONE);
     {
         // face velocities (a periodic axis has no face)
         float wv[18];
@@ -844,6 +850,12 @@ int fsl_particles_set(fsl_ctx *c, int n, const double *x, const double *u, const
         }
         if (!(R[P] > 0.0) || !(rho_p[P] > 0.0)) return fail(c, FSL_E_ARG, "particles_set: radius and density must be > 0");
         if (R[P] > 60.0) return fail(c, FSL_E_ARG, "particles_set: radius above 60 cells");
+        if (!sphere_supported(t + P_X, R[P], c->cfg.n, c->G.per))
+            return fail(c, FSL_E_ARG, "particles_set: a centre is not finite, outside the box, or closer than "
+                                      "R + 1 to a periodic face");
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(t[P_U + a]) || !std::isfinite(t[P_W + a]))
+                return fail(c, FSL_E_ARG, "particles_set: a velocity is not finite");
         t[P_R] = R[P];
         t[P_RHO] = rho_p[P];
         Rmax = std::max(Rmax, R[P]);

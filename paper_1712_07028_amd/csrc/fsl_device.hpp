@@ -40,6 +40,9 @@ constexpr uint8_t GAS = 0, LIQ = 1, IFC = 2, SOL = 3, WALL = 4;
 
 // device error bits (latched, reported by the host at the next sync)
 constexpr unsigned ERR_LG = 1u, ERR_NAN = 2u, ERR_CAP = 4u, ERR_VOL = 8u;
+// a sphere centre left the box, or came closer than R + 1 to a periodic face (the
+// coverage, pair search and lever arms do not wrap)
+constexpr unsigned ERR_PART = 16u;
 
 // conversion marks (one byte per cell, zero outside the conversion phase)
 constexpr uint8_t CV_F = 1, CV_E0 = 2, CV_E = 4, CV_NEWG = 8, CV_NEWL = 16;
@@ -158,11 +161,11 @@ struct Dev {
     float *rhog;                     // FP32 gas density per bubble id (through root)
     float *kappa;                    // interface curvature (null without surface tension)
     float *wallu;                    // face velocities [axis][low, high][component]
-    // (density, launch stamp) of every liquid and interface cell, as computed from its
-    // populations by the launch stamped .y (null without particles): Eq. bbrule's
-    // rho_w for the next launch, which reads entries stamped st_prev (< 0: none) and
-    // writes them stamped st_cur (< 0: none)
-    int2 *rhow;
+    // density of every liquid and interface cell as computed from its populations by
+    // the last launch (null without particles), for Eq. bbrule's rho_w in the next
+    // launch: see rhow_word; a launch reads words of stamp st_prev and writes words of
+    // stamp st_cur (< 0: none)
+    unsigned *rhow;
     int st_prev, st_cur;
     int cap;                         // conversion list capacity
     int capEv;                       // coverage event list capacity
@@ -180,6 +183,35 @@ __device__ __forceinline__ PMir pmir_load(const float4 *pmir, int P) {
     const float4 *m = pmir + 4LL * P;
     const float4 a = m[0], b = m[1], c = m[2];
     return PMir{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+}
+
+// The sphere positions the library handles: every component finite; on a
+// non-periodic axis the centre inside the box (faces at -1/2 and n - 1/2); on a
+// periodic axis at least R + 1 from the first and R + 2 from the last node, so that
+// the sphere and its links never wrap.
+__host__ __device__ inline bool sphere_supported(const double x[3], double R, const int n[3], const int per[3]) {
+    for (int a = 0; a < 3; ++a) {
+        const double v = x[a];
+        if (!(v == v) || v - v != 0.0) return false;  // NaN or infinite
+        if (per[a]) {
+            if (!(v >= R + 1.0 && v <= n[a] - R - 2.0)) return false;
+        } else if (!(v >= -0.5 && v <= n[a] - 0.5)) {
+            return false;
+        }
+    }
+    return true;
+}
+
+// Stored density word: the FP32 density with its lowest mantissa bit replaced by the
+// parity of the stamp of the launch that wrote it (a change of at most one unit in the
+// last place); RHOW_NONE (a NaN) where no density is held.  A reader takes the word
+// only with the parity of the stamp it expects.
+constexpr unsigned RHOW_NONE = 0x7fc00000u;
+__device__ __forceinline__ unsigned rhow_word(float rho, int stamp) {
+    return (__float_as_uint(rho) & ~1u) | (unsigned)(stamp & 1);
+}
+__device__ __forceinline__ bool rhow_valid(unsigned w, int stamp) {
+    return stamp >= 0 && (w & 0x7f800000u) != 0x7f800000u && (w & 1u) == (unsigned)(stamp & 1);
 }
 
 // ---- small helpers ---------------------------------------------------------------

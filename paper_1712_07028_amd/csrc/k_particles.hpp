@@ -52,14 +52,23 @@ __global__ __launch_bounds__(256) void k_part_forces(Dev D, int integrate) {
     if (threadIdx.x == 0 && red[0] != 0.0) unsafeAtomicAdd(D.ledger, -red[0]);
 }
 
-__device__ __forceinline__ void sphere_box(const Geom &G, const double *x, double R, int lo[3], int hi[3]) {
+// node box [lo, hi] of a sphere clipped to the box; false when nothing is left (a
+// sphere outside the box, which the next synchronising call reports)
+__device__ __forceinline__ bool sphere_box(const Geom &G, const double *x, double R, int lo[3], int hi[3]) {
     const int n[3] = {G.nx, G.ny, G.nz};
+    bool ok = true;
     for (int a = 0; a < 3; ++a) {
-        lo[a] = (int)floor(x[a] - R);
-        hi[a] = (int)ceil(x[a] + R);
-        if (lo[a] < 0) lo[a] = 0;
-        if (hi[a] > n[a] - 1) hi[a] = n[a] - 1;
+        const double l = floor(x[a] - R), h = ceil(x[a] + R);
+        if (!(l <= n[a] - 1.0 && h >= 0.0)) {  // also NaN
+            lo[a] = 0;
+            hi[a] = -1;
+            ok = false;
+            continue;
+        }
+        lo[a] = l < 0.0 ? 0 : (int)l;
+        hi[a] = h > n[a] - 1.0 ? n[a] - 1 : (int)h;
     }
+    return ok;
 }
 
 __device__ __forceinline__ bool inside(double i, double j, double k, const double *x, double R) {
@@ -370,6 +379,7 @@ __global__ void k_substep(Dev D, Geom G, double dt, double g0, double g1, double
             }
             fl[d] = 0.0;
         }
+        if (!sphere_supported(t + P_X, R, n, G.per)) atomicOr(D.err, ERR_PART);
     }
 }
 
@@ -453,9 +463,13 @@ __global__ __launch_bounds__(256) void k_cov_scan(Geom G, Dev D) {
     if (P >= D.np) return;
     const double *t = D.ptab + (long long)P * P_STRIDE;
     int lo[3], hi[3], lo2[3], hi2[3];
-    sphere_box(G, t + P_X, t[P_R], lo, hi);
-    sphere_box(G, t + P_XOLD, t[P_R], lo2, hi2);
-    for (int a = 0; a < 3; ++a) { lo[a] = min(lo[a], lo2[a]); hi[a] = max(hi[a], hi2[a]); }
+    const bool inNew = sphere_box(G, t + P_X, t[P_R], lo, hi);
+    const bool inOld = sphere_box(G, t + P_XOLD, t[P_R], lo2, hi2);
+    if (!inNew && !inOld) return;
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = !inNew ? lo2[a] : !inOld ? lo[a] : min(lo[a], lo2[a]);
+        hi[a] = !inNew ? hi2[a] : !inOld ? hi[a] : max(hi[a], hi2[a]);
+    }
     int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
     int tot = ex * ey * ez;
     if (cov_claims(D, t)) {
@@ -612,7 +626,7 @@ __global__ void k_unc_apply(Geom G, Phys Ph, Dev D, double *phi) {
         store_equilibrium<ST>(G, Ph, D.fB, c, rb - 1.0, u0, u1, u2);
         // the density of the stored populations, for rho_w (Eq. bbrule) in the next launch
         if (D.rhow != nullptr && D.st_cur >= 0)
-            D.rhow[c] = make_int2(__float_as_int((float)cell_rho<ST>(G, D, Ph, D.fB, c)), D.st_cur);
+            D.rhow[c] = rhow_word((float)cell_rho<ST>(G, D, Ph, D.fB, c), D.st_cur);
         unsafeAtomicAdd(D.ledger, -rb);
         phi[c] = 1.0;
         if (type == IFC) {

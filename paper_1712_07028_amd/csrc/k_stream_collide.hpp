@@ -346,9 +346,9 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
         if (!needOwn && sm) {
             bool have = false;
             if (D.rhow != nullptr && D.st_prev >= 0) {
-                const int2 e = D.rhow[c];
-                have = e.y == D.st_prev;
-                rho_t = __int_as_float(e.x);
+                const unsigned e = D.rhow[c];
+                have = rhow_valid(e, D.st_prev);
+                rho_t = __uint_as_float(e);
             }
             needOwn = !have;
         }
@@ -515,8 +515,7 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
 
         // the density of the populations stored below (the collision keeps the
         // mass), for the next launch
-        if (D.rhow != nullptr && D.st_cur >= 0)
-            D.rhow[c] = make_int2(__float_as_int(1.0f + (float)drho_d), D.st_cur);
+        if (D.rhow != nullptr && D.st_cur >= 0) D.rhow[c] = rhow_word(1.0f + (float)drho_d, D.st_cur);
         if (!collide_store<ST>(Ph, fi, M, B, S, (unsigned)c)) atomicOr(D.err, ERR_NAN);
     }
 
@@ -661,12 +660,15 @@ __device__ __forceinline__ void pre_flags(const uint8_t *flags, const StageIdx &
     }
 }
 
-// particle ids of the particle nodes among the rows whose types R holds
+// particle ids of the particle nodes among the rows whose types R holds; -1 at every
+// other cell, and a particle node without a valid id reads as INT_MAX (an id that no
+// particle has, so its links report the inconsistency)
+__device__ __forceinline__ int ring_id(int p) { return p >= 0 ? p : 0x7fffffff; }
 __device__ __forceinline__ void pre_pids(const int *pid, const StageIdx &I, RowPre &R, int zo) {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-        R.p[k] = (R.f[k] & 0xff) == SOL ? pid[I.xm + I.yo[k] + zo] : -1;
-        R.pe[k] = ((R.f[k] >> 8) & 0xff) == SOL ? pid[I.xe + I.yo[k] + zo] : -1;
+        R.p[k] = (R.f[k] & 0xff) == SOL ? ring_id(pid[I.xm + I.yo[k] + zo]) : -1;
+        R.pe[k] = ((R.f[k] >> 8) & 0xff) == SOL ? ring_id(pid[I.xe + I.yo[k] + zo]) : -1;
     }
 }
 
@@ -852,21 +854,21 @@ __device__ __forceinline__ void march_cell(const Geom &G, const Phys &Ph, const 
     }
     const bool okP = (unsigned)P < (unsigned)D.np;
     // rho_w of Eq. bbrule: the density of this cell at t, as the launch before stored it
-    int2 e = make_int2(0, -1);
+    unsigned e = RHOW_NONE;
     if (sm && D.rhow != nullptr && D.st_prev >= 0) e = D.rhow[c];
     PMir pm{};
     if (sm && okP) pm = pmir_load(D.pmir, P);
-    // pulls (every lane loads; a lane without a cell reads a neighbour's word and drops it)
+    // pulls
     float fi[Q];
-#define FSL_PULL(QQ)                                                                   \
-    {                                                                                  \
-        const float v = SS::ld(A + QQ * S + (unsigned)(c + src_off<QQ>(so)), inv);    \
-        fi[QQ] = act ? v : 0.f;                                                        \
-    }
-    FSL_PULL(0) FSL_PULL(1) FSL_PULL(2) FSL_PULL(3) FSL_PULL(4) FSL_PULL(5) FSL_PULL(6)
-    FSL_PULL(7) FSL_PULL(8) FSL_PULL(9) FSL_PULL(10) FSL_PULL(11) FSL_PULL(12) FSL_PULL(13)
-    FSL_PULL(14) FSL_PULL(15) FSL_PULL(16) FSL_PULL(17) FSL_PULL(18)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) fi[q] = 0.f;
+    if (act) {  // lanes without a liquid cell load nothing
+#define FSL_PULL(QQ) fi[QQ] = SS::ld(A + QQ * S + (unsigned)(c + src_off<QQ>(so)), inv);
+        FSL_PULL(0) FSL_PULL(1) FSL_PULL(2) FSL_PULL(3) FSL_PULL(4) FSL_PULL(5) FSL_PULL(6)
+        FSL_PULL(7) FSL_PULL(8) FSL_PULL(9) FSL_PULL(10) FSL_PULL(11) FSL_PULL(12) FSL_PULL(13)
+        FSL_PULL(14) FSL_PULL(15) FSL_PULL(16) FSL_PULL(17) FSL_PULL(18)
 #undef FSL_PULL
+    }
     // particle ids of plane z+2 for the ring (its cell types were loaded before)
     pre_pids(D.pid, SI, R, zo2);
     // bounce-back links take the cell's own opposite population instead
@@ -876,8 +878,7 @@ __device__ __forceinline__ void march_cell(const Geom &G, const Phys &Ph, const 
             if ((bb >> q) & 1u) fi[q] = SS::ld(A + opp(q) * S + (unsigned)c, inv);
     }
     if (sm) {
-        const float rho_t = (D.st_prev >= 0 && e.y == D.st_prev) ? __int_as_float(e.x)
-                                                                 : own_density<ST>(Av, S, c, inv);
+        const float rho_t = rhow_valid(e, D.st_prev) ? __uint_as_float(e) : own_density<ST>(Av, S, c, inv);
         const int t = threadIdx.x;
         // the links mk of particle Pk (mirror m): moving-wall rule and momentum exchange.
         // With rho u = rho_w u_w the link adds a_q = 6 w_q c_q . rho u to the bounced
@@ -962,11 +963,9 @@ __device__ __forceinline__ void march_cell(const Geom &G, const Phys &Ph, const 
     }
     const Moments M = cell_moments(fi);
     if (D.rhow != nullptr && D.st_cur >= 0 && store) {
-        // (density, launch stamp) as one 8-byte word: the stamp of the launch for a
-        // liquid cell, none for the row's other cells
-        const unsigned long long w = (unsigned long long)(unsigned)__float_as_int(1.0f + (float)M.drho) |
-                                     ((unsigned long long)(unsigned)(act ? D.st_cur : -1) << 32);
-        __builtin_nontemporal_store(w, (unsigned long long *)(D.rhow + c));
+        // the density for a liquid cell, none for the row's other cells
+        const unsigned w = act ? rhow_word(1.0f + (float)M.drho, D.st_cur) : RHOW_NONE;
+        __builtin_nontemporal_store(w, D.rhow + c);
     }
     if (!collide_store<ST, true>(Ph, fi, M, B, S, (unsigned)c, store) && act) atomicOr(D.err, ERR_NAN);
 }
@@ -1138,7 +1137,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MW ? 1 : 5)
     }
 }
 
-// (density, stamp) of every liquid and interface cell from its populations in A, for
+// the density word of every liquid and interface cell from its populations in A, for
 // the first launch after the populations were set from outside
 template <int ST>
 __global__ void k_rhow_fill(Geom G, Phys Ph, Dev D, int stamp) {
@@ -1147,12 +1146,12 @@ __global__ void k_rhow_fill(Geom G, Phys Ph, Dev D, int stamp) {
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < G.N;
          c += (long long)gridDim.x * blockDim.x) {
         const uint8_t f = D.flags[c];
-        int2 w = make_int2(0, -1);
+        unsigned w = RHOW_NONE;
         if (f == LIQ || f == IFC) {
             float fa[Q];
 #pragma unroll
             for (int q = 0; q < Q; ++q) fa[q] = SS::ld(A + q * G.S + c, Ph.inv);
-            w = make_int2(__float_as_int(1.0f + (float)cell_moments(fa).drho), stamp);
+            w = rhow_word(1.0f + (float)cell_moments(fa).drho, stamp);
         }
         D.rhow[c] = w;
     }

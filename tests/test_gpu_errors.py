@@ -4,7 +4,10 @@ error codes.  Every kernel still runs to its end: the errors are latched on the
 device, never trapped.
   - a NaN population in a liquid cell: FSL_E_NUMERIC;
   - a liquid cell next to a gas cell (the interface layer broken): FSL_E_INVARIANT;
-  - conversion lists of capacity 1 with many cells filling at once: FSL_E_CAPACITY.
+  - conversion lists of capacity 1 with many cells filling at once: FSL_E_CAPACITY;
+  - a sphere whose centre comes closer than R + 1 to a periodic face: FSL_E_INVARIANT.
+The argument checks of the particle setter and of the differentiation window (no
+moving faces) are checked here too: they need a context on the device.
 """
 import numpy as np
 import pytest
@@ -67,4 +70,63 @@ def test_list_overflow_is_reported():
     with pytest.raises(fsl.FslError, match="overflowed"):
         s.sync()
     o.close()
+    s.close()
+
+
+def _one_sphere(x, periodic=(1, 1, 1), n=(24, 24, 24), u=(0.0, 0.0, 0.0), g=(0.0, 0.0, 0.0)):
+    p = W.Particles(x=np.array([x], dtype=np.float64), u=np.array([u], dtype=np.float64),
+                    omega=np.zeros((1, 3)), R=np.array([3.0]), rho_p=np.array([1.5]))
+    return W.Workload(name="one", n=n, trt=True, tau=0.6, g=g, zs=-1.0, steps=0, periodic=periodic,
+                      particles=p)
+
+
+def test_unsupported_sphere_positions_are_refused():
+    """The particle setter refuses what the coverage and pair search cannot handle
+    (they do not wrap): centres closer than R + 1 to a periodic face, outside a walled
+    box, or not finite; the limits themselves are accepted, as by the oracle."""
+    s = fsl.Sim(_one_sphere((12.0, 12.0, 12.0)))
+    for x in [(3.5, 12.0, 12.0), (12.0, 19.5, 12.0), (np.nan, 12.0, 12.0)]:
+        with pytest.raises(fsl.FslError, match="particles_set"):
+            s.particles_set(_one_sphere(x).particles)
+    s.particles_set(_one_sphere((4.0, 19.0, 12.0)).particles)
+    s.close()
+    s = fsl.Sim(_one_sphere((12.0, 12.0, 12.0), periodic=(0, 0, 0)))
+    for x in [(12.0, 12.0, 24.2), (-0.7, 12.0, 12.0), (12.0, np.inf, 12.0)]:
+        with pytest.raises(fsl.FslError, match="particles_set"):
+            s.particles_set(_one_sphere(x, periodic=(0, 0, 0)).particles)
+    s.particles_set(_one_sphere((-0.5, 12.0, 23.5), periodic=(0, 0, 0)).particles)
+    s.close()
+
+
+def test_sphere_reaching_a_periodic_face_is_reported():
+    """A sphere driven toward a periodic face: the step that brings its centre closer
+    than R + 1 is reported by the next synchronising call (FSL_E_INVARIANT), after the
+    kernels ran to their end; the oracle sets its particle flag in the same step."""
+    w = _one_sphere((5.0, 12.0, 12.0), u=(-0.2, 0.0, 0.0), g=(-1e-3, 0.0, 0.0))
+    o = O.Oracle(w, n_threads=4)
+    s = fsl.Sim(w)
+    t_o = next(t for t in range(1, 31) if o.step(1))
+    with pytest.raises(fsl.FslError, match="sphere"):
+        for _ in range(30):
+            s.step(1)
+            s.sync()
+    s.close()
+    o.close()
+    assert t_o <= 30
+
+
+def test_window_refuses_moving_faces():
+    """The adjoint transposes resting bounce-back at the box faces only, so a window
+    on a box whose faces move is refused (the oracle's window would include the
+    moving-wall term and the two would disagree)."""
+    w = W.Workload(name="walled", n=(20, 14, 12), trt=True, tau=0.6, g=(0.0, 0.0, -1e-5), zs=-1.0, steps=0,
+                   periodic=(1, 0, 0), integrate=False)
+    wall = [[[0.0] * 3, [0.0] * 3] for _ in range(3)]
+    wall[1][1][0] = 0.01  # the face y = n - 1/2 moves along x
+    s = fsl.Sim(w, window=(4, 2), wall_u=wall)
+    with pytest.raises(fsl.FslError, match="moving box faces"):
+        s.window_forward(4, 2)
+    s.close()
+    s = fsl.Sim(w, window=(4, 2))
+    s.window_forward(4, 2)
     s.close()
