@@ -5,8 +5,8 @@
  *
  * The library advances one simulation state on one GPU.  It never allocates
  * device memory: the caller passes one device workspace of
- * fsl_workspace_bytes(cfg) bytes and a HIP stream; every kernel runs on that
- * stream.  The library allocates only its small host context (freed by
+ * fsl_workspace_bytes(cfg) bytes (with fsl_init_static, the state part only) and
+ * a HIP stream; every kernel runs on that stream.  The library allocates only its small host context (freed by
  * fsl_destroy, which never frees the workspace).  Host arrays passed to the
  * get/set calls are owned by the caller, row-major, FP64 unless stated.
  *
@@ -123,6 +123,34 @@ size_t fsl_workspace_bytes(const fsl_config *cfg);
  * The workspace must outlive the context.  FSL_E_ARG on a bad configuration. */
 int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, fsl_ctx **out);
 
+/* Bytes of device working memory that the library holds on each device for the
+ * contexts of fsl_init_static (a file-scope device array, kept until the process
+ * ends). */
+#define FSL_STATIC_SCRATCH_BYTES (128u << 20)
+
+/* fsl_init for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc) once the state
+ * exists.  The workspace of fsl_init has two parts: the state, which lives from
+ * one call to the next (fields, particle and bubble tables, counters, error word,
+ * stored densities, differentiation window), and the working memory that each
+ * call writes before it reads it (conversion and event lists, particle pairs and
+ * candidate grid, splitting labels, field staging, tile lists).  Here the caller
+ * passes the state only; the working memory is the library's array of
+ * FSL_STATIC_SCRATCH_BYTES on the current device, which must be the device of
+ * hip_stream.
+ *   d_state NULL: *bytes receives the state bytes cfg needs; nothing else happens.
+ *   otherwise:    d_state (device, 256-byte aligned, *bytes >= that size, owned by
+ *                 the caller and outliving the context) receives the initial state
+ *                 and *out the context, used like one from fsl_init.
+ * FSL_E_ARG if cfg is invalid or needs more working memory than the array holds
+ * (roughly 15 bytes per cell with particles, 8 without), with the text from
+ * fsl_error_string(NULL); FSL_E_HIP if the array's address cannot be found.  Every
+ * context made here on one device shares the array: calls on such contexts that
+ * overlap in time (other streams, other threads) race and give wrong results;
+ * calls that follow one another on the device are independent.  No call allocates
+ * device memory. */
+int fsl_init_static(const fsl_config *cfg, void *d_state, size_t *bytes, void *hip_stream, fsl_ctx **out);
+
 /* Enqueue n lattice steps on the stream (asynchronous).  One step: streaming with
  * wall / moving-particle / free-surface reconstruction, moments, interface mass
  * exchange, collision (Eqs. LBE1, LBE2, fsk, bbrule, massExchange, massExchangeb),
@@ -187,7 +215,8 @@ int fsl_mass_get(fsl_ctx *ctx, double *total, double *ledger);
 /* Wait for the stream and report a latched device error (FSL_E_*). */
 int fsl_sync(fsl_ctx *ctx);
 
-/* Text of the last error of ctx (never NULL). */
+/* Text of the last error of ctx (never NULL); with ctx NULL, of the last call on
+ * this thread that failed before it had a context (fsl_init_static). */
 const char *fsl_error_string(const fsl_ctx *ctx);
 
 /* Free the host context (not the workspace). */

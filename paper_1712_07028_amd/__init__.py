@@ -23,7 +23,7 @@ EXPORTS = [
     "fsl_workspace_bytes", "fsl_init", "fsl_step", "fsl_particles_set", "fsl_particles_get",
     "fsl_bubbles_get", "fsl_bubbles_set", "fsl_fields_get", "fsl_fields_set", "fsl_mass_get",
     "fsl_sync", "fsl_error_string", "fsl_destroy", "fsl_profile_enable", "fsl_profile_get",
-    "fsl_window_forward", "fsl_window_backward", "fsl_params_set",
+    "fsl_window_forward", "fsl_window_backward", "fsl_params_set", "fsl_init_static",
 ]
 
 
@@ -72,6 +72,8 @@ def load_library(path=LIB_PATH):
     L.fsl_workspace_bytes.restype = ctypes.c_size_t
     L.fsl_workspace_bytes.argtypes = [ctypes.POINTER(FslConfig)]
     L.fsl_init.argtypes = [ctypes.POINTER(FslConfig), P, ctypes.c_size_t, P, ctypes.POINTER(P)]
+    L.fsl_init_static.argtypes = [ctypes.POINTER(FslConfig), P, ctypes.POINTER(ctypes.c_size_t), P,
+                                  ctypes.POINTER(P)]
     L.fsl_step.argtypes = [P, ctypes.c_int]
     L.fsl_particles_set.argtypes = [P, ctypes.c_int, dp, dp, dp, dp, dp]
     L.fsl_particles_get.argtypes = [P, ctypes.c_int, dp, dp, dp, dp, dp]
@@ -138,10 +140,12 @@ class Sim:
     """One simulation state on the current HIP device.
 
     The workspace is a torch uint8 tensor; the library runs on torch's current
-    stream.  ``w`` is a workloads.Workload."""
+    stream.  ``w`` is a workloads.Workload.  With ``static=True`` the context comes
+    from fsl_init_static: the tensor holds the state only and the working memory is
+    the library's own array on the device."""
 
     def __init__(self, w, device="cuda", max_particles=None, list_capacity=0, window=(0, 0),
-                 set_particles=True, wall_u=None, max_bubbles=0):
+                 set_particles=True, wall_u=None, max_bubbles=0, static=False):
         import torch
 
         self.L = load_library()
@@ -150,17 +154,34 @@ class Sim:
         self.w = w
         self.N = w.cells
         self.cfg = make_config(w, max_particles, list_capacity, window, wall_u, max_bubbles)
-        nbytes = self.L.fsl_workspace_bytes(ctypes.byref(self.cfg))
-        if nbytes == 0:
-            raise FslError("invalid configuration")
-        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
-        self.stream = torch.cuda.current_stream(self.workspace.device)
         self.ctx = ctypes.c_void_p()
-        rc = self.L.fsl_init(ctypes.byref(self.cfg), ctypes.c_void_p(self.workspace.data_ptr()),
-                             ctypes.c_size_t(nbytes), ctypes.c_void_p(self.stream.cuda_stream),
-                             ctypes.byref(self.ctx))
-        if rc:
-            raise FslError(f"fsl_init failed ({rc})")
+        if static:
+            dev = torch.device(device)
+            if dev.index is None:
+                dev = torch.device("cuda", torch.cuda.current_device())
+            torch.cuda.set_device(dev)  # the library's array on the stream's device
+            nb = ctypes.c_size_t(0)
+            rc = self.L.fsl_init_static(ctypes.byref(self.cfg), None, ctypes.byref(nb), None, None)
+            if rc:
+                raise FslError(f"fsl_init_static failed ({rc}): {self.L.fsl_error_string(None).decode()}")
+            self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
+            self.stream = torch.cuda.current_stream(self.workspace.device)
+            rc = self.L.fsl_init_static(ctypes.byref(self.cfg), ctypes.c_void_p(self.workspace.data_ptr()),
+                                        ctypes.byref(nb), ctypes.c_void_p(self.stream.cuda_stream),
+                                        ctypes.byref(self.ctx))
+            if rc:
+                raise FslError(f"fsl_init_static failed ({rc}): {self.L.fsl_error_string(None).decode()}")
+        else:
+            nbytes = self.L.fsl_workspace_bytes(ctypes.byref(self.cfg))
+            if nbytes == 0:
+                raise FslError("invalid configuration")
+            self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+            self.stream = torch.cuda.current_stream(self.workspace.device)
+            rc = self.L.fsl_init(ctypes.byref(self.cfg), ctypes.c_void_p(self.workspace.data_ptr()),
+                                 ctypes.c_size_t(nbytes), ctypes.c_void_p(self.stream.cuda_stream),
+                                 ctypes.byref(self.ctx))
+            if rc:
+                raise FslError(f"fsl_init failed ({rc})")
         self.n_particles = 0
         if set_particles and w.particles is not None and w.particles.n:
             self.particles_set(w.particles)

@@ -16,6 +16,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "../../include/fsl.h"
@@ -35,16 +36,25 @@ constexpr int NPROF = 8;
 
 size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
+// The workspace has two parts.  The state (offsets from the workspace) holds what
+// lives from one call to the next: fields, tables, counters, the error word, stored
+// densities, curvature tile flags and the differentiation window.  The working
+// memory (offsets from its own base) holds what one call writes before it reads it:
+// conversion and event lists, particle pairs and candidate grid, splitting labels,
+// field staging and the general-path tile list; their lengths are counters in the
+// state.  fsl_init puts the working memory right after the state.
 struct Layout {
     size_t fA, fB, flags, cv, phiA, phiB, m, bub, pid, claim;
-    size_t lF, lE0, lE, lNG, lNL, lCov, lUnc, uncRho, uncDec, merges, pairs;
-    size_t counters, ctl, ptab, pacc, pFT, pFTp, pFl, pmir, gStart, gCount, gIdx, gBsum;
-    size_t btab, bacc, broot, balive, rhog, kappa, ktf, klist, kcount, wallu, stage;
-    size_t slab, scomp, scid, spar, svol;  // bubble splitting
+    size_t counters, ctl, ptab, pacc, pFT, pFTp, pFl, pmir;
+    size_t btab, bacc, broot, balive, rhog, kappa, ktf, klist, kcount, wallu;
     size_t rhow;  // densities of the liquid and interface cells for the next launch
+    size_t win;   // differentiation window storage
+    // working memory
+    size_t lF, lE0, lE, lNG, lNL, lCov, lUnc, uncRho, uncDec, merges, pairs;
+    size_t gStart, gCount, gIdx, gBsum, stage;
+    size_t slab, scomp, scid, spar, svol;  // bubble splitting
     size_t glist;  // tiles of the general path of the stream-collide step
-    size_t win;  // differentiation window storage
-    size_t total;
+    size_t state, work, total;
     long long S;
     int cap, capEv, pcap, maxP, maxB, ncellMax, nTiles;
     int ktx, kty, nKT;  // curvature tiles
@@ -74,7 +84,8 @@ bool valid(const fsl_config *c) {
     return true;
 }
 
-Layout layout_of(const fsl_config *c) {
+// stage_cap: the most bytes of field staging (chunks of a field pass through it)
+Layout layout_of(const fsl_config *c, size_t stage_cap = (size_t)64 << 20) {
     Layout L{};
     long long N = (long long)c->n[0] * c->n[1] * c->n[2];
     L.S = (N + 255) / 256 * 256;
@@ -86,7 +97,7 @@ Layout layout_of(const fsl_config *c) {
     L.pcap = 16 * L.maxP;
     L.maxB = c->max_bubbles > 0 ? c->max_bubbles : 64;
     L.ncellMax = ((c->n[0] + 2) / 3) * ((c->n[1] + 2) / 3) * ((c->n[2] + 2) / 3) + 1;
-    L.stageBytes = std::min<size_t>((size_t)64 << 20, std::max<size_t>((size_t)L.S * 8, 1 << 20));
+    L.stageBytes = std::min<size_t>(stage_cap, std::max<size_t>((size_t)L.S * 8, 1 << 20));
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o += up(bytes); return r; };
     size_t lat = (size_t)Q * L.S * esize(c->storage);
@@ -100,17 +111,6 @@ Layout layout_of(const fsl_config *c) {
     L.bub = take(L.S * 2);
     L.pid = take(L.S * 4);
     L.claim = take(L.S * 4);
-    L.lF = take((size_t)L.cap * 4);
-    L.lE0 = take((size_t)L.cap * 4);
-    L.lE = take((size_t)L.cap * 4);
-    L.lNG = take((size_t)L.cap * 4);
-    L.lNL = take((size_t)L.cap * 4);
-    L.lCov = take((size_t)L.capEv * 8);
-    L.lUnc = take((size_t)L.capEv * 8);
-    L.uncRho = take((size_t)L.capEv * 8);
-    L.uncDec = take((size_t)L.capEv * 4);
-    L.merges = take((size_t)L.cap * 8);
-    L.pairs = take((size_t)L.pcap * 8);
     L.counters = take(64 * 4);
     L.ctl = take(64 * 8);  // [0] err word, [8] ledger, [16..] mass sums
     L.ptab = take((size_t)L.maxP * P_STRIDE * 8);
@@ -120,10 +120,6 @@ Layout layout_of(const fsl_config *c) {
     L.pFl = take((size_t)L.maxP * 3 * 8);
     L.pmir = take((size_t)L.maxP * 64);
     L.rhow = take(c->max_particles > 0 ? (size_t)L.S * 4 : 0);
-    L.gStart = take((size_t)(L.ncellMax + 1) * 4);
-    L.gCount = take((size_t)L.ncellMax * 4);
-    L.gIdx = take((size_t)L.maxP * 4);
-    L.gBsum = take(1025 * 4);
     L.btab = take((size_t)L.maxB * B_STRIDE * 8);
     L.bacc = take((size_t)L.maxB * BACC_STRIDE * 8);
     L.broot = take((size_t)L.maxB * 4);
@@ -137,18 +133,36 @@ Layout layout_of(const fsl_config *c) {
     L.klist = take((size_t)L.nKT * 4);
     L.kcount = take(c->sigma != 0.0 ? 4 : 0);
     L.wallu = take(18 * 4);
+    L.nTiles = ((c->n[0] + TX - 1) / TX) * ((c->n[1] + TY - 1) / TY) * c->n[2];
+    L.winBytes = adjoint_window_bytes(c->window_steps, c->window_every, (size_t)L.S, c->max_particles,
+                                      L.nTiles);
+    L.win = take(L.winBytes);
+    L.state = o;
+    o = 0;  // working memory
+    L.lF = take((size_t)L.cap * 4);
+    L.lE0 = take((size_t)L.cap * 4);
+    L.lE = take((size_t)L.cap * 4);
+    L.lNG = take((size_t)L.cap * 4);
+    L.lNL = take((size_t)L.cap * 4);
+    L.lCov = take((size_t)L.capEv * 8);
+    L.lUnc = take((size_t)L.capEv * 8);
+    L.uncRho = take((size_t)L.capEv * 8);
+    L.uncDec = take((size_t)L.capEv * 4);
+    L.merges = take((size_t)L.cap * 8);
+    L.pairs = take((size_t)L.pcap * 8);
+    L.gStart = take((size_t)(L.ncellMax + 1) * 4);
+    L.gCount = take((size_t)L.ncellMax * 4);
+    L.gIdx = take((size_t)L.maxP * 4);
+    L.gBsum = take(1025 * 4);
     L.slab = take(L.S * 4);
     L.scomp = take(SPLIT_MAXC * 4);
     L.scid = take(SPLIT_MAXC * 4);
     L.spar = take(SPLIT_MAXC * 4);
     L.svol = take(SPLIT_MAXC * 8);
     L.stage = take(L.stageBytes);
-    L.nTiles = ((c->n[0] + TX - 1) / TX) * ((c->n[1] + TY - 1) / TY) * c->n[2];
-    L.winBytes = adjoint_window_bytes(c->window_steps, c->window_every, (size_t)L.S, c->max_particles,
-                                      L.nTiles);
     L.glist = take((size_t)L.nTiles * 4);
-    L.win = take(L.winBytes);
-    L.total = o;
+    L.work = o;
+    L.total = L.state + L.work;
     return L;
 }
 
@@ -162,7 +176,8 @@ struct fsl_ctx {
     Dev D;
     SplitBuf SB;
     hipStream_t st;
-    char *ws;
+    char *ws;  // state
+    char *xs;  // working memory
     char err[256];
     double Rmax;
     PGrid PG;
@@ -272,7 +287,7 @@ void set_phys(fsl_ctx *c) {
 // a moving or slipping face)
 template <int ST, bool MW>
 void launch_stream_collide_mw(fsl_ctx *c, const Dev &Dv) {
-    int *glist = (int *)(c->ws + c->L.glist), *ngen = Dv.counters + C_NGEN;
+    int *glist = (int *)(c->xs + c->L.glist), *ngen = Dv.counters + C_NGEN;
     const int nChunks = (c->G.nz + NZC - 1) / NZC;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->st, ngen, 1LL, 0);
     hipLaunchKernelGGL((k_stream_collide<ST, MW>), dim3(c->tilesX * c->tilesY * nChunks), dim3(256), 0, c->st,
@@ -382,7 +397,7 @@ int enqueue_pair_forces(fsl_ctx *c) {
     {
         const int chunk = std::max(256, (c->ncell + 1023) / 1024 + 255) / 256 * 256;
         const int nb = (c->ncell + chunk - 1) / chunk;
-        int *bsum = (int *)(c->ws + c->L.gBsum);
+        int *bsum = (int *)(c->xs + c->L.gBsum);
         hipLaunchKernelGGL(k_gscan_sum, dim3(nb), dim3(256), 0, c->st, D, c->ncell, chunk, bsum);
         hipLaunchKernelGGL(k_gscan_top, dim3(1), dim3(1024), 0, c->st, D, c->ncell, nb, bsum);
         hipLaunchKernelGGL(k_gscan_apply, dim3(nb), dim3(256), 0, c->st, D, c->ncell, chunk, (const int *)bsum);
@@ -654,6 +669,47 @@ int window_backward(fsl_ctx *c, double dJ, double *dJ_dtau, double *dJ_dg) {
 }  // namespace
 
 // ==================================================================================
+// Working memory of the contexts made by fsl_init_static: one copy on each device the
+// library runs on, held until the process ends and shared by every such context on
+// that device.  Host code never names it: it uses the device address looked up once
+// per device.
+static __device__ __align__(256) unsigned char scratch[FSL_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr size_t STATIC_STAGE_BYTES = (size_t)8 << 20;  // field staging within the array
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+char *scratch_ptr[MAX_DEVICES];             // the array's device address on each device
+thread_local char noctx_err[256] = "null context";  // last error of a call without context
+
+int fail_noctx(int code, const char *msg) {
+    snprintf(noctx_err, sizeof noctx_err, "%s", msg);
+    return code;
+}
+
+// the array's address on the current device, looked up on first use
+char *static_work(int *code) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+        *code = fail_noctx(FSL_E_HIP, "init_static: no current device");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            char b[200];
+            snprintf(b, sizeof b, "init_static: hipGetSymbolAddress: %s", hipGetErrorString(e));
+            *code = fail_noctx(FSL_E_HIP, b);
+            return nullptr;
+        }
+        scratch_ptr[dev] = (char *)p;
+    }
+    return scratch_ptr[dev];
+}
+}  // namespace
+
 extern "C" {
 
 size_t fsl_workspace_bytes(const fsl_config *cfg) {
@@ -661,19 +717,17 @@ size_t fsl_workspace_bytes(const fsl_config *cfg) {
     return layout_of(cfg).total;
 }
 
-int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, fsl_ctx **out) {
-    if (!out) return FSL_E_ARG;
-    *out = nullptr;
-    if (!valid(cfg) || !d_ws || ((uintptr_t)d_ws % ALIGN)) return FSL_E_ARG;
-    Layout L = layout_of(cfg);
-    if (bytes < L.total) return FSL_E_ARG;
+// a context on the state d_ws and the working memory d_work, both laid out by L
+static int init_ctx(const fsl_config *cfg, const Layout &L, char *d_ws, char *d_work, void *hip_stream,
+                    fsl_ctx **out) {
     fsl_ctx *c = new (std::nothrow) fsl_ctx();
     if (!c) return FSL_E_ARG;
     c->cfg = *cfg;
     if (c->cfg.n_sub <= 0) c->cfg.n_sub = 10;
     c->L = L;
     c->st = (hipStream_t)hip_stream;
-    c->ws = (char *)d_ws;
+    c->ws = d_ws;
+    c->xs = d_work;
     c->err[0] = 0;
     Geom &G = c->G;
     G.nx = cfg->n[0];
@@ -684,7 +738,7 @@ int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, 
     G.S = L.S;
     set_phys(c);
     Dev &D = c->D;
-    char *w = c->ws;
+    char *w = c->ws, *x = c->xs;
     D.fA = w + L.fA;
     D.fB = w + L.fB;
     D.flags = (uint8_t *)(w + L.flags);
@@ -695,17 +749,17 @@ int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, 
     D.bub = (uint16_t *)(w + L.bub);
     D.pid = (int *)(w + L.pid);
     D.claim = (int *)(w + L.claim);
-    D.lF = (int *)(w + L.lF);
-    D.lE0 = (int *)(w + L.lE0);
-    D.lE = (int *)(w + L.lE);
-    D.lNG = (int *)(w + L.lNG);
-    D.lNL = (int *)(w + L.lNL);
-    D.lCov = (int *)(w + L.lCov);
-    D.lUnc = (int *)(w + L.lUnc);
-    D.uncRho = (double *)(w + L.uncRho);
-    D.uncDec = (int *)(w + L.uncDec);
-    D.merges = (int2 *)(w + L.merges);
-    D.pairs = (int2 *)(w + L.pairs);
+    D.lF = (int *)(x + L.lF);
+    D.lE0 = (int *)(x + L.lE0);
+    D.lE = (int *)(x + L.lE);
+    D.lNG = (int *)(x + L.lNG);
+    D.lNL = (int *)(x + L.lNL);
+    D.lCov = (int *)(x + L.lCov);
+    D.lUnc = (int *)(x + L.lUnc);
+    D.uncRho = (double *)(x + L.uncRho);
+    D.uncDec = (int *)(x + L.uncDec);
+    D.merges = (int2 *)(x + L.merges);
+    D.pairs = (int2 *)(x + L.pairs);
     D.counters = (int *)(w + L.counters);
     D.err = (unsigned *)(w + L.ctl);
     D.ledger = (double *)(w + L.ctl + 8);
@@ -715,9 +769,9 @@ int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, 
     D.pFTp = (double *)(w + L.pFTp);
     D.pFl = (double *)(w + L.pFl);
     D.pmir = (float4 *)(w + L.pmir);
-    D.gridStart = (int *)(w + L.gStart);
-    D.gridCount = (int *)(w + L.gCount);
-    D.gridIdx = (int *)(w + L.gIdx);
+    D.gridStart = (int *)(x + L.gStart);
+    D.gridCount = (int *)(x + L.gCount);
+    D.gridIdx = (int *)(x + L.gIdx);
     D.btab = (double *)(w + L.btab);
     D.bacc = (double *)(w + L.bacc);
     D.broot = (int *)(w + L.broot);
@@ -751,8 +805,8 @@ int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, 
     D.maxB = L.maxB;
     D.np = 0;
     D.nb = L.maxB;  // kernels walk the whole table; unused ids hold no cells
-    c->SB = SplitBuf{(int *)(w + L.slab), (int *)(w + L.scomp), (int *)(w + L.scid), (int *)(w + L.spar),
-                     (double *)(w + L.svol)};
+    c->SB = SplitBuf{(int *)(x + L.slab), (int *)(x + L.scomp), (int *)(x + L.scid), (int *)(x + L.spar),
+                     (double *)(x + L.svol)};
     c->Rmax = 0;
     c->ncell = 1;
     c->PG = PGrid{{1, 1, 1}, {(double)G.nx, (double)G.ny, (double)G.nz}, 2.0 / 3.0 + 1.0};
@@ -825,6 +879,39 @@ int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, 
     }
     *out = c;
     return FSL_OK;
+}
+
+int fsl_init(const fsl_config *cfg, void *d_ws, size_t bytes, void *hip_stream, fsl_ctx **out) {
+    if (!out) return FSL_E_ARG;
+    *out = nullptr;
+    if (!valid(cfg) || !d_ws || ((uintptr_t)d_ws % ALIGN)) return FSL_E_ARG;
+    Layout L = layout_of(cfg);
+    if (bytes < L.total) return FSL_E_ARG;
+    return init_ctx(cfg, L, (char *)d_ws, (char *)d_ws + L.state, hip_stream, out);
+}
+
+int fsl_init_static(const fsl_config *cfg, void *d_state, size_t *bytes, void *hip_stream, fsl_ctx **out) {
+    if (out) *out = nullptr;
+    if (!bytes) return fail_noctx(FSL_E_ARG, "init_static: bytes is NULL");
+    if (!valid(cfg)) return fail_noctx(FSL_E_ARG, "init_static: invalid configuration");
+    const Layout L = layout_of(cfg, STATIC_STAGE_BYTES);
+    if (L.work > (size_t)FSL_STATIC_SCRATCH_BYTES) {
+        char b[200];
+        snprintf(b, sizeof b, "init_static: the configuration needs %zu bytes of working memory, above the %zu held",
+                 L.work, (size_t)FSL_STATIC_SCRATCH_BYTES);
+        return fail_noctx(FSL_E_ARG, b);
+    }
+    if (!d_state) {
+        *bytes = L.state;
+        return FSL_OK;
+    }
+    if (!out || ((uintptr_t)d_state % ALIGN))
+        return fail_noctx(FSL_E_ARG, "init_static: out is NULL or the state is not 256-byte aligned");
+    if (*bytes < L.state) return fail_noctx(FSL_E_ARG, "init_static: state buffer too small");
+    int rc = FSL_OK;
+    char *work = static_work(&rc);
+    if (!work) return rc;
+    return init_ctx(cfg, L, (char *)d_state, work, hip_stream, out);
 }
 
 int fsl_step(fsl_ctx *c, int n) {
@@ -963,6 +1050,8 @@ int fsl_bubbles_set(fsl_ctx *c, int n, const double *M, const int *root, const i
     HIPCHK(c, hipMemcpyAsync(c->D.balive, al.data(), nt * 4, hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipMemcpyAsync(c->D.counters + C_BUSED, &n, 4, hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
+    // the lists a step leaves are not read again: the splitting pass below clears no marks
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, c->st, c->D);
     int rc = by_storage(c, [&](auto st) {
         int r = enqueue_bubbles<decltype(st)::value>(c, c->D.phi_cur, 0);
         return r ? r : enqueue_split<decltype(st)::value>(c, c->D.phi_cur, 1);
@@ -975,7 +1064,7 @@ int fsl_fields_get(fsl_ctx *c, int field, void *host) {
     if (!c || !host) return FSL_E_ARG;
     const long long N = c->G.N;
     Dev &D = c->D;
-    double *stage = (double *)(c->ws + c->L.stage);
+    double *stage = (double *)(c->xs + c->L.stage);
     const long long chunk = (long long)(c->L.stageBytes / 8);
     switch (field) {
     case FSL_FIELD_FLAGS: HIPCHK(c, hipMemcpyAsync(host, D.flags, N, hipMemcpyDeviceToHost, c->st)); break;
@@ -984,7 +1073,7 @@ int fsl_fields_get(fsl_ctx *c, int field, void *host) {
     case FSL_FIELD_PID: HIPCHK(c, hipMemcpyAsync(host, D.pid, N * 4, hipMemcpyDeviceToHost, c->st)); break;
     case FSL_FIELD_KAPPA: {
         if (!D.kappa) return fail(c, FSL_E_ARG, "fields_get: no surface tension configured");
-        double *stage = (double *)(c->ws + c->L.stage);
+        double *stage = (double *)(c->xs + c->L.stage);
         const long long chunk = (long long)(c->L.stageBytes / 8);
         enqueue_curvature(c);  // of the current state: the one the next step uses
         LAUNCHCHK(c);
@@ -1036,7 +1125,7 @@ int fsl_fields_set(fsl_ctx *c, int field, const void *host) {
     c->adj.ready = 0;
     const long long N = c->G.N;
     Dev &D = c->D;
-    double *stage = (double *)(c->ws + c->L.stage);
+    double *stage = (double *)(c->xs + c->L.stage);
     const long long chunk = (long long)(c->L.stageBytes / 8);
     switch (field) {
     case FSL_FIELD_FLAGS: HIPCHK(c, hipMemcpyAsync(D.flags, host, N, hipMemcpyHostToDevice, c->st)); break;
@@ -1098,7 +1187,7 @@ int fsl_sync(fsl_ctx *c) {
 }
 
 const char *fsl_error_string(const fsl_ctx *c) {
-    if (!c) return "null context";
+    if (!c) return noctx_err;
     return c->err;
 }
 

@@ -74,3 +74,27 @@ def test_init_rejects_bad_arguments(lib):
     assert not ctx.value
     assert lib.fsl_step(None, 1) == fsl.FSL_E_ARG
     assert lib.fsl_error_string(None) == b"null context"
+
+
+def test_init_static_sizes_and_limit(lib):
+    """fsl_init_static: the size query returns the state part of the workspace, and a
+    configuration whose working memory exceeds the library's array is refused with
+    a text that says so (both before any device work)."""
+    import paper_1712_07028_amd as fsl
+    from paper_1712_07028_amd import workloads as W
+
+    c = fsl.make_config(W.bubble_column_small())
+    nb = ctypes.c_size_t(0)
+    assert lib.fsl_init_static(ctypes.byref(c), None, ctypes.byref(nb), None, None) == fsl.FSL_OK
+    assert 0 < nb.value < lib.fsl_workspace_bytes(ctypes.byref(c))
+    big = fsl.make_config(W.Workload(name="big", n=(1024, 1024, 256), trt=True, tau=0.6, g=(0, 0, -1e-5),
+                                     zs=200.0, steps=0))
+    assert lib.fsl_workspace_bytes(ctypes.byref(big)) > 0
+    assert lib.fsl_init_static(ctypes.byref(big), None, ctypes.byref(nb), None, None) == fsl.FSL_E_ARG
+    assert b"working memory" in lib.fsl_error_string(None)
+    assert lib.fsl_init_static(ctypes.byref(c), None, None, None, None) == fsl.FSL_E_ARG
+    ctx = ctypes.c_void_p()
+    nb = ctypes.c_size_t(1 << 30)
+    assert lib.fsl_init_static(ctypes.byref(c), ctypes.c_void_p(0x1001), ctypes.byref(nb), None,
+                               ctypes.byref(ctx)) == fsl.FSL_E_ARG
+    assert not ctx.value
