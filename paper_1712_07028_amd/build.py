@@ -1,4 +1,5 @@
-"""Build the HIP library libfsl.so (gfx950) in the package directory."""
+"""Build the HIP library libfsl.so (gfx950) in the package directory, and
+libfsl_checks.so: host builds of two pure functions of its kernels, for tests."""
 from __future__ import annotations
 
 import os
@@ -9,6 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfsl.so")
 SOURCES = [os.path.join(CSRC, "fsl_api.hip")]
+CHECKS_LIB = os.path.join(HERE, "libfsl_checks.so")
+CHECKS_SOURCES = [os.path.join(CSRC, "fsl_checks.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -24,14 +27,19 @@ FLAGS = [
 ]
 
 
-def build(verbose=False):
-    """Compile every HIP source into libfsl.so; always recompiles."""
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *SOURCES]
+def _compile(lib, sources, verbose):
+    tmp = lib + ".tmp"
+    cmd = [HIPCC, *FLAGS, "-o", tmp, *sources]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True, cwd=CSRC)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose=False):
+    """Compile libfsl.so and libfsl_checks.so; always recompiles."""
+    _compile(LIB, SOURCES, verbose)
+    _compile(CHECKS_LIB, CHECKS_SOURCES, verbose)
     return LIB
 
 

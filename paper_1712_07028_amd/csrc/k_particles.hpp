@@ -5,6 +5,7 @@
 // sphere are obstacle nodes; covered / uncovered cells keep the mass ledger).
 #pragma once
 
+#include "cov_column.hpp"
 #include "k_free_surface.hpp"
 
 namespace fsl {
@@ -482,11 +483,9 @@ __global__ __launch_bounds__(256) void k_cov_scan(Geom G, Dev D) {
     // a sphere alone: only nodes whose inside test changed between the old and new
     // positions can change owner.  Walked as (x, y) columns: the in-plane part of
     // both squared distances is formed once per column, in the order of inside(), and
-    // a column outside both circles is skipped (adding dz^2 cannot bring it inside).
-    // Along a column each sphere holds one interval of nodes, and the nodes whose
-    // test changes lie between the two lower ends or between the two upper ends; the
-    // ends come from a square root, so one node of margin on each side covers its
-    // rounding, and every candidate still takes the exact test.
+    // a column outside both circles is skipped (adding dz^2 cannot bring it inside);
+    // cov_column_ranges gives the candidates of the others, and every candidate
+    // still takes the exact test.
     const double *xn = t + P_X, *xo = t + P_XOLD;
     const double R2 = __dmul_rn(t[P_R], t[P_R]);
     for (int s = threadIdx.x & 63; s < ex * ey; s += 64) {
@@ -495,27 +494,10 @@ __global__ __launch_bounds__(256) void k_cov_scan(Geom G, Dev D) {
         const double sn = __dadd_rn(__dmul_rn(a0, a0), __dmul_rn(a1, a1));
         const double so = __dadd_rn(__dmul_rn(b0, b0), __dmul_rn(b1, b1));
         if (sn > R2 && so > R2) continue;
-        int r1lo, r1hi, r2lo, r2hi;  // candidate ranges of k
-        if (sn <= R2 && so <= R2) {
-            const double hn = sqrt(R2 - sn), ho = sqrt(R2 - so);
-            const int ln = (int)ceil(xn[2] - hn), un = (int)floor(xn[2] + hn);
-            const int lo_ = (int)ceil(xo[2] - ho), uo = (int)floor(xo[2] + ho);
-            r1lo = min(ln, lo_) - 1;
-            r1hi = max(ln, lo_) + 1;
-            r2lo = max(min(un, uo) - 1, r1hi + 1);
-            r2hi = max(un, uo) + 1;
-        } else {
-            const double zc = sn <= R2 ? xn[2] : xo[2], h = sqrt(R2 - (sn <= R2 ? sn : so));
-            r1lo = (int)ceil(zc - h) - 1;
-            r1hi = (int)floor(zc + h) + 1;
-            r2lo = 1;
-            r2hi = 0;
-        }
-        r1lo = max(r1lo, lo[2]);
-        r1hi = min(r1hi, hi[2]);
-        r2lo = max(r2lo, lo[2]);
-        r2hi = min(r2hi, hi[2]);
-        const int n1 = max(r1hi - r1lo + 1, 0), n2 = max(r2hi - r2lo + 1, 0);
+        int r[4];  // candidate ranges of k
+        cov_column_ranges(sn, so, R2, xn[2], xo[2], lo[2], hi[2], r);
+        const int r1lo = r[0], r2lo = r[2];
+        const int n1 = max(r[1] - r1lo + 1, 0), n2 = max(r[3] - r2lo + 1, 0);
         for (int m = 0; m < n1 + n2; ++m) {
             const int k = m < n1 ? r1lo + m : r2lo + (m - n1);
             const double a2 = k - xn[2], b2 = k - xo[2];

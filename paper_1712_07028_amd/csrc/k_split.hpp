@@ -22,6 +22,7 @@
 #pragma once
 
 #include "k_particles.hpp"
+#include "split_block.hpp"
 
 namespace fsl {
 
@@ -37,22 +38,6 @@ struct SplitBuf {
 };
 
 // ---- local test on the 3x3x3 block ------------------------------------------------
-// block cells as a 27-bit set, bit (dx + 1) + 3 (dy + 1) + 9 (dz + 1); the centre is 13
-__device__ __forceinline__ unsigned blk_step(unsigned m) {
-    // cells of the block one D3Q19 step away from a cell of m
-    unsigned out = 0u;
-    for (int b = 0; b < 27; ++b) {
-        if (!((m >> b) & 1u)) continue;
-        const int a0 = b % 3, a1 = (b / 3) % 3, a2 = b / 9;
-        for (int q = 1; q < Q; ++q) {
-            const int e0 = a0 + cx(q), e1 = a1 + cy(q), e2 = a2 + cz(q);
-            if (e0 < 0 || e0 > 2 || e1 < 0 || e1 > 2 || e2 < 0 || e2 > 2) continue;
-            out |= 1u << (e0 + 3 * e1 + 9 * e2);
-        }
-    }
-    return out;
-}
-
 __device__ __forceinline__ int blk_cell(const Geom &G, int x, int y, int z, int dx, int dy, int dz) {
     int a = x + dx, b = y + dy, d = z + dz;
     if (a < 0 || a >= G.nx) { if (!G.per[0]) return -1; a = wrapc(a, G.nx); }
@@ -61,11 +46,8 @@ __device__ __forceinline__ int blk_cell(const Geom &G, int x, int y, int z, int 
     return a + G.nx * (b + G.ny * d);
 }
 
-// Cell c left the gas phase.  The gas of its root stays connected if (1) its gas
-// neighbours of that root are connected within the block, and (2) each of its
-// neighbours of that root that also left the gas touches that connected set: a gas
-// path through a run of removed cells can then be rerouted through the block gas
-// of each cell of the run.
+// Cell c left the gas phase: its block's gas and removed cells of its root, tested by
+// split_block_ok.
 __device__ bool split_local_ok(const Geom &G, const Dev &D, int c) {
     int x, y, z;
     cell_xyz(G, c, x, y, z);
@@ -81,19 +63,7 @@ __device__ bool split_local_ok(const Geom &G, const Dev &D, int c) {
             rem |= 1u << b;
         }
     }
-    const unsigned n18 = blk_step(1u << 13);
-    const unsigned s = gas & n18;
-    if (!s) return true;
-    unsigned comp = s & (~s + 1u);
-    for (int it = 0; it < 27; ++it) {
-        const unsigned grown = comp | (blk_step(comp) & gas);
-        if (grown == comp) break;
-        comp = grown;
-    }
-    if (s & ~comp) return false;
-    for (unsigned rm = rem & n18; rm; rm &= rm - 1u)
-        if (!(blk_step(rm & (~rm + 1u)) & comp)) return false;
-    return true;
+    return split_block_ok(gas, rem);
 }
 
 // Cell c entered the gas phase: it joins the older gas of its root (gas before the

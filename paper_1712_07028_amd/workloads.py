@@ -162,6 +162,34 @@ def bubble_column_large(n_particles=100_000, nz=1024, zs=980.0):
                     gas_spheres=[bub], particles=parts)
 
 
+def layers_of(w: Workload, z0: int, z1: int, spin_seed: int | None = None,
+              vel_range: float = 0.01) -> Workload:
+    """Layers z0 <= z < z1 of a walled column as a box of its own, with no-slip faces
+    at the cut: the spheres that lie wholly inside with a cell to spare, the gas
+    spheres that reach into the cut and the pool surface shifted down by z0 (a
+    surface above the cut leaves it liquid throughout).  With spin_seed the kept
+    spheres get seeded velocities and angular velocities in (-vel_range, vel_range)
+    and (-vel_range/2, vel_range/2), so that moving-wall links and torques are
+    exercised."""
+    nz = z1 - z0
+    p = w.particles
+    if p is not None:
+        z = p.x[:, 2] - z0
+        keep = (z - p.R >= 1.0) & (z + p.R <= nz - 2.0)
+        x = p.x[keep].copy()
+        x[:, 2] -= z0
+        u, om = p.u[keep].copy(), p.omega[keep].copy()
+        if spin_seed is not None:
+            rng = np.random.Generator(np.random.PCG64(spin_seed))
+            u = rng.uniform(-vel_range, vel_range, size=x.shape)
+            om = rng.uniform(-vel_range / 2, vel_range / 2, size=x.shape)
+        p = Particles(x=x, u=u, omega=om, R=p.R[keep].copy(), rho_p=p.rho_p[keep].copy())
+    gas = [(cx, cy, cz - z0, r, rho) for (cx, cy, cz, r, rho) in w.gas_spheres if cz - r < z1 and cz + r > z0]
+    zs = w.zs - z0 if w.zs < z1 else -1.0  # a surface above the cut: liquid throughout
+    return w.replace(name=f"{w.name}_z{z0}-{z1}", n=(w.n[0], w.n[1], nz), particles=p, zs=zs,
+                     gas_spheres=gas)
+
+
 def adjoint_window(n=64, n_particles=20):
     """Fully liquid periodic n^3 window, 20 spheres R=4 moving with U(-0.01,0.01)^3."""
     parts = particle_bed(n_particles, 4.0, (n, n, n), -1.0, None, seed=5, vel_range=0.01)

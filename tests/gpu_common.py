@@ -51,12 +51,18 @@ def compare_step(o, s, w, f_rtol=1e-6, m_tol=1e-6, ft_rtol=1e-5, allow_flag_mism
     if w.particles is not None and w.particles.n:
         n = w.particles.n
         a, b = o.particles_get(n), s.particles_get(n)
-        scale = max(np.abs(a["F"]).max(), 1e-12)
-        out["F_rel"] = float(np.abs(a["F"] - b["F"]).max() / scale)
-        # torques against the largest one, at least the largest force at one radius
-        # (a torque that vanishes by symmetry leaves only rounding to compare)
-        tscale = max(np.abs(a["T"]).max(), scale * float(np.max(w.particles.R)), 1e-12)
-        out["T_rel"] = float(np.abs(a["T"] - b["T"]).max() / tscale)
+        # per particle and component: each force component against the particle's
+        # force, each torque component against the larger of the particle's torque and
+        # its force at one lever arm R + 1 (the farthest boundary node of Eq. torque; a
+        # torque that vanishes by symmetry leaves only the rounding of the force's
+        # link terms at that arm)
+        Fn = np.linalg.norm(a["F"], axis=1)
+        Tn = np.linalg.norm(a["T"], axis=1)
+        arm = w.particles.R + 1.0
+        dF = np.abs(a["F"] - b["F"]).max(axis=1)
+        dT = np.abs(a["T"] - b["T"]).max(axis=1)
+        out["F_rel"] = float((dF / np.maximum(Fn, 1e-300)).max())
+        out["T_rel"] = float((dT / np.maximum(np.maximum(Tn, arm * Fn), 1e-300)).max())
         out["x_abs"] = float(np.abs(a["x"] - b["x"]).max())
         assert out["F_rel"] < ft_rtol and out["T_rel"] < ft_rtol, out
         assert out["x_abs"] < x_tol, out

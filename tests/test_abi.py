@@ -98,3 +98,17 @@ def test_init_static_sizes_and_limit(lib):
     assert lib.fsl_init_static(ctypes.byref(c), ctypes.c_void_p(0x1001), ctypes.byref(nb), None,
                                ctypes.byref(ctx)) == fsl.FSL_E_ARG
     assert not ctx.value
+
+
+def test_checks_library_exports_its_header():
+    """libfsl_checks.so (host builds of two kernel functions, for the exactness
+    tests) exports what include/fsl_checks.h declares."""
+    path = os.path.join(ROOT, "paper_1712_07028_amd", "libfsl_checks.so")
+    if not os.path.exists(path):
+        pytest.fail("libfsl_checks.so is not built (run __graft_entry__.build())")
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "fsl_checks.h")).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(fsl_[a-z_]+)\s*\(", text)))
+    assert names == ["fsl_check_cov_column", "fsl_check_split_block"]
+    L = ctypes.CDLL(path)
+    for n in names:
+        assert hasattr(L, n), n

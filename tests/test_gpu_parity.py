@@ -2,8 +2,9 @@
 
 Single steps start from identical states (the oracle's state imported into the
 library) and must give bit-exact cell types, populations within 1e-6 relative,
-interface mass / fill level within 1e-6 and particle force / torque within 1e-5
-of the largest value.  Multi-step runs must conserve the mass ledger to 1e-10 and
+interface mass / fill level within 1e-6, and per particle and component the force
+within 1e-5 of the particle's force and the torque within 1e-5 of the larger of
+the particle's torque and its force at lever arm R + 1.  Multi-step runs must conserve the mass ledger to 1e-10 and
 agree with the oracle on the bubble rise velocity and mean particle drag to 1 %.
 """
 import math

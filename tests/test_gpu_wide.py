@@ -1,0 +1,138 @@
+"""Element-wise parity on wide boxes, where the marching pass of the stream-collide
+step has interior tiles: layers of the 512 x 512 benchmark column (eight 64-cell
+tiles per row, so rows of tiles away from the side faces) with its own sphere
+placement, the kept spheres given seeded velocities and spins, against the FP64
+oracle on the same state:
+  - 24 layers through the free surface (582 spheres below it, the pool surface
+    of 512^2 interface cells);
+  - 96 layers through the gas bubble (R = 40, 8,394 spheres around it);
+  - a 192 x 16 x 16 box with a bubble, a free surface and spheres in the three
+    storage forms.
+Each run takes the oracle's state after a few steps, then steps both sides three
+times.  The first step is compared as in the small single-step cases; the next
+two follow the library's own stored densities (written by its previous launch)
+and are compared against bars that allow the rounding of the earlier steps
+(see each assertion).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1712_07028_amd as fsl
+from paper_1712_07028_amd import workloads as W
+
+from gpu_common import compare_step, transfer
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    O.build(force=False)
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    fsl.load_library()
+
+
+@pytest.fixture(scope="module")
+def column():
+    return W.bubble_column_large()
+
+
+def run_three(w, warm, bars):
+    o = O.Oracle(w, n_threads=16)
+    o.step(warm)
+    s = fsl.Sim(w)
+    transfer(o, s, w)
+    for k in range(3):
+        o.step(1)
+        s.step(1)
+        s.sync()
+        say(f"  step {k + 1}:", compare_step(o, s, w, **bars[k]))
+    o.close()
+    s.close()
+
+
+# populations: 1e-6 relative after one step from identical states (FP32 storage of
+# h = f - w and FP32 collision), growing by at most that per further step; interface
+# mass and fill level (FP64, fed by FP32 populations) likewise; forces and torques
+# 1e-5 per particle; positions to the FP64 rounding of the particle update
+F32_BARS = [dict(), dict(f_rtol=2e-6, m_tol=2e-6, ft_rtol=2e-5), dict(f_rtol=3e-6, m_tol=3e-6, ft_rtol=3e-5)]
+
+
+@pytest.mark.parametrize("cut", [(964, 988), (16, 112)], ids=["surface", "bubble"])
+def test_column_layers(column, cut):
+    w = W.layers_of(column, *cut, spin_seed=11)
+    say(f"layers {cut} of the column: {w.n}, {w.particles.n} spheres, gas spheres {len(w.gas_spheres)}")
+    run_three(w, 2, F32_BARS)
+
+
+def narrow_bed(storage):
+    bub = (96.0, 8.0, 5.0, 3.5, 1.0)
+    p = W.Particles(x=np.array([[20.3, 7.6, 5.2], [60.8, 8.3, 6.1], [131.4, 7.2, 4.9], [170.2, 8.9, 5.6]]),
+                    u=np.array([[0.01, -0.004, 0.002], [-0.006, 0.003, 0.0], [0.002, 0.0, -0.005],
+                                [0.0, 0.007, 0.003]]),
+                    omega=np.array([[0.003, 0.0, -0.002], [0.0, 0.004, 0.0], [-0.002, 0.001, 0.0],
+                                    [0.0, 0.0, 0.005]]),
+                    R=np.array([3.0, 3.4, 2.8, 3.2]), rho_p=np.full(4, 2.5))
+    return W.Workload(name="narrow192", n=(192, 16, 16), trt=True, tau=0.55, g=(0, 0, -2e-5), zs=12.5,
+                      steps=0, gas_spheres=[bub], particles=p, storage=storage)
+
+
+@pytest.mark.parametrize("storage", [W.STORAGE_F32, W.STORAGE_F16S, W.STORAGE_BF16S], ids=["f32", "f16s", "bf16s"])
+def test_narrow_box_forms(storage):
+    w = narrow_bed(storage)
+    say(f"192 x 16 x 16, storage {storage}")
+    if storage == W.STORAGE_F32:
+        run_three(w, 10, F32_BARS)
+        return
+    # 16-bit forms: after the first step from identical states, cell types bit-exact
+    # and every population within 4 u max|h| (u the unit roundoff of the storage
+    # format), as in the single-step case.  From then on the two states differ by a
+    # storage rounding, which moves fill levels by about u and can flip a conversion
+    # that lies that close to its threshold; the flipped cell and the neighbours it
+    # converts form one cluster of differing types.  After step k + 1: at most
+    # max(2, 2e-3 n_ifc) such clusters (n_ifc interface cells; 1 to 4 were seen
+    # among about 3,700), at most one 3x3x3 block of cells each per step, and the
+    # populations of the cells more than k + 1 cells away from them (a difference
+    # spreads one cell per step) within (4 + 2k) u max|h| (two more roundings per
+    # step: the stored input and output).
+    from scipy.ndimage import binary_dilation, label
+
+    u = {W.STORAGE_F16S: 2.0 ** -11, W.STORAGE_BF16S: 2.0 ** -9}[storage]
+    wq = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    o = O.Oracle(w, n_threads=16)
+    o.step(10)
+    s = fsl.Sim(w)
+    transfer(o, s, w)
+    for k in range(3):
+        o.step(1)
+        s.step(1)
+        s.sync()
+        fo, fg = o.get(O.FLAGS), s.get(fsl.FIELD_FLAGS)
+        mism = fo != fg
+        if k == 0:
+            np.testing.assert_array_equal(fo, fg)
+        clusters = label(mism, structure=np.ones((3, 3, 3), bool))[1]
+        assert clusters <= max(2, 2e-3 * (fo == O.IFC).sum()), clusters
+        assert mism.sum() <= 27 * k * clusters, (int(mism.sum()), clusters)
+        act = (fo == O.LIQ) | (fo == O.IFC)
+        if mism.any():
+            act &= ~binary_dilation(mism, np.ones((3, 3, 3), bool), iterations=k + 1)
+        Fo, Fg = o.get(O.F), s.get(fsl.FIELD_F)
+        hmax = np.abs(Fo - wq[:, None, None, None])[:, act].max()
+        err = np.abs(Fg - Fo)[:, act].max()
+        say(f"  step {k + 1}: {int(mism.sum())} type mismatches in {clusters} clusters, max |f - f_oracle| / max|h| = "
+            f"{err / hmax:.3e} (unit {u:.3e})")
+        assert err <= (4 + 2 * k) * u * hmax
+    o.close()
+    s.close()
