@@ -221,23 +221,89 @@ def copy_bandwidth(torch, gib=2.0, reps=5):
     return round(2.0 * n / (ms / 1e3) / 1e9, 1)
 
 
+def ceiling_bandwidth(torch, n=(512, 512, 256), reps=5):
+    """The D3Q19 pull with no arithmetic (libfsl_ceiling.so) over a closed FP32 box on
+    torch's current stream: 152 B per cell over its time (HIP events), the ceiling
+    that the stream-collide kernel's access shape allows."""
+    import ctypes
+
+    from paper_1712_07028_amd import build as B
+
+    lib = ctypes.CDLL(B.CEILING_LIB)
+    lib.fsl_ceiling_pull.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_longlong, ctypes.c_void_p]
+    N = n[0] * n[1] * n[2]
+    S = (N + 255) // 256 * 256
+    a = torch.zeros(19 * S, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+
+    def launch():
+        rc = lib.fsl_ceiling_pull(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), n[0], n[1], n[2], S,
+                                  ctypes.c_void_p(stream.cuda_stream))
+        if rc:
+            raise RuntimeError(f"fsl_ceiling_pull failed ({rc})")
+
+    launch()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        launch()
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return round(152.0 * N / (ms / 1e3) / 1e9, 1)
+
+
+def host_threads():
+    """Threads the host grants this job: OMP_NUM_THREADS when the job scheduler sets
+    it, else the CPUs in the process's affinity mask."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, steps):
-    """The FP64 oracle on a bounded sample: the lowest 16 layers of the column."""
+    """The FP64 oracle on the host: the headline value on a bounded sample of the
+    column (its lowest 16 layers, all granted threads), plus the small-box and
+    128^3-bed configurations at one thread and at all granted threads."""
     import oracle
     from paper_1712_07028_amd import workloads as W
 
     oracle.build(force=False)
-    threads = min(os.cpu_count() or 1, 16)
+    threads = host_threads()
+
+    def timed(wl, n, th):
+        o = oracle.Oracle(wl, n_threads=th)
+        t0 = time.perf_counter()
+        o.step(n)
+        dt = time.perf_counter() - t0
+        o.close()
+        return {"workload": wl.name, "box": list(wl.n), "steps": n, "threads": th,
+                "seconds": round(dt, 3), "MLUPS": round(wl.cells * n / dt / 1e6, 4)}
+
     s = W.slab_of(w, 16) if w.n[2] > 16 else w
-    o = oracle.Oracle(s, n_threads=threads)
-    t0 = time.perf_counter()
-    o.step(steps)
-    dt = time.perf_counter() - t0
-    o.close()
-    return {"value": round(s.cells * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": threads,
-            "kind": "oracle",
+    head = timed(s, steps, threads)
+    small, bed = W.bubble_column_small(), W.bubble_bed_128()
+    runs = [timed(small, small.steps, 1), timed(small, small.steps, threads),
+            timed(bed, 3, 1), timed(bed, 10, threads), timed(s, 1, 1)]
+    return {"value": head["MLUPS"], "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"{s.n[0]}x{s.n[1]}x{s.n[2]} bottom slab of the column "
-                      f"({s.particles.n if s.particles is not None else 0} spheres), {steps} steps, FP64"}
+                      f"({s.particles.n if s.particles is not None else 0} spheres), {steps} steps, FP64",
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(), "runs": runs}
 
 
 def main():
@@ -331,7 +397,10 @@ def main():
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
             "kernel": "k_stream_collide", "kernel_ms": round(avg_s * 1e3, 4),
             "algorithmic_bytes_per_launch": int(alg_bytes), "active_cells": n_active,
-            "copy_GBs": copy_bandwidth(torch)}
+            "copy_GBs": copy_bandwidth(torch),
+            "ceiling_GBs": ceiling_bandwidth(torch),
+            "ceiling_kernel": "k_pull_ceiling: D3Q19 pull, 19 FP32 SoA plane reads + 19 writes, no arithmetic, "
+                              "512x512x256 closed box"}
     breakdown = {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()}
     log(f"{mlups:.0f} MLUPS, stream-collide {avg_s * 1e3:.3f} ms, {achieved:.0f} GB/s, "
         f"breakdown ms/step {breakdown}")

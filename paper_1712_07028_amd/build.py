@@ -1,5 +1,7 @@
-"""Build the HIP library libfsl.so (gfx950) in the package directory, and
-libfsl_checks.so: host builds of two pure functions of its kernels, for tests."""
+"""Build the HIP library libfsl.so (gfx950) in the package directory, and two
+helpers: libfsl_checks.so (host builds of two pure functions of its kernels, for
+tests) and libfsl_ceiling.so (the pull with no arithmetic, a bandwidth ceiling for
+the benchmark)."""
 from __future__ import annotations
 
 import os
@@ -12,6 +14,8 @@ LIB = os.path.join(HERE, "libfsl.so")
 SOURCES = [os.path.join(CSRC, "fsl_api.hip")]
 CHECKS_LIB = os.path.join(HERE, "libfsl_checks.so")
 CHECKS_SOURCES = [os.path.join(CSRC, "fsl_checks.hip")]
+CEILING_LIB = os.path.join(HERE, "libfsl_ceiling.so")
+CEILING_SOURCES = [os.path.join(CSRC, "fsl_ceiling.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -40,6 +44,7 @@ def build(verbose=False):
     """Compile libfsl.so and libfsl_checks.so; always recompiles."""
     _compile(LIB, SOURCES, verbose)
     _compile(CHECKS_LIB, CHECKS_SOURCES, verbose)
+    _compile(CEILING_LIB, CEILING_SOURCES, verbose)
     return LIB
 
 

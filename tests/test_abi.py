@@ -100,15 +100,20 @@ def test_init_static_sizes_and_limit(lib):
     assert not ctx.value
 
 
-def test_checks_library_exports_its_header():
+@pytest.mark.parametrize("lib_name,header,expected", [
+    ("libfsl_checks.so", "fsl_checks.h", ["fsl_check_cov_column", "fsl_check_split_block"]),
+    ("libfsl_ceiling.so", "fsl_ceiling.h", ["fsl_ceiling_pull"]),
+])
+def test_helper_libraries_export_their_headers(lib_name, header, expected):
     """libfsl_checks.so (host builds of two kernel functions, for the exactness
-    tests) exports what include/fsl_checks.h declares."""
-    path = os.path.join(ROOT, "paper_1712_07028_amd", "libfsl_checks.so")
+    tests) and libfsl_ceiling.so (the benchmark's bandwidth ceiling) export what
+    their headers declare."""
+    path = os.path.join(ROOT, "paper_1712_07028_amd", lib_name)
     if not os.path.exists(path):
-        pytest.fail("libfsl_checks.so is not built (run __graft_entry__.build())")
-    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "fsl_checks.h")).read(), flags=re.S)
+        pytest.fail(f"{lib_name} is not built (run __graft_entry__.build())")
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", header)).read(), flags=re.S)
     names = sorted(set(re.findall(r"\b(fsl_[a-z_]+)\s*\(", text)))
-    assert names == ["fsl_check_cov_column", "fsl_check_split_block"]
+    assert names == expected
     L = ctypes.CDLL(path)
     for n in names:
         assert hasattr(L, n), n

@@ -48,6 +48,32 @@ def column():
     return W.bubble_column_large()
 
 
+def interior_boundary_cells(fl):
+    """Liquid and interface cells of the marching pass's interior tiles (64 x 4 cells
+    of a plane whose one-cell halo lies inside the box) that are interface cells or
+    have a neighbour that is not liquid: the cells whose update leaves the plain pull
+    there (reconstruction, bounce-back, mass exchange)."""
+    nz, ny, nx = fl.shape
+    ix = np.zeros(nx, bool)
+    for t in range(nx // 64):
+        if t * 64 >= 1 and t * 64 + 63 <= nx - 2:
+            ix[t * 64:(t + 1) * 64] = True
+    iy = np.zeros(ny, bool)
+    for t in range(ny // 4):
+        if t * 4 >= 1 and t * 4 + 3 <= ny - 2:
+            iy[t * 4:(t + 1) * 4] = True
+    inner = iy[None, :, None] & ix[None, None, :]
+    other = np.pad(fl != fsl.LIQ, 1, constant_values=True)
+    near = np.zeros(fl.shape, bool)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if abs(dx) + abs(dy) + abs(dz) in (1, 2):
+                    near |= other[1 + dz:1 + dz + nz, 1 + dy:1 + dy + ny, 1 + dx:1 + dx + nx]
+    act = (fl == fsl.LIQ) | (fl == fsl.IFC)
+    return int((act & inner & (near | (fl == fsl.IFC))).sum())
+
+
 def run_three(w, warm, bars):
     o = O.Oracle(w, n_threads=16)
     o.step(warm)
@@ -57,7 +83,8 @@ def run_three(w, warm, bars):
         o.step(1)
         s.step(1)
         s.sync()
-        say(f"  step {k + 1}:", compare_step(o, s, w, **bars[k]))
+        out = compare_step(o, s, w, **bars[k])
+        say(f"  step {k + 1}: {interior_boundary_cells(s.get(fsl.FIELD_FLAGS))} boundary cells of interior tiles;", out)
     o.close()
     s.close()
 
