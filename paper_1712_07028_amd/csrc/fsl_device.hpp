@@ -28,6 +28,15 @@ __host__ __device__ constexpr int opp(int q) {
     constexpr int v[Q] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8, 7, 14, 13, 12, 11, 18, 17, 16, 15};
     return v[q];
 }
+
+// directions whose component along axis A (0 x, 1 y, 2 z) equals V, as a bit set
+template <int A, int V>
+__host__ __device__ constexpr uint32_t dir_mask() {
+    uint32_t m = 0;
+    for (int q = 1; q < Q; ++q)
+        if ((A == 0 ? cx(q) : A == 1 ? cy(q) : cz(q)) == V) m |= 1u << q;
+    return m;
+}
 __host__ __device__ constexpr float wq(int q) {
     return q == 0 ? 1.0f / 3.0f : (q <= 6 ? 1.0f / 18.0f : 1.0f / 36.0f);
 }

@@ -823,34 +823,36 @@ __device__ __forceinline__ void march_cell(const Geom &G, const Phys &Ph, const 
     T *B = (T *)Bv;
     const float inv = Ph.inv;
     auto slot = [&](int q) { return cz(q) == 1 ? sm1 : (cz(q) == -1 ? sp1 : s0); };  // plane z - c_z
-    // bounce-back sources: particle nodes (sm) and walls (wm)
+    // bounce-back sources: particle nodes (sm, from the staged cell types) and resting
+    // walls (wm: the sources beyond a non-periodic face, from the cell's position)
     uint32_t sm = 0, wm = 0;
-    if (act && nbnf) {
+    if (act) {
+        if (!G.per[0]) wm |= (x == 0 ? dir_mask<0, 1>() : 0u) | (x == G.nx - 1 ? dir_mask<0, -1>() : 0u);
+        if (!G.per[1]) wm |= (y == 0 ? dir_mask<1, 1>() : 0u) | (y == G.ny - 1 ? dir_mask<1, -1>() : 0u);
+        if (!G.per[2]) wm |= (z == 0 ? dir_mask<2, 1>() : 0u) | (z == G.nz - 1 ? dir_mask<2, -1>() : 0u);
+        if (nbnf) {
 #pragma unroll
-        for (int q = 1; q < Q; ++q) {
-            const uint8_t sf = L.ft[slot(q)][ly + 1 - cy(q)][lx + 1 - cx(q)];
-            sm |= (uint32_t)(sf == SOL) << q;
-            wm |= (uint32_t)(sf == WALL) << q;
+            for (int q = 1; q < Q; ++q) sm |= (uint32_t)(L.ft[slot(q)][ly + 1 - cy(q)][lx + 1 - cx(q)] == SOL) << q;
         }
     }
     const uint32_t bb = sm | wm;
-    // the particle P of the first particle-node link (in direction order) and whether
-    // any other such link leads elsewhere, from the staged ids
+    // the particle P of the particle-node links and whether some link leads to another:
+    // over the 18 staged ids (-1 at every cell that is no particle node) the smallest as
+    // an unsigned value and the largest as a signed one agree exactly when every
+    // particle node among them has the same id
     int P = -1;
     bool multi = false;
     if (sm) {
-#pragma unroll
-        for (int q = Q - 1; q >= 1; --q) {
-            const int p = L.pt[slot(q)][ly + 1 - cy(q)][lx + 1 - cx(q)];
-            P = ((sm >> q) & 1u) ? p : P;
-        }
-        unsigned diff = 0;
+        unsigned pmin = 0xffffffffu;
+        int pmax = -1;
 #pragma unroll
         for (int q = 1; q < Q; ++q) {
             const int p = L.pt[slot(q)][ly + 1 - cy(q)][lx + 1 - cx(q)];
-            diff |= ((sm >> q) & 1u) ? (unsigned)(p ^ P) : 0u;
+            pmin = min(pmin, (unsigned)p);
+            pmax = max(pmax, p);
         }
-        multi = diff != 0u;
+        P = (int)pmin;
+        multi = (int)pmin != pmax;
     }
     const bool okP = (unsigned)P < (unsigned)D.np;
     // rho_w of Eq. bbrule: the density of this cell at t, as the launch before stored it
@@ -858,25 +860,33 @@ __device__ __forceinline__ void march_cell(const Geom &G, const Phys &Ph, const 
     if (sm && D.rhow != nullptr && D.st_prev >= 0) e = D.rhow[c];
     PMir pm{};
     if (sm && okP) pm = pmir_load(D.pmir, P);
-    // pulls
+    // pulls; a bounce-back link takes the cell's own opposite population instead (the
+    // source address is selected, so every population is one load)
     float fi[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) fi[q] = 0.f;
     if (act) {  // lanes without a liquid cell load nothing
+        if (__ballot(bb) == 0ull) {
 #define FSL_PULL(QQ) fi[QQ] = SS::ld(A + QQ * S + (unsigned)(c + src_off<QQ>(so)), inv);
-        FSL_PULL(0) FSL_PULL(1) FSL_PULL(2) FSL_PULL(3) FSL_PULL(4) FSL_PULL(5) FSL_PULL(6)
-        FSL_PULL(7) FSL_PULL(8) FSL_PULL(9) FSL_PULL(10) FSL_PULL(11) FSL_PULL(12) FSL_PULL(13)
-        FSL_PULL(14) FSL_PULL(15) FSL_PULL(16) FSL_PULL(17) FSL_PULL(18)
+            FSL_PULL(0) FSL_PULL(1) FSL_PULL(2) FSL_PULL(3) FSL_PULL(4) FSL_PULL(5) FSL_PULL(6)
+            FSL_PULL(7) FSL_PULL(8) FSL_PULL(9) FSL_PULL(10) FSL_PULL(11) FSL_PULL(12) FSL_PULL(13)
+            FSL_PULL(14) FSL_PULL(15) FSL_PULL(16) FSL_PULL(17) FSL_PULL(18)
 #undef FSL_PULL
+        } else {
+            fi[0] = SS::ld(A + (unsigned)c, inv);
+#define FSL_PULL(QQ)                                                                                       \
+    {                                                                                                      \
+        const bool b_ = (bb >> QQ) & 1u;                                                                   \
+        fi[QQ] = SS::ld((b_ ? A + opp(QQ) * S : A + QQ * S) + (unsigned)(b_ ? c : c + src_off<QQ>(so)), inv); \
+    }
+            FSL_PULL(1) FSL_PULL(2) FSL_PULL(3) FSL_PULL(4) FSL_PULL(5) FSL_PULL(6)
+            FSL_PULL(7) FSL_PULL(8) FSL_PULL(9) FSL_PULL(10) FSL_PULL(11) FSL_PULL(12) FSL_PULL(13)
+            FSL_PULL(14) FSL_PULL(15) FSL_PULL(16) FSL_PULL(17) FSL_PULL(18)
+#undef FSL_PULL
+        }
     }
     // particle ids of plane z+2 for the ring (its cell types were loaded before)
     pre_pids(D.pid, SI, R, zo2);
-    // bounce-back links take the cell's own opposite population instead
-    if (bb) {
-#pragma unroll
-        for (int q = 1; q < Q; ++q)
-            if ((bb >> q) & 1u) fi[q] = SS::ld(A + opp(q) * S + (unsigned)c, inv);
-    }
     if (sm) {
         const float rho_t = rhow_valid(e, D.st_prev) ? __uint_as_float(e) : own_density<ST>(Av, S, c, inv);
         const int t = threadIdx.x;
