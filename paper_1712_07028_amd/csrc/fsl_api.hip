@@ -280,6 +280,9 @@ void set_phys(fsl_ctx *c) {
     }
     c->Ph.open_atm = f.open_atmosphere != 0;
     c->Ph.inv = 1.0f / c->Ph.scale;
+    // FSL_WIDE_OFFSETS=1 takes the 64-bit form on any box (a test of that form)
+    const char *wide = getenv("FSL_WIDE_OFFSETS");
+    c->Ph.wide = c->G.S >= (1ll << 30) || (wide && wide[0] == '1');
 }
 
 // one lattice update of every cell: the marching pass over the liquid cells, then the

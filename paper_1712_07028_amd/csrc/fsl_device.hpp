@@ -146,6 +146,8 @@ struct Phys {
                        // then take the general path
     int slip[3];       // the faces of axis a are free-slip
     int open_atm;      // bubble 0 is held at its density (pressure outlet)
+    int wide;          // the march's bounce-back pulls take 64-bit offsets (S >= 2^30,
+                       // where an offset within a pair of planes leaves 32 bits)
 };
 
 struct Dev {

@@ -872,6 +872,25 @@ __device__ __forceinline__ void march_cell(const Geom &G, const Phys &Ph, const 
             FSL_PULL(7) FSL_PULL(8) FSL_PULL(9) FSL_PULL(10) FSL_PULL(11) FSL_PULL(12) FSL_PULL(13)
             FSL_PULL(14) FSL_PULL(15) FSL_PULL(16) FSL_PULL(17) FSL_PULL(18)
 #undef FSL_PULL
+        } else if (!Ph.wide) {
+            // the planes q and opp(q) share the base of the lower one; the lane's offset
+            // from it (at most 4 S) stays within 32 bits
+            const unsigned S32 = (unsigned)S;
+            fi[0] = SS::ld(A + (unsigned)c, inv);
+#define FSL_PULL(QQ)                                                                                      \
+    {                                                                                                     \
+        constexpr int lo_ = QQ < opp(QQ) ? QQ : opp(QQ);                                                  \
+        const int so_ = src_off<QQ>(so);                                                                  \
+        const unsigned m_ = (unsigned)__builtin_amdgcn_sbfe((int)bb, QQ, 1); /* all ones on a link */     \
+        unsigned o_ = (unsigned)(QQ - lo_) * S32 + (unsigned)(c + so_) +                                   \
+                      (((unsigned)(opp(QQ) - QQ) * S32 - (unsigned)so_) & m_);                            \
+        __asm__("" : "+v"(o_));                                                                           \
+        fi[QQ] = SS::ld(A + lo_ * S + o_, inv);                                                           \
+    }
+            FSL_PULL(1) FSL_PULL(2) FSL_PULL(3) FSL_PULL(4) FSL_PULL(5) FSL_PULL(6)
+            FSL_PULL(7) FSL_PULL(8) FSL_PULL(9) FSL_PULL(10) FSL_PULL(11) FSL_PULL(12) FSL_PULL(13)
+            FSL_PULL(14) FSL_PULL(15) FSL_PULL(16) FSL_PULL(17) FSL_PULL(18)
+#undef FSL_PULL
         } else {
             fi[0] = SS::ld(A + (unsigned)c, inv);
 #define FSL_PULL(QQ)                                                                                       \

@@ -101,6 +101,22 @@ def test_single_step_particle_bed(warm):
     say(compare_step(o, s, w))
 
 
+def test_single_step_wide_offsets(monkeypatch):
+    """The 64-bit form of the marching pass's bounce-back pulls, which boxes of 2^30
+    cells and more take, forced on the particle bed: the same bars."""
+    monkeypatch.setenv("FSL_WIDE_OFFSETS", "1")
+    w = small_bed()
+    say("single step, particle bed, 64-bit pull offsets")
+    o = O.Oracle(w)
+    o.step(30)
+    s = fsl.Sim(w)
+    transfer(o, s, w)
+    o.step(1)
+    s.step(1)
+    s.sync()
+    say(compare_step(o, s, w))
+
+
 @pytest.mark.parametrize("integrate", [False, True])
 def test_single_step_touching_spheres(integrate):
     """Three spheres with surface gaps below one cell: nodes of one sphere have links
