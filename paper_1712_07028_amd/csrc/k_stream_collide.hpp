@@ -714,6 +714,10 @@ __device__ __forceinline__ bool nbr_any(const MarchLds &L, int sm, int s0, int s
     return (m >> lx) & 1ull;
 }
 
+__device__ __forceinline__ void lds_add(double *p, double v) {
+    (void)__hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // one lane's sums (in LDS) straight to its particle (a lane that moves on to another
 // particle), then cleared
 __device__ __forceinline__ void macc_atomic(const Dev &D, MarchLds &L, int t) {
@@ -816,7 +820,8 @@ template <int ST>
 __device__ __forceinline__ void march_cell(const Geom &G, const Phys &Ph, const Dev &D, MarchLds &L,
                                            int sm1, int s0, int sp1, int lx, int ly, int x, int y, int z, int c,
                                            const SrcOff &so, bool act, bool store, bool nbnf, const void *Av,
-                                           void *Bv, long long S, const StageIdx &SI, RowPre &R, int zo2) {
+                                           void *Bv, long long S, const StageIdx &SI, RowPre &R, int zo2,
+                                           int &curP) {
     using SS = Store<ST>;
     using T = typename SS::T;
     const T *A = (const T *)Av;
@@ -913,8 +918,9 @@ __device__ __forceinline__ void march_cell(const Geom &G, const Phys &Ph, const 
         // With rho u = rho_w u_w the link adds a_q = 6 w_q c_q . rho u to the bounced
         // population, and Delta j = -c_q (h*_qbar + h_q + 2 w_q) with h_q = h*_qbar + a_q.
         auto particle_links = [&](int Pk, uint32_t mk, const PMir &m) {
-            if (Pk != L.accP[t]) {
-                if (L.accP[t] >= 0) macc_atomic(D, L, t);
+            if (Pk != curP) {  // the lane's sums move on to another particle
+                if (curP >= 0) macc_atomic(D, L, t);
+                curP = Pk;
                 L.accP[t] = Pk;
             }
             // rigid-body velocity at the node: c_q . u_w at the link midpoint equals
@@ -957,13 +963,14 @@ __device__ __forceinline__ void march_cell(const Geom &G, const Phys &Ph, const 
             const double F0 = (double)f0 + kx * (1.0 / 18.0), F1 = (double)f1 + ky * (1.0 / 18.0),
                          F2 = (double)f2 + kz * (1.0 / 18.0);
             const double dx = rx, dy = ry, dz = rz;
-            L.acc[0][t] += F0;
-            L.acc[1][t] += F1;
-            L.acc[2][t] += F2;
-            L.acc[3][t] += dy * F2 - dz * F1;
-            L.acc[4][t] += dz * F0 - dx * F2;
-            L.acc[5][t] += dx * F1 - dy * F0;
-            L.acc[6][t] += (double)dm;
+            // LDS atomic adds without return: the lane's own slots, so nothing waits
+            lds_add(&L.acc[0][t], F0);
+            lds_add(&L.acc[1][t], F1);
+            lds_add(&L.acc[2][t], F2);
+            lds_add(&L.acc[3][t], dy * F2 - dz * F1);
+            lds_add(&L.acc[4][t], dz * F0 - dx * F2);
+            lds_add(&L.acc[5][t], dx * F1 - dy * F0);
+            lds_add(&L.acc[6][t], (double)dm);
         };
         if (!multi && okP) {
             particle_links(P, sm, pm);
@@ -1040,6 +1047,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE_MARCH))
     }
     if (threadIdx.x < 2) L.genflag[threadIdx.x] = 0;
     L.accP[threadIdx.x] = -1;
+    int curP = -1;  // the particle of the lane's sums (a copy of L.accP)
 #pragma unroll
     for (int k = 0; k < 7; ++k) L.acc[k][threadIdx.x] = 0.0;
     __syncthreads();
@@ -1077,7 +1085,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE_MARCH))
             so.zp = step_to(z, 1, G.nz, G.per[2], nxy);
             const int c = xc + G.nx * yc + nxy * z;
             march_cell<ST>(G, Ph, D, L, sm1, s0, sp1, lx, ly, xl, yl, z, c, so, act, inb && !gen_c, nbnf, Av, Bv, Sl,
-                           SI, R, zo2);
+                           SI, R, zo2, curP);
         } else {
             pre_pids(D.pid, SI, R, zo2);
         }
