@@ -53,6 +53,7 @@ class OrcConfig(ctypes.Structure):
         ("sigma", ctypes.c_double),
         ("freeslip", ctypes.c_int * 3),
         ("open_atmosphere", ctypes.c_int),
+        ("contact_k", ctypes.c_double),
     ]
 
 
@@ -97,6 +98,8 @@ def lib():
         L.orc_equilibrium.argtypes = [ctypes.c_double, dp, dp]
         L.orc_lubrication.argtypes = [dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, dp]
+        L.orc_contact.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_walls_get.argtypes = [P, dp]
         L.orc_lambda_minus.restype = ctypes.c_double
         L.orc_lambda_minus.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int]
         _lib = L
@@ -118,6 +121,13 @@ def lubrication(x1, x2, u1, u2, R1, R2, mu):
     a = [np.ascontiguousarray(v, dtype=np.float64) for v in (x1, x2, u1, u2)]
     F = np.zeros(3)
     applied = lib().orc_lubrication(*[_dp(v) for v in a], float(R1), float(R2), float(mu), _dp(F))
+    return F, bool(applied)
+
+
+def contact(x1, x2, R1, R2, k):
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (x1, x2)]
+    F = np.zeros(3)
+    applied = lib().orc_contact(*[_dp(v) for v in a], float(R1), float(R2), float(k), _dp(F))
     return F, bool(applied)
 
 
@@ -159,6 +169,7 @@ class Oracle:
         for a in range(3):
             cfg.freeslip[a] = int(getattr(w, "freeslip", (0, 0, 0))[a])
         cfg.open_atmosphere = int(bool(getattr(w, "open_atmosphere", False)))
+        cfg.contact_k = float(getattr(w, "contact_k", 0.0))
         self.w = w
         self.N = w.cells
         self.L = lib()
@@ -191,6 +202,13 @@ class Oracle:
         rc = self.L.orc_particles_set(self.c, int(p.n), *[_dp(v) for v in arr])
         if rc:
             raise ValueError("orc_particles_set failed")
+
+    def walls(self):
+        """Force of the fluid on each no-slip face over the last step, (3, 2, 3):
+        [axis][low/high side][component]."""
+        F = np.zeros(18)
+        self.L.orc_walls_get(self.c, _dp(F))
+        return F.reshape(3, 2, 3)
 
     def particles_get(self, n):
         out = [np.zeros((n, 3)) for _ in range(5)]

@@ -81,6 +81,7 @@ struct orc_ctx {
     int np;
     double *px, *pu, *pw, *pR, *prho, *pF, *pT, *pFp, *pTp;
     int have_prev;          /* a previous step's force exists */
+    double wallF[18];       /* force on each no-slip face [2 axis + side][comp], last step */
     /* bubbles */
     int nb;
     double *bM, *bV, *bV0, *bcent, *brho;
@@ -144,6 +145,24 @@ static int mirror_dir(int q, int m)
     for (int p = 0; p < 19; ++p)
         if (CX[p] == e[0] && CY[p] == e[1] && CZ[p] == e[2]) return p;
     return q;
+}
+
+/* Periodic images of the spheres: along a periodic axis a displacement is taken as
+ * its nearest image, in [-n/2, n/2); along a walled axis as it is. */
+static double min_image(const orc_ctx *c, int a, double d)
+{
+    if (!c->cfg.periodic[a]) return d;
+    const double n = c->cfg.n[a];
+    return d - n * floor(d / n + 0.5);
+}
+
+/* a coordinate along a periodic axis taken into [0, n) */
+static double wrap_coord(const orc_ctx *c, int a, double v)
+{
+    if (!c->cfg.periodic[a]) return v;
+    const double n = c->cfg.n[a];
+    v -= n * floor(v / n);
+    return v < n ? v : 0.0; /* v just below 0 can round up to n */
 }
 
 static void cell_ijk(const orc_ctx *c, int x, int *i, int *j, int *k)
@@ -210,11 +229,11 @@ static void post_moments(const orc_ctx *c, const double *f, int x, double *rho, 
     u[2] = jz / r - 0.5 * c->cfg.g[2];
 }
 
-/* rigid-body velocity of particle P at point p */
+/* rigid-body velocity of particle P at point p (arm to the nearest image) */
 static void rigid_velocity(const orc_ctx *c, int P, const double p[3], double uw[3])
 {
     const double *xp = c->px + 3 * P, *up = c->pu + 3 * P, *wp = c->pw + 3 * P;
-    double r0 = p[0] - xp[0], r1 = p[1] - xp[1], r2 = p[2] - xp[2];
+    double r0 = min_image(c, 0, p[0] - xp[0]), r1 = min_image(c, 1, p[1] - xp[1]), r2 = min_image(c, 2, p[2] - xp[2]);
     uw[0] = up[0] + (wp[1] * r2 - wp[2] * r1);
     uw[1] = up[1] + (wp[2] * r0 - wp[0] * r2);
     uw[2] = up[2] + (wp[0] * r1 - wp[1] * r0);
@@ -607,6 +626,7 @@ static void coverage_update(orc_ctx *c)
         for (int a = 0; a < 3; ++a) {
             lo[a] = (int)floor(xp[a] - R);
             hi[a] = (int)ceil(xp[a] + R);
+            if (c->cfg.periodic[a]) continue; /* nodes of the images across the faces */
             if (lo[a] < 0) lo[a] = 0;
             if (hi[a] > c->cfg.n[a] - 1) hi[a] = c->cfg.n[a] - 1;
         }
@@ -615,7 +635,7 @@ static void coverage_update(orc_ctx *c)
                 for (int i = lo[0]; i <= hi[0]; ++i) {
                     double d0 = i - xp[0], d1 = j - xp[1], d2 = k - xp[2];
                     if ((d0 * d0 + d1 * d1) + d2 * d2 <= R * R) {
-                        int x = i + c->nx * (j + c->ny * k);
+                        int x = wrap_or_wall(i, c->nx, 1) + c->nx * (wrap_or_wall(j, c->ny, 1) + c->ny * wrap_or_wall(k, c->nz, 1));
                         if (c->claim[x] < 0) c->claim[x] = P;
                     }
                 }
@@ -725,20 +745,16 @@ static void coverage_update(orc_ctx *c)
 }
 
 /* ---- particles ---------------------------------------------------------------- */
-/* Sphere positions this implementation covers: coverage, pair search and lever arms
- * take node coordinates without wrapping, so on a periodic axis a sphere and its links
- * must stay clear of the faces (centre in [R + 1, n - R - 2]); on a walled axis the
- * centre lies in the box (faces at -1/2 and n - 1/2).  Every component finite. */
+/* Sphere positions: every component finite; on a walled axis the centre lies in the
+ * box (faces at -1/2 and n - 1/2); on a periodic axis anywhere (the centre is kept
+ * in [0, n), and the sphere acts through its nearest images). */
 static int position_ok(const orc_ctx *c, const double *x, double R)
 {
+    (void)R;
     for (int a = 0; a < 3; ++a) {
         double v = x[a];
         if (!isfinite(v)) return 0;
-        if (c->cfg.periodic[a]) {
-            if (v < R + 1.0 || v > c->cfg.n[a] - R - 2.0) return 0;
-        } else if (v < -0.5 || v > c->cfg.n[a] - 0.5) {
-            return 0;
-        }
+        if (!c->cfg.periodic[a] && (v < -0.5 || v > c->cfg.n[a] - 0.5)) return 0;
     }
     return 1;
 }
@@ -762,7 +778,7 @@ int orc_particles_set(orc_ctx *c, int n, const double *x, const double *u,
     c->have_prev = 0;
     for (int P = 0; P < n; ++P) {
         for (int a = 0; a < 3; ++a) {
-            c->px[3 * P + a] = x[3 * P + a];
+            c->px[3 * P + a] = wrap_coord(c, a, x[3 * P + a]);
             c->pu[3 * P + a] = u ? u[3 * P + a] : 0.0;
             c->pw[3 * P + a] = omega ? omega[3 * P + a] : 0.0;
             c->pF[3 * P + a] = 0;
@@ -774,6 +790,12 @@ int orc_particles_set(orc_ctx *c, int n, const double *x, const double *u,
     coverage_update(c);
     bubbles_recompute(c);
     split_bubbles(c);
+    return 0;
+}
+
+int orc_walls_get(const orc_ctx *c, double F[18])
+{
+    for (int a = 0; a < 18; ++a) F[a] = c->wallF[a];
     return 0;
 }
 
@@ -789,6 +811,22 @@ int orc_particles_get(orc_ctx *c, int n, double *x, double *u, double *omega, do
             if (T) T[3 * P + a] = c->pT[3 * P + a];
         }
     return n;
+}
+
+/* Contact between overlapping spheres.  The paper gives no contact model (its
+ * lubrication force is cut off at small gaps); reading: a linear repulsive spring
+ * of stiffness k along the line of centres, F1 = -k (R1 + R2 - |d|) d/|d| for
+ * |d| < R1 + R2 (d = x2 - x1), equal and opposite on particle 2; k = 0 switches it
+ * off.  Returns 1 when a force is applied. */
+int orc_contact(const double x1[3], const double x2[3], double R1, double R2, double k, double F1[3])
+{
+    double d[3] = {x2[0] - x1[0], x2[1] - x1[1], x2[2] - x1[2]};
+    double dist = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    F1[0] = F1[1] = F1[2] = 0;
+    if (!(k > 0.0) || !(dist < R1 + R2) || dist <= 0.0) return 0;
+    double s = -k * (R1 + R2 - dist) / dist;
+    for (int a = 0; a < 3; ++a) F1[a] = s * d[a];
+    return 1;
 }
 
 /* Eq. (lubrication) with the gap limited from below by 0.2 Delta_c and applied only
@@ -820,9 +858,11 @@ int orc_lubrication(const double x1[3], const double x2[3], const double u1[3],
  * exchange that otherwise drives explicit coupling unstable at density ratio
  * 2.5); right after the particle table is set, this step's value alone.  The
  * lubrication force is recomputed every substep, gravity m_P g (buoyancy comes
- * through the fluid pressure), m_P = rho_P 4/3 pi R^3, I = 2/5 m_P R^2.
- * Velocity is updated before position.  A sphere closer than R to a wall face
- * while moving towards it has that velocity component reversed. */
+ * through the fluid pressure), m_P = rho_P 4/3 pi R^3, I = 2/5 m_P R^2.  The pair
+ * forces (lubrication, contact) take the nearest periodic image of the partner.
+ * Velocity is updated before position; along a periodic axis the position is kept
+ * in [0, n).  A sphere closer than R to a wall face while moving towards it has
+ * that velocity component reversed. */
 static void particles_integrate(orc_ctx *c)
 {
     const int np = c->np, ns = c->cfg.n_sub;
@@ -833,9 +873,17 @@ static void particles_integrate(orc_ctx *c)
         memset(Fl, 0, sizeof(double) * 3 * np);
         for (int a = 0; a < np; ++a)
             for (int b = a + 1; b < np; ++b) {
-                double F1[3];
-                if (orc_lubrication(c->px + 3 * a, c->px + 3 * b, c->pu + 3 * a, c->pu + 3 * b,
+                double F1[3], xb[3];
+                for (int d = 0; d < 3; ++d)
+                    xb[d] = c->px[3 * a + d] + min_image(c, d, c->px[3 * b + d] - c->px[3 * a + d]);
+                if (orc_lubrication(c->px + 3 * a, xb, c->pu + 3 * a, c->pu + 3 * b,
                                     c->pR[a], c->pR[b], mu, F1)) {
+                    for (int d = 0; d < 3; ++d) {
+                        Fl[3 * a + d] += F1[d];
+                        Fl[3 * b + d] -= F1[d];
+                    }
+                }
+                if (orc_contact(c->px + 3 * a, xb, c->pR[a], c->pR[b], c->cfg.contact_k, F1)) {
                     for (int d = 0; d < 3; ++d) {
                         Fl[3 * a + d] += F1[d];
                         Fl[3 * b + d] -= F1[d];
@@ -854,7 +902,7 @@ static void particles_integrate(orc_ctx *c)
                 }
                 double F = Fh + mP * c->cfg.g[d] + Fl[3 * P + d];
                 c->pu[3 * P + d] += dt * F / mP;
-                c->px[3 * P + d] += dt * c->pu[3 * P + d];
+                c->px[3 * P + d] = wrap_coord(c, d, c->px[3 * P + d] + dt * c->pu[3 * P + d]);
                 c->pw[3 * P + d] += dt * Th / IP;
                 if (!c->cfg.periodic[d]) {
                     if (c->px[3 * P + d] < R - 0.5 && c->pu[3 * P + d] < 0)
@@ -884,7 +932,8 @@ static void particles_integrate(orc_ctx *c)
  * c_qbar f_qbar(x,t+1) with f_qbar(x,t+1) from Eq. (bbrule); the torque arm is the
  * node x.  A solid node of another particle P' with a link into P contributes
  * with equilibrium populations at rho = 1 and the rigid velocity of P' at that
- * node: Delta j = 2 c_q e^+_q(1, u_P'(x)).  Walls and gas contribute nothing. */
+ * node: Delta j = 2 c_q e^+_q(1, u_P'(x)).  Walls and gas contribute nothing.  The
+ * torque arm runs from the nearest image of the centre. */
 static void force_pass(orc_ctx *c)
 {
     const size_t N = (size_t)c->N;
@@ -912,7 +961,8 @@ static void force_pass(orc_ctx *c)
                 double fin = bb_particle(c, c->f, x, q, P, rho);
                 /* link x -> x + c_qbar enters P; Delta j = c_qbar (fout + fin) */
                 double dj[3] = {-CX[q] * (fout + fin), -CY[q] * (fout + fin), -CZ[q] * (fout + fin)};
-                double r[3] = {i - c->px[3 * P], j - c->px[3 * P + 1], k - c->px[3 * P + 2]};
+                double r[3] = {min_image(c, 0, i - c->px[3 * P]), min_image(c, 1, j - c->px[3 * P + 1]),
+                               min_image(c, 2, k - c->px[3 * P + 2])};
                 c->pF[3 * P] += dj[0];
                 c->pF[3 * P + 1] += dj[1];
                 c->pF[3 * P + 2] += dj[2];
@@ -932,7 +982,8 @@ static void force_pass(orc_ctx *c)
                 rigid_velocity(c, Pp, p, ur);
                 double ep = 2.0 * eq_plus(q, 1.0, ur);
                 double dj[3] = {CX[q] * ep, CY[q] * ep, CZ[q] * ep};
-                double r[3] = {i - c->px[3 * P], j - c->px[3 * P + 1], k - c->px[3 * P + 2]};
+                double r[3] = {min_image(c, 0, i - c->px[3 * P]), min_image(c, 1, j - c->px[3 * P + 1]),
+                               min_image(c, 2, k - c->px[3 * P + 2])};
                 c->pF[3 * P] += dj[0];
                 c->pF[3 * P + 1] += dj[1];
                 c->pF[3 * P + 2] += dj[2];
@@ -1063,8 +1114,10 @@ static void stream_collide(orc_ctx *c)
     const size_t N = (size_t)c->N;
     const double *g = c->cfg.g;
     int nerr = 0;
+    double wf[18];
+    for (int a = 0; a < 18; ++a) wf[a] = 0.0;
 #ifdef _OPENMP
-#pragma omp parallel for schedule(static) reduction(| : nerr) num_threads(c->cfg.n_threads > 0 ? c->cfg.n_threads : omp_get_max_threads())
+#pragma omp parallel for schedule(static) reduction(| : nerr) reduction(+ : wf[:18]) num_threads(c->cfg.n_threads > 0 ? c->cfg.n_threads : omp_get_max_threads())
 #endif
     for (int k = 0; k < c->nz; ++k)
         for (int j = 0; j < c->ny; ++j)
@@ -1120,9 +1173,16 @@ static void stream_collide(orc_ctx *c)
                         int a = 0;
                         while (!((cross >> a) & 1) || c->cfg.freeslip[a]) ++a;
                         const int v = a == 0 ? i - CX[q] : (a == 1 ? j - CY[q] : k - CZ[q]);
-                        const double *uw = c->cfg.wall_u[a][v < 0 ? 0 : 1];
+                        const int side = v < 0 ? 0 : 1;
+                        const double *uw = c->cfg.wall_u[a][side];
                         double cu = CX[q] * uw[0] + CY[q] * uw[1] + CZ[q] * uw[2];
-                        fc[q] = c->f[(size_t)OPP[q] * N + x] + 6.0 * W[q] * rho_t * cu;
+                        const double fout = c->f[(size_t)OPP[q] * N + x];
+                        fc[q] = fout + 6.0 * W[q] * rho_t * cu;
+                        /* momentum exchange with that face (as for particle links):
+                         * Delta j = c_qbar (f*_qbar(x,t) + f_q(x,t+1)) */
+                        wf[3 * (2 * a + side)] -= CX[q] * (fout + fc[q]);
+                        wf[3 * (2 * a + side) + 1] -= CY[q] * (fout + fc[q]);
+                        wf[3 * (2 * a + side) + 2] -= CZ[q] * (fout + fc[q]);
                     } else if (sf == SOL) {
                         fc[q] = bb_particle(c, c->f, x, q, c->pid[s], rho_t);
                     } else { /* gas: Eq. (fsk) with p_w = p_g of the neighbour's bubble */
@@ -1186,6 +1246,7 @@ static void stream_collide(orc_ctx *c)
                 for (int q = 0; q < 19; ++q) c->fn[(size_t)q * N + x] = fc[q];
             }
     c->err |= (uint32_t)nerr;
+    for (int a = 0; a < 18; ++a) c->wallF[a] = wf[a];
     double *t = c->f; c->f = c->fn; c->fn = t;
     t = c->phi; c->phi = c->phi_new; c->phi_new = t;
 }

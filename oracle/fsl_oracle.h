@@ -50,6 +50,7 @@ typedef struct {
                                  specularly (free slip) instead of bouncing back */
     int open_atmosphere;      /* 1 = bubble 0 (the gas above the pool) is held at
                                  rho_g0 (pressure outlet) instead of a fixed mass */
+    double contact_k;         /* stiffness of the sphere contact spring (0 = none) */
 } orc_config;
 
 typedef struct {
@@ -68,6 +69,11 @@ int orc_particles_set(orc_ctx *c, int n, const double *x, const double *u,
 int orc_particles_get(orc_ctx *c, int n, double *x, double *u, double *omega,
                       double *F, double *T);
 int orc_bubbles_get(orc_ctx *c, orc_bubble *out, int cap, int *n);
+/* force of the fluid on each no-slip face over the last step (momentum exchange of
+ * its half-way bounce-back links), F[3 (2 axis + side) + comp], side 0 = low face;
+ * a link beyond several faces counts for the first no-slip one; free-slip and
+ * periodic faces read 0 */
+int orc_walls_get(const orc_ctx *c, double F[18]);
 void orc_mass_get(orc_ctx *c, double *total, double *ledger);
 
 enum { ORC_FLAGS = 0, ORC_MASS = 1, ORC_PHI = 2, ORC_F = 3, ORC_BUBBLE_ID = 4, ORC_PID = 5,
@@ -100,6 +106,7 @@ int orc_split(orc_ctx *c);
 void orc_equilibrium(double rho, const double u[3], double e[19]);
 int orc_lubrication(const double x1[3], const double x2[3], const double u1[3],
                     const double u2[3], double R1, double R2, double mu, double F1[3]);
+int orc_contact(const double x1[3], const double x2[3], double R1, double R2, double k, double F1[3]);
 double orc_lambda_minus(double tau, double magic, int trt);
 
 #ifdef __cplusplus

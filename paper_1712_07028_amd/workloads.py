@@ -55,6 +55,7 @@ class Workload:
     sigma: float = 0.0  # surface tension (0: no Laplace pressure jump)
     freeslip: tuple = (0, 0, 0)  # 1: the faces of a non-periodic axis are free-slip walls
     open_atmosphere: bool = False  # the gas above the pool held at rho_g0 (pressure outlet)
+    contact_k: float = 0.0  # stiffness of the sphere contact spring (0: none)
 
     @property
     def cells(self) -> int:

@@ -42,34 +42,30 @@ def _one_sphere(x, periodic=(1, 1, 1), n=(24, 24, 24), u=(0.0, 0.0, 0.0), R=3.0)
 
 
 def test_unsupported_sphere_positions_are_rejected():
-    """Coverage, pair search and lever arms do not wrap: a centre closer than R + 1
-    to a periodic face (R + 2 on the far side), outside a walled box, or not finite
-    is refused by the particle setter, as the library refuses it."""
-    ok = _one_sphere((12.0, 12.0, 12.0))
-    o = O.Oracle(ok, n_threads=2)
-    for bad, per in [((3.5, 12.0, 12.0), (1, 1, 1)), ((12.0, 19.5, 12.0), (1, 1, 1)),
-                     ((12.0, 12.0, 24.2), (0, 0, 0)), ((-0.7, 12.0, 12.0), (0, 0, 0)),
+    """A centre outside a walled box (faces at -1/2 and n - 1/2) or not finite is
+    refused by the particle setter, as the library refuses it; on periodic axes any
+    finite centre is taken (into [0, n)), and the faces of a walled box themselves
+    are allowed."""
+    for bad, per in [((12.0, 12.0, 24.2), (0, 0, 0)), ((-0.7, 12.0, 12.0), (0, 0, 0)),
                      ((np.nan, 12.0, 12.0), (1, 1, 1)), ((12.0, np.inf, 12.0), (0, 0, 0))]:
-        w = _one_sphere(bad, periodic=per)
         with pytest.raises(ValueError):
-            O.Oracle(w, n_threads=2).close()
-    # the limits themselves are allowed: R + 1 and n - R - 2 on periodic axes, the
-    # faces at -1/2 and n - 1/2 on walled ones
-    for x, per in [((4.0, 19.0, 12.0), (1, 1, 1)), ((-0.5, 12.0, 23.5), (0, 0, 0))]:
+            O.Oracle(_one_sphere(bad, periodic=per), n_threads=2).close()
+    for x, per in [((-0.5, 12.0, 23.5), (0, 0, 0)), ((0.5, 23.9, 12.0), (1, 1, 1))]:
         O.Oracle(_one_sphere(x, periodic=per), n_threads=2).close()
+    o = O.Oracle(_one_sphere((-3.0, 27.5, 12.0), periodic=(1, 1, 0)), n_threads=2)
+    np.testing.assert_allclose(o.particles_get(1)["x"][0], [21.0, 3.5, 12.0], rtol=0, atol=1e-12)
     o.close()
 
 
-def test_sphere_reaching_a_periodic_face_sets_the_flag():
-    """A sphere driven toward a periodic face: once its centre is closer than R + 1
-    the step reports it (and keeps running)."""
-    w = _one_sphere((5.0, 12.0, 12.0), u=(-0.2, 0.0, 0.0)).replace(g=(-1e-3, 0.0, 0.0))
+def test_sphere_with_a_nan_force_sets_the_flag():
+    """A NaN population at a cell with links into a sphere makes its force, velocity
+    and centre NaN: the step reports the particle flag beside the NaN flag (a sphere
+    cannot leave a walled box otherwise: the face reverses its velocity)."""
+    w = _one_sphere((12.0, 12.0, 12.0), periodic=(0, 1, 1))
     o = O.Oracle(w, n_threads=2)
-    rc = 0
-    for _ in range(30):
-        rc = o.step(1)
-        if rc:
-            break
-    assert rc != 0 and o.error & ERR_PART
-    assert not o.error & ~(ERR_PART | ERR_ARG)
+    F = o.get(O.F)
+    assert o.get(O.FLAGS)[12, 12, 16] == O.LIQ and o.get(O.FLAGS)[12, 12, 15] == O.SOL
+    F[2, 12, 12, 16] = np.nan  # pulled by the particle link of the cell itself
+    o.set(O.F, F)
+    assert o.step(1) != 0 and o.error & ERR_PART
     o.close()

@@ -1,0 +1,138 @@
+"""Pins of the oracle's pieces for the sheared suspension (Sec. 3.1, validation of
+the particle suspension model): the force of the fluid on the moving plates, spheres
+across periodic faces (nearest images) and the contact spring.
+
+- Couette flow between plates moving at -U and +U: the tangential force on each
+  plate is the viscous stress mu 2U/n times the plate area, exactly (the steady LBM
+  profile is exactly linear), opposite on the two plates, and the normal force is
+  the pressure rho c_s^2 = 1/3 times the area.
+- Momentum balance with moving plates: the fluid's momentum changes by the body
+  force minus the forces on the faces, exactly.
+- Spheres across periodic faces: shifting the whole state by whole cells along the
+  periodic axes (spheres straddling the faces in one, not in the other) gives the
+  shifted fields, positions, velocities, forces and torques to rounding.
+- Contact: the spring law's closed form, equal and opposite, zero without overlap.
+"""
+import numpy as np
+import pytest
+
+from paper_1712_07028_amd import workloads as W
+
+C = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
+              [1, 1, 0], [1, -1, 0], [-1, 1, 0], [-1, -1, 0], [1, 0, 1], [1, 0, -1], [-1, 0, 1],
+              [-1, 0, -1], [0, 1, 1], [0, 1, -1], [0, -1, 1], [0, -1, -1]], dtype=np.float64)
+
+
+def plates(U):
+    """faces z = -1/2 and n - 1/2 moving along x with -U and +U"""
+    return [[[0, 0, 0], [0, 0, 0]], [[0, 0, 0], [0, 0, 0]], [[-U, 0, 0], [U, 0, 0]]]
+
+
+@pytest.mark.parametrize("trt,tau", [(False, 0.8), (True, 0.6), (True, 1.3)])
+def test_couette_plate_force_closed_form(orc, trt, tau):
+    n, U = (3, 2, 12), 0.01
+    w = W.Workload(name="couette", n=n, trt=trt, tau=tau, g=(0, 0, 0), zs=-1.0, steps=0,
+                   periodic=(1, 1, 0), integrate=False)
+    o = orc.Oracle(w, wall_u=plates(U))
+    o.step(40000)
+    F = o.walls()
+    mu, A = (tau - 0.5) / 3.0, n[0] * n[1]
+    shear = mu * 2.0 * U / n[2] * A
+    # the fluid below the top plate is slower: it drags the top plate back and the
+    # bottom plate forward; both feel the pressure rho c_s^2 = 1/3 outward
+    np.testing.assert_allclose(F[2, 1], [-shear, 0, A / 3.0], rtol=0, atol=1e-12 * A)
+    np.testing.assert_allclose(F[2, 0], [shear, 0, -A / 3.0], rtol=0, atol=1e-12 * A)
+    assert abs(F[2, 1, 0] / -shear - 1) < 1e-9
+    assert np.all(F[:2] == 0)  # periodic axes have no faces
+
+
+def test_momentum_balance_with_moving_plates(orc):
+    n, U, g = (6, 5, 10), 0.02, np.array([3e-6, -2e-6, 1e-6])
+    w = W.Workload(name="plates", n=n, trt=True, tau=0.7, g=tuple(g), zs=-1.0, steps=0,
+                   periodic=(1, 1, 0), integrate=False)
+    wall = plates(U)
+    wall[2][0][1] = 0.004  # the low plate also moves along y
+    o = orc.Oracle(w, wall_u=wall)
+    o.step(25)
+    P0 = np.einsum("qa,qn->a", C, o.get(orc.F).reshape(19, -1))
+    o.step(1)
+    f1 = o.get(orc.F).reshape(19, -1)
+    P1 = np.einsum("qa,qn->a", C, f1)
+    F = o.walls()
+    expect = P0 - F.sum(axis=(0, 1)) + g * f1.sum()
+    assert np.abs(F).max() > 1e-3
+    np.testing.assert_allclose(P1, expect, rtol=0, atol=1e-13)
+
+
+def spheres(shift, n):
+    # sphere 0 straddles the x and y faces, sphere 2 the y face; spheres 0 and 1 are
+    # 0.31 apart across the x face (lubrication range 2/3)
+    x = np.array([[1.3, 1.0, 5.4], [8.0, 1.2, 5.3], [5.6, 10.1, 9.7]])
+    x[:, 0] = (x[:, 0] + shift[0]) % n[0]
+    x[:, 1] = (x[:, 1] + shift[1]) % n[1]
+    return W.Particles(x=x, u=np.array([[0.01, -0.004, 0.002], [-0.006, 0.008, 0.0], [0.0, 0.0, -0.003]]),
+                       omega=np.array([[0.002, 0.0, -0.003], [0.0, 0.004, 0.001], [-0.002, 0.0, 0.0]]),
+                       R=np.array([2.6, 2.4, 2.4]), rho_p=np.array([2.0, 2.5, 3.0]))
+
+
+def test_periodic_images_shift_invariance(orc):
+    """Periodic in x and y, plates in z: the same spheres, once straddling the faces
+    and once shifted by whole cells, must step identically (the fields rolled by the
+    shift); spheres 0 and 1 are within lubrication range across the x face in the
+    first state and inside the box in the second."""
+    n, shift = (12, 11, 14), (5, 4)
+    out = []
+    for s in [(0, 0), shift]:
+        w = W.Workload(name="shift", n=n, trt=True, tau=0.6, g=(0, 0, -1e-5), zs=-1.0, steps=0,
+                       periodic=(1, 1, 0), particles=spheres(s, n), contact_k=0.01)
+        o = orc.Oracle(w, wall_u=plates(0.005))
+        assert o.error == 0
+        o.step(12)
+        assert o.error == 0
+        p = o.particles_get(3)
+        out.append(dict(p, flags=o.get(orc.FLAGS), pop=o.get(orc.F), pid=o.get(orc.PID), walls=o.walls()))
+        o.close()
+    a, b = out
+    roll = lambda v: np.roll(v, shift=shift[::-1], axis=(-2, -1))  # (y, x) of [.., z, y, x]
+    np.testing.assert_array_equal(roll(a["flags"]), b["flags"])
+    np.testing.assert_array_equal(roll(a["pid"]), b["pid"])
+    np.testing.assert_allclose(roll(a["pop"]), b["pop"], rtol=0, atol=1e-13)
+    dx = b["x"] - a["x"] - np.array([shift[0], shift[1], 0.0])
+    dx[:, 0] -= n[0] * np.round(dx[:, 0] / n[0])
+    dx[:, 1] -= n[1] * np.round(dx[:, 1] / n[1])
+    assert np.abs(dx).max() < 1e-12
+    for k in ("u", "omega", "F", "T"):
+        np.testing.assert_allclose(a[k], b[k], rtol=0, atol=1e-12 * max(1.0, np.abs(a[k]).max()))
+    np.testing.assert_allclose(a["walls"], b["walls"], rtol=0, atol=1e-12)
+    assert np.abs(a["F"]).max() > 1e-4 and np.abs(a["T"]).max() > 1e-5
+
+
+def test_spheres_cross_periodic_faces(orc):
+    """A sphere driven along x crosses the periodic face: it keeps its centre in
+    [0, n), keeps covering as many nodes (within the discretisation), and no error."""
+    n = (16, 12, 12)
+    p = W.Particles(x=np.array([[13.5, 6.0, 6.0]]), u=np.array([[0.3, 0.0, 0.0]]), omega=np.zeros((1, 3)),
+                    R=np.array([3.0]), rho_p=np.array([50.0]))
+    w = W.Workload(name="cross", n=n, trt=True, tau=0.8, g=(0, 0, 0), zs=-1.0, steps=0,
+                   periodic=(1, 1, 1), particles=p)
+    o = orc.Oracle(w)
+    counts, xs = [], []
+    for _ in range(20):
+        o.step(1)
+        counts.append(int((o.get(orc.FLAGS) == orc.SOL).sum()))
+        xs.append(o.particles_get(1)["x"][0, 0])
+    assert o.error == 0
+    assert all(0 <= v < n[0] for v in xs) and xs[-1] < 13.5  # went round
+    assert 4.0 < xs[-1] + n[0] - 13.5 < 6.0  # about 20 steps at 0.3 (slowed by the drag)
+    assert min(counts) >= 100 and max(counts) <= 130  # 4/3 pi 27 = 113 nodes on average
+
+
+def test_contact_law(orc):
+    x1, x2 = np.array([1.0, 2.0, 3.0]), np.array([4.0, 6.0, 3.0])  # |d| = 5
+    F, on = orc.contact(x1, x2, 3.0, 2.5, 0.2)
+    assert on
+    np.testing.assert_allclose(F, -0.2 * 0.5 * np.array([3.0, 4.0, 0.0]) / 5.0, rtol=1e-15, atol=0)
+    F2, _ = orc.contact(x2, x1, 2.5, 3.0, 0.2)
+    np.testing.assert_allclose(F2, -F, rtol=0, atol=1e-18)
+    assert not orc.contact(x1, x2, 2.0, 2.9, 0.2)[1]  # gap 0.1
+    assert not orc.contact(x1, x2, 3.0, 2.5, 0.0)[1]  # switched off
