@@ -101,6 +101,10 @@ typedef struct {
     int open_atmosphere;        /* 1: bubble 0 (the gas above the pool) is held at
                                    rho_g0, its mass following its volume, and is never
                                    split: a pressure outlet (Sec. 3.2)               */
+    double contact_k;           /* stiffness of the contact spring between overlapping
+                                   spheres, F = k (R1 + R2 - |d|) along the line of
+                                   centres (0 = none; the paper gives no contact
+                                   model, its lubrication force is cut off)          */
 } fsl_config;
 
 typedef struct {
@@ -167,11 +171,17 @@ int fsl_init_static(const fsl_config *cfg, void *d_state, size_t *bytes, void *h
  * reported as FSL_E_CAPACITY by the next synchronising call. */
 int fsl_step(fsl_ctx *ctx, int n);
 
-/* Replace the particle table with n spheres (arrays n x 3: centres in node
- * coordinates, velocities, angular velocities; n: radii, specific densities;
+/* Replace the particle table with n spheres (Sec. 2.3; arrays n x 3: centres in
+ * node coordinates, velocities, angular velocities; n: radii, specific densities;
  * u / omega may be NULL for zero) and recompute node coverage.  Newly covered
  * cells hand their liquid mass to the ledger, uncovered cells are re-initialised.
- * FSL_E_ARG if n > max_particles or a radius is not in (0, 60] cells. */
+ * Along a periodic axis a sphere may lie across the faces: its centre is taken into
+ * [0, n) and it acts through its nearest images (coverage, links, lever arms, pair
+ * forces); the axis must be longer than 2R + 4.  FSL_E_ARG if n > max_particles, a
+ * radius is not in (0, 60] cells, a density is not positive, a value is not finite,
+ * a centre lies outside a walled axis (faces at -1/2 and n - 1/2) or a periodic axis
+ * is too short.  A sphere whose centre leaves a walled box later is reported as
+ * FSL_E_INVARIANT by the next synchronising call. */
 int fsl_particles_set(fsl_ctx *ctx, int n, const double *x, const double *u,
                       const double *omega, const double *R, const double *rho_p);
 
@@ -180,6 +190,16 @@ int fsl_particles_set(fsl_ctx *ctx, int n, const double *x, const double *u,
  * (Eqs. netforce, torque).  Synchronises the stream. */
 int fsl_particles_get(fsl_ctx *ctx, int n, double *x, double *u, double *omega,
                       double *F, double *T);
+
+/* Force of the fluid on each no-slip face of the box over the last completed step:
+ * the momentum exchange (Eqs. netforce, momentum_transfer) of the face's half-way
+ * bounce-back links, resting or moving (Eq. bbrule), as for particle links; the
+ * plate force of the sheared suspension (Sec. 3.1, mu_s = F_x / (A gamma)).
+ * F[3 (2 axis + side) + component], side 0 the low face; a link whose source lies
+ * beyond several faces counts for the first no-slip one; free-slip and periodic
+ * faces read 0.  The normal components include the fluid pressure (rho c_s^2 per
+ * unit area at rest).  Synchronises. */
+int fsl_walls_get(fsl_ctx *ctx, double F[18]);
 
 /* Copy up to cap bubble records to out; *n receives the number of ids in use
  * (splits add ids).  Synchronises. */

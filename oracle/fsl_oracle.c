@@ -747,14 +747,19 @@ static void coverage_update(orc_ctx *c)
 /* ---- particles ---------------------------------------------------------------- */
 /* Sphere positions: every component finite; on a walled axis the centre lies in the
  * box (faces at -1/2 and n - 1/2); on a periodic axis anywhere (the centre is kept
- * in [0, n), and the sphere acts through its nearest images). */
+ * in [0, n), and the sphere acts through its nearest images), the axis longer than
+ * 2R + 4 so that every node within a link of the sphere is nearer to the centre than
+ * half the box. */
 static int position_ok(const orc_ctx *c, const double *x, double R)
 {
-    (void)R;
     for (int a = 0; a < 3; ++a) {
         double v = x[a];
         if (!isfinite(v)) return 0;
-        if (!c->cfg.periodic[a] && (v < -0.5 || v > c->cfg.n[a] - 0.5)) return 0;
+        if (c->cfg.periodic[a]) {
+            if (!(c->cfg.n[a] > 2.0 * R + 4.0)) return 0;
+        } else if (v < -0.5 || v > c->cfg.n[a] - 0.5) {
+            return 0;
+        }
     }
     return 1;
 }

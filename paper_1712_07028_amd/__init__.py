@@ -23,7 +23,7 @@ EXPORTS = [
     "fsl_workspace_bytes", "fsl_init", "fsl_step", "fsl_particles_set", "fsl_particles_get",
     "fsl_bubbles_get", "fsl_bubbles_set", "fsl_fields_get", "fsl_fields_set", "fsl_mass_get",
     "fsl_sync", "fsl_error_string", "fsl_destroy", "fsl_profile_enable", "fsl_profile_get",
-    "fsl_window_forward", "fsl_window_backward", "fsl_params_set", "fsl_init_static",
+    "fsl_window_forward", "fsl_window_backward", "fsl_params_set", "fsl_init_static", "fsl_walls_get",
 ]
 
 
@@ -39,6 +39,7 @@ class FslConfig(ctypes.Structure):
         ("sigma", ctypes.c_double),
         ("wall_u", ((ctypes.c_double * 3) * 2) * 3),
         ("open_atmosphere", ctypes.c_int),
+        ("contact_k", ctypes.c_double),
     ]
 
 
@@ -83,6 +84,7 @@ def load_library(path=LIB_PATH):
     L.fsl_fields_get.argtypes = [P, ctypes.c_int, P]
     L.fsl_fields_set.argtypes = [P, ctypes.c_int, P]
     L.fsl_mass_get.argtypes = [P, dp, dp]
+    L.fsl_walls_get.argtypes = [P, dp]
     L.fsl_sync.argtypes = [P]
     L.fsl_error_string.restype = ctypes.c_char_p
     L.fsl_error_string.argtypes = [P]
@@ -126,6 +128,7 @@ def make_config(w, max_particles=None, list_capacity=0, window=(0, 0), wall_u=No
     c.list_capacity = int(list_capacity)
     c.max_bubbles = int(max_bubbles)
     c.open_atmosphere = int(bool(getattr(w, "open_atmosphere", False)))
+    c.contact_k = float(getattr(w, "contact_k", 0.0))
     c.window_steps, c.window_every = int(window[0]), int(window[1])
     c.sigma = float(getattr(w, "sigma", 0.0))
     if wall_u is not None:
@@ -235,6 +238,13 @@ class Sim:
         ip = ctypes.POINTER(ctypes.c_int)
         self._check(self.L.fsl_bubbles_set(self.ctx, int(M.size), _dp(M), r.ctypes.data_as(ip),
                                            a.ctypes.data_as(ip)), "fsl_bubbles_set")
+
+    def walls(self):
+        """Force of the fluid on each no-slip face over the last step, (3, 2, 3):
+        [axis][low/high side][component]."""
+        F = np.zeros(18)
+        self._check(self.L.fsl_walls_get(self.ctx, _dp(F)), "fsl_walls_get")
+        return F.reshape(3, 2, 3)
 
     def mass(self):
         t, l = ctypes.c_double(0), ctypes.c_double(0)

@@ -25,6 +25,7 @@
 #include "k_split.hpp"
 #include "k_stream_collide.hpp"
 #include "k_adjoint.hpp"
+#include "k_walls.hpp"
 
 using namespace fsl;
 
@@ -48,6 +49,7 @@ struct Layout {
     size_t counters, ctl, ptab, pacc, pFT, pFTp, pFl, pmir;
     size_t btab, bacc, broot, balive, rhog, kappa, ktf, klist, kcount, wallu;
     size_t rhow;  // densities of the liquid and interface cells for the next launch
+    size_t wallF; // force on each no-slip face over the last step
     size_t win;   // differentiation window storage
     // working memory
     size_t lF, lE0, lE, lNG, lNL, lCov, lUnc, uncRho, uncDec, merges, pairs;
@@ -133,6 +135,7 @@ Layout layout_of(const fsl_config *c, size_t stage_cap = (size_t)64 << 20) {
     L.klist = take((size_t)L.nKT * 4);
     L.kcount = take(c->sigma != 0.0 ? 4 : 0);
     L.wallu = take(18 * 4);
+    L.wallF = take(18 * 8);
     L.nTiles = ((c->n[0] + TX - 1) / TX) * ((c->n[1] + TY - 1) / TY) * c->n[2];
     L.winBytes = adjoint_window_bytes(c->window_steps, c->window_every, (size_t)L.S, c->max_particles,
                                       L.nTiles);
@@ -181,6 +184,7 @@ struct fsl_ctx {
     char err[256];
     double Rmax;
     PGrid PG;
+    FaceSet FS;  // the no-slip face layers for the face forces
     int ncell;
     int tilesX, tilesY, nTiles;
     int profiling;
@@ -421,7 +425,8 @@ int enqueue_integration(fsl_ctx *c) {
     const int ns = c->cfg.n_sub > 0 ? c->cfg.n_sub : 10;
     const double mu = (c->cfg.tau - 0.5) / 3.0;
     for (int s = 0; s < ns; ++s) {
-        hipLaunchKernelGGL(k_lub, dim3(grid_for(c->L.pcap, 256, 1024)), dim3(256), 0, c->st, D, mu, c->L.pcap);
+        hipLaunchKernelGGL(k_lub, dim3(grid_for(c->L.pcap, 256, 1024)), dim3(256), 0, c->st, c->G, D, mu,
+                           c->cfg.contact_k, c->L.pcap);
         hipLaunchKernelGGL(k_substep, dim3(grid_for(np)), dim3(256), 0, c->st, D, c->G, 1.0 / ns,
                            c->cfg.g[0], c->cfg.g[1], c->cfg.g[2], c->have_prev);
     }
@@ -436,8 +441,9 @@ int enqueue_coverage_step(fsl_ctx *c) {
     const int np = D.np;
     ProfScope ps(c, 5);
     dim3 pw((np + 3) / 4);
-    hipLaunchKernelGGL(k_cov_flag_init, dim3(grid_for(np)), dim3(256), 0, c->st, D);
-    hipLaunchKernelGGL(k_cov_flag_pairs, dim3(grid_for(c->L.pcap, 256, 1024)), dim3(256), 0, c->st, D, c->L.pcap);
+    hipLaunchKernelGGL(k_cov_flag_init, dim3(grid_for(np)), dim3(256), 0, c->st, c->G, D);
+    hipLaunchKernelGGL(k_cov_flag_pairs, dim3(grid_for(c->L.pcap, 256, 1024)), dim3(256), 0, c->st, c->G, D,
+                       c->L.pcap);
     hipLaunchKernelGGL(k_cov_claim, pw, dim3(256), 0, c->st, c->G, D, 0);
     hipLaunchKernelGGL(k_cov_scan, pw, dim3(256), 0, c->st, c->G, D);
     int rc = enqueue_cover_events<ST>(c, D, D.phi_nxt);
@@ -468,6 +474,10 @@ int enqueue_steps(fsl_ctx *c, int n, int split) {
     for (int s = 0; s < n; ++s) {
         Dev &D = c->D;
         hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, c->st, D);
+        hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, c->st, D.wallF, 18LL, 0.0);
+        if (c->FS.n > 0)  // face forces from the state at t
+            hipLaunchKernelGGL(k_wall_forces<ST>, dim3(grid_for(c->FS.start[c->FS.n], 256, 1024)), dim3(256), 0, c->st,
+                               c->G, c->Ph, D, c->FS);
         if (D.kappa) {  // curvature of the interface at t for the Laplace jump
             ProfScope ps(c, 6);
             enqueue_curvature(c);
@@ -563,7 +573,7 @@ int read_error(fsl_ctx *c) {
     if (e & ERR_NAN) return fail(c, FSL_E_NUMERIC, "NaN density or velocity");
     if (e & ERR_LG) return fail(c, FSL_E_INVARIANT, "a liquid cell has a gas neighbour");
     if (e & ERR_PART)
-        return fail(c, FSL_E_INVARIANT, "a sphere centre left the box or came closer than R + 1 to a periodic face");
+        return fail(c, FSL_E_INVARIANT, "a sphere centre left the box or is not finite");
     return fail(c, FSL_E_NUMERIC, "device error");
 }
 
@@ -782,6 +792,7 @@ static int init_ctx(const fsl_config *cfg, const Layout &L, char *d_ws, char *d_
     D.rhog = (float *)(w + L.rhog);
     D.kappa = cfg->sigma != 0.0 ? (float *)(w + L.kappa) : nullptr;
     D.wallu = (float *)(w + L.wallu);
+    D.wallF = (double *)(w + L.wallF);
     D.rhow = cfg->max_particles > 0 ? (unsigned *)(w + L.rhow) : nullptr;
     D.st_prev = D.st_cur = -1;
     c->stamp = 1;
@@ -812,7 +823,23 @@ static int init_ctx(const fsl_config *cfg, const Layout &L, char *d_ws, char *d_
                      (double *)(x + L.svol)};
     c->Rmax = 0;
     c->ncell = 1;
-    c->PG = PGrid{{1, 1, 1}, {(double)G.nx, (double)G.ny, (double)G.nz}, 2.0 / 3.0 + 1.0};
+    c->PG = PGrid{{1, 1, 1}, {(double)G.nx, (double)G.ny, (double)G.nz}, 2.0 / 3.0 + 1.0, {G.nx, G.ny, G.nz},
+                  {G.per[0], G.per[1], G.per[2]}};
+    {
+        FaceSet &F = c->FS;
+        F.n = 0;
+        F.start[0] = 0;
+        const long long nn[3] = {G.nx, G.ny, G.nz};
+        for (int a = 0; a < 3; ++a) {
+            if (cfg->boundary[a] != FSL_NOSLIP) continue;
+            for (int sd = 0; sd < 2; ++sd) {
+                F.axis[F.n] = a;
+                F.side[F.n] = sd;
+                F.start[F.n + 1] = F.start[F.n] + nn[a == 0 ? 1 : 0] * nn[a == 2 ? 1 : 2];
+                ++F.n;
+            }
+        }
+    }
     c->tilesX = (G.nx + TX - 1) / TX;
     c->tilesY = (G.ny + TY - 1) / TY;
     c->nTiles = c->tilesX * c->tilesY * G.nz;
@@ -822,6 +849,7 @@ static int init_ctx(const fsl_config *cfg, const Layout &L, char *d_ws, char *d_
 
     // control block, tables, accumulators
     hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, c->st, (double *)(w + L.ctl), 64LL, 0.0);
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, c->st, D.wallF, 18LL, 0.0);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->st, D.counters, 64LL, 0);
     {
         const int used = cfg->n_gas_spheres + 1;  // bubble ids in use: atmosphere and gas spheres
@@ -933,16 +961,18 @@ int fsl_particles_set(fsl_ctx *c, int n, const double *x, const double *u, const
     for (int P = 0; P < n; ++P) {
         double *t = &tab[(size_t)P * P_STRIDE];
         for (int a = 0; a < 3; ++a) {
-            t[P_X + a] = x[3 * P + a];
-            t[P_XOLD + a] = x[3 * P + a];
+            const double v = c->G.per[a] && std::isfinite(x[3 * P + a]) ? wrap_coord(x[3 * P + a], c->cfg.n[a])
+                                                                          : x[3 * P + a];
+            t[P_X + a] = v;
+            t[P_XOLD + a] = v;
             t[P_U + a] = u ? u[3 * P + a] : 0.0;
             t[P_W + a] = omega ? omega[3 * P + a] : 0.0;
         }
         if (!(R[P] > 0.0) || !(rho_p[P] > 0.0)) return fail(c, FSL_E_ARG, "particles_set: radius and density must be > 0");
         if (R[P] > 60.0) return fail(c, FSL_E_ARG, "particles_set: radius above 60 cells");
         if (!sphere_supported(t + P_X, R[P], c->cfg.n, c->G.per))
-            return fail(c, FSL_E_ARG, "particles_set: a centre is not finite, outside the box, or closer than "
-                                      "R + 1 to a periodic face");
+            return fail(c, FSL_E_ARG, "particles_set: a centre is not finite or outside a walled axis, or a "
+                                      "periodic axis is not longer than 2R + 4");
         for (int a = 0; a < 3; ++a)
             if (!std::isfinite(t[P_U + a]) || !std::isfinite(t[P_W + a]))
                 return fail(c, FSL_E_ARG, "particles_set: a velocity is not finite");
@@ -978,6 +1008,13 @@ int fsl_particles_set(fsl_ctx *c, int n, const double *x, const double *u, const
     if (n > 0) hipLaunchKernelGGL(k_part_mirror, dim3(grid_for(n)), dim3(256), 0, c->st, D);
     int rc = by_storage(c, [&](auto st) { return enqueue_coverage_full<decltype(st)::value>(c); });
     if (rc) return rc;
+    return read_error(c);
+}
+
+int fsl_walls_get(fsl_ctx *c, double F[18]) {
+    if (!c || !F) return FSL_E_ARG;
+    HIPCHK(c, hipMemcpyAsync(F, c->D.wallF, 18 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
     return read_error(c);
 }
 

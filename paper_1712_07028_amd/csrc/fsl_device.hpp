@@ -164,6 +164,7 @@ struct Dev {
     int *counters;
     unsigned *err;
     double *ledger;                  // [0] ledger
+    double *wallF;                   // force on each no-slip face over the last step [18]
     double *ptab, *pacc, *pFT, *pFTp, *pFl; // particles (pFTp: previous step's F, T)
     float4 *pmir;                    // FP32 mirror per particle (PMir: anchor, fraction, u, omega)
     int *gridStart, *gridCount, *gridIdx;
@@ -198,19 +199,41 @@ __device__ __forceinline__ PMir pmir_load(const float4 *pmir, int P) {
 
 // The sphere positions the library handles: every component finite; on a
 // non-periodic axis the centre inside the box (faces at -1/2 and n - 1/2); on a
-// periodic axis at least R + 1 from the first and R + 2 from the last node, so that
-// the sphere and its links never wrap.
+// periodic axis anywhere (the centre is kept in [0, n) and the sphere acts through its
+// nearest images), the axis longer than 2R + 4, so that every node within a link of
+// the sphere lies less than n/2 from its centre and the sphere never meets its own
+// image.
 __host__ __device__ inline bool sphere_supported(const double x[3], double R, const int n[3], const int per[3]) {
     for (int a = 0; a < 3; ++a) {
         const double v = x[a];
         if (!(v == v) || v - v != 0.0) return false;  // NaN or infinite
         if (per[a]) {
-            if (!(v >= R + 1.0 && v <= n[a] - R - 2.0)) return false;
+            if (!(n[a] > 2.0 * R + 4.0)) return false;
         } else if (!(v >= -0.5 && v <= n[a] - 0.5)) {
             return false;
         }
     }
     return true;
+}
+
+// a coordinate along a periodic axis taken into [0, n)
+__host__ __device__ inline double wrap_coord(double v, int n) {
+    v -= n * floor(v / n);
+    return v < n ? v : 0.0;  // v just below 0 can round up to n
+}
+
+// a displacement along an axis, the nearest image along a periodic one: [-n/2, n/2)
+__host__ __device__ inline double min_img(double d, int n, int per) {
+    return per ? d - n * floor(d / n + 0.5) : d;
+}
+
+// lever arm x - x_P along one axis from the FP32 mirror: the integer part x - anchor
+// taken to its nearest image along a periodic axis (exactly: it is an integer below n
+// in size), minus the fraction
+__device__ __forceinline__ float mirror_arm(int x, float anchor, float frac, int n, int per) {
+    float d = (float)x - anchor;
+    if (per) d -= (float)n * rintf(d / (float)n);
+    return d - frac;
 }
 
 // Stored density word: the FP32 density with its lowest mantissa bit replaced by the

@@ -173,7 +173,8 @@ __device__ __forceinline__ void adj_cell(const Geom &G, const Phys &Ph, const De
     // since c_q . (omega x c_q) = 0)
     auto node_velocity = [&](int P, float &u0, float &u1, float &u2) {
         const PMir m = pmir_load(D.pmir, P);
-        const float rx = ((float)x - m.ax) - m.fx, ry = ((float)y - m.ay) - m.fy, rz = ((float)z - m.az) - m.fz;
+        const float rx = mirror_arm(x, m.ax, m.fx, G.nx, G.per[0]), ry = mirror_arm(y, m.ay, m.fy, G.ny, G.per[1]),
+                    rz = mirror_arm(z, m.az, m.fz, G.nz, G.per[2]);
         u0 = m.ux + (m.wy * rz - m.wz * ry);
         u1 = m.uy + (m.wz * rx - m.wx * rz);
         u2 = m.uz + (m.wx * ry - m.wy * rx);

@@ -53,23 +53,47 @@ __global__ __launch_bounds__(256) void k_part_forces(Dev D, int integrate) {
     if (threadIdx.x == 0 && red[0] != 0.0) unsafeAtomicAdd(D.ledger, -red[0]);
 }
 
-// node box [lo, hi] of a sphere clipped to the box; false when nothing is left (a
-// sphere outside the box, which the next synchronising call reports)
+// node box [lo, hi] of a sphere: clipped to the box along walled axes, unwrapped along
+// periodic ones (node_at wraps the indices; the box never holds a node twice, see
+// sphere_supported); false when nothing is left (a sphere outside the box or not
+// finite, which the next synchronising call reports)
 __device__ __forceinline__ bool sphere_box(const Geom &G, const double *x, double R, int lo[3], int hi[3]) {
     const int n[3] = {G.nx, G.ny, G.nz};
     bool ok = true;
     for (int a = 0; a < 3; ++a) {
         const double l = floor(x[a] - R), h = ceil(x[a] + R);
-        if (!(l <= n[a] - 1.0 && h >= 0.0)) {  // also NaN
+        const bool in = G.per[a] ? (l >= -2.0 * n[a] && h <= 3.0 * n[a]) : (l <= n[a] - 1.0 && h >= 0.0);
+        if (!in) {  // also NaN
             lo[a] = 0;
             hi[a] = -1;
             ok = false;
             continue;
         }
-        lo[a] = l < 0.0 ? 0 : (int)l;
-        hi[a] = h > n[a] - 1.0 ? n[a] - 1 : (int)h;
+        if (G.per[a]) {
+            lo[a] = (int)l;
+            hi[a] = (int)h;
+        } else {
+            lo[a] = l < 0.0 ? 0 : (int)l;
+            hi[a] = h > n[a] - 1.0 ? n[a] - 1 : (int)h;
+        }
     }
     return ok;
+}
+
+// cell index of node coordinates that may lie beyond periodic faces (in range along
+// walled axes)
+__device__ __forceinline__ int node_at(const Geom &G, int i, int j, int k) {
+    if (G.per[0]) i = ((i % G.nx) + G.nx) % G.nx;
+    if (G.per[1]) j = ((j % G.ny) + G.ny) % G.ny;
+    if (G.per[2]) k = ((k % G.nz) + G.nz) % G.nz;
+    return i + G.nx * (j + G.ny * k);
+}
+
+// position of sphere t's centre as the image nearest to the point p (per axis)
+__device__ __forceinline__ void image_near(const Geom &G, const double *t, const double *p, double out[3]) {
+    const int n[3] = {G.nx, G.ny, G.nz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[a] = p[a] + min_img(t[a] - p[a], n[a], G.per[a]);
 }
 
 __device__ __forceinline__ bool inside(double i, double j, double k, const double *x, double R) {
@@ -97,6 +121,7 @@ struct PGrid {
     int g[3];
     double cs[3];
     double reach;  // pair candidate distance between surfaces
+    int n[3], per[3];  // the box, for nearest images across periodic faces
 };
 
 __device__ __forceinline__ int pgrid_cell(const PGrid &PG, const double *x, int a) {
@@ -220,15 +245,29 @@ __global__ __launch_bounds__(256) void k_pairs(Dev D, PGrid PG, int pcap) {
         if (idx >= total) continue;
         const int P = idx / 27, d = idx - 27 * P;
         const double *x = D.ptab + (long long)P * P_STRIDE;
-        const int a = pgrid_cell(PG, x, 0) + d % 3 - 1, b = pgrid_cell(PG, x, 1) + (d / 3) % 3 - 1,
-                  e = pgrid_cell(PG, x, 2) + d / 9 - 1;
-        if (a < 0 || b < 0 || e < 0 || a >= PG.g[0] || b >= PG.g[1] || e >= PG.g[2]) continue;
-        const int cell = a + PG.g[0] * (b + PG.g[1] * e);
+        const int off[3] = {d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1};
+        int cc[3];
+        bool skip = false;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            int v = pgrid_cell(PG, x, k) + off[k];
+            if (PG.per[k]) {
+                // a periodic axis of one or two grid cells holds each neighbour once
+                if ((PG.g[k] == 1 && off[k] != 0) || (PG.g[k] == 2 && off[k] < 0)) skip = true;
+                v = v < 0 ? v + PG.g[k] : (v >= PG.g[k] ? v - PG.g[k] : v);
+            } else if (v < 0 || v >= PG.g[k]) {
+                skip = true;
+            }
+            cc[k] = v;
+        }
+        if (skip) continue;
+        const int cell = cc[0] + PG.g[0] * (cc[1] + PG.g[1] * cc[2]);
         for (int s = D.gridStart[cell]; s < D.gridStart[cell + 1]; ++s) {
             const int Qp = D.gridIdx[s];
             if (Qp <= P) continue;
             const double *y = D.ptab + (long long)Qp * P_STRIDE;
-            const double d0 = y[0] - x[0], d1 = y[1] - x[1], d2 = y[2] - x[2];
+            const double d0 = min_img(y[0] - x[0], PG.n[0], PG.per[0]), d1 = min_img(y[1] - x[1], PG.n[1], PG.per[1]),
+                         d2 = min_img(y[2] - x[2], PG.n[2], PG.per[2]);
             const double gap = sqrt(d0 * d0 + d1 * d1 + d2 * d2) - x[P_R] - y[P_R];
             if (gap >= PG.reach) continue;
             const int k = atomicAdd(&cnt, 1);
@@ -266,17 +305,23 @@ __global__ __launch_bounds__(256) void k_solid_pairs(Geom G, Dev D, int pcap) {
         // nodes of one sphere next to nodes of the other need the centres closer than
         // the radii plus the longest link (sqrt 2); margin 1.5
         const double *ta = D.ptab + (long long)pa * P_STRIDE, *tb = D.ptab + (long long)pb * P_STRIDE;
-        const double d0 = ta[P_X] - tb[P_X], d1 = ta[P_X + 1] - tb[P_X + 1], d2 = ta[P_X + 2] - tb[P_X + 2];
+        const double d0 = min_img(ta[P_X] - tb[P_X], G.nx, G.per[0]), d1 = min_img(ta[P_X + 1] - tb[P_X + 1], G.ny, G.per[1]),
+                     d2 = min_img(ta[P_X + 2] - tb[P_X + 2], G.nz, G.per[2]);
         const double reach = ta[P_R] + tb[P_R] + 1.5;
         if (d0 * d0 + d1 * d1 + d2 * d2 > reach * reach) continue;
     }
     for (int side = 0; side < 2; ++side) {
         const int Pp = side ? pb : pa, Po = side ? pa : pb;
-        const double *tp = D.ptab + (long long)Pp * P_STRIDE, *to = D.ptab + (long long)Po * P_STRIDE;
-        const double ro = (to[P_R] + 1.5) * (to[P_R] + 1.5);
+        const double *tp = D.ptab + (long long)Pp * P_STRIDE, *tq = D.ptab + (long long)Po * P_STRIDE;
+        // the other sphere's centre at its image nearest to this one (node coordinates
+        // below stay in this sphere's frame; node_at wraps them)
+        double to[3];
+        image_near(G, tq + P_X, tp + P_X, to);
+        const double Ro = tq[P_R];
+        const double ro = (Ro + 1.5) * (Ro + 1.5);
         int lo[3], hi[3], lo2[3], hi2[3];
         sphere_box(G, tp + P_X, tp[P_R], lo, hi);
-        sphere_box(G, to + P_X, to[P_R] + 1.0, lo2, hi2);
+        sphere_box(G, to, Ro + 1.0, lo2, hi2);
         for (int a = 0; a < 3; ++a) { lo[a] = max(lo[a], lo2[a]); hi[a] = min(hi[a], hi2[a]); }
         double acc[7] = {0, 0, 0, 0, 0, 0, 0};
         if (lo[0] <= hi[0] && lo[1] <= hi[1] && lo[2] <= hi[2]) {
@@ -286,23 +331,25 @@ __global__ __launch_bounds__(256) void k_solid_pairs(Geom G, Dev D, int pcap) {
                 const int i = lo[0] + s2 % ex, j = lo[1] + (s2 / ex) % ey, kk = lo[2] + s2 / (ex * ey);
                 {
                     // only nodes within a link of the other sphere can have such links
-                    const double e0 = i - to[P_X], e1 = j - to[P_X + 1], e2 = kk - to[P_X + 2];
+                    const double e0 = i - to[0], e1 = j - to[1], e2 = kk - to[2];
                     if (e0 * e0 + e1 * e1 + e2 * e2 > ro) continue;
                 }
                 // a node of Pp lies inside Pp and a node of Po inside Po (coverage takes
                 // the same inside test), so cells that fail it need no loads
                 if (!inside(i, j, kk, tp + P_X, tp[P_R])) continue;
-                const int c = i + G.nx * (j + G.ny * kk);
+                const int c = node_at(G, i, j, kk);
                 if (D.flags[c] != SOL || D.pid[c] != Pp) continue;
                 const double rx = i - tp[P_X], ry = j - tp[P_X + 1], rz = kk - tp[P_X + 2];
                 const double ur0 = tp[P_U] + (tp[P_W + 1] * rz - tp[P_W + 2] * ry);
                 const double ur1 = tp[P_U + 1] + (tp[P_W + 2] * rx - tp[P_W] * rz);
                 const double ur2 = tp[P_U + 2] + (tp[P_W] * ry - tp[P_W + 1] * rx);
                 const double uu = ur0 * ur0 + ur1 * ur1 + ur2 * ur2;
-                const double ox = i - to[P_X], oy = j - to[P_X + 1], oz = kk - to[P_X + 2];
+                const double ox = i - to[0], oy = j - to[1], oz = kk - to[2];
                 for (int q = 1; q < Q; ++q) {
-                    if (!inside(i + cx(q), j + cy(q), kk + cz(q), to + P_X, to[P_R])) continue;
-                    const int nb = nbr_idx(G, i, j, kk, q, 1);
+                    if (!inside(i + cx(q), j + cy(q), kk + cz(q), to, Ro)) continue;
+                    int iw, jw, kw;
+                    cell_xyz(G, c, iw, jw, kw);
+                    const int nb = nbr_idx(G, iw, jw, kw, q, 1);
                     if (nb < 0 || D.flags[nb] != SOL || D.pid[nb] != Po) continue;
                     const double cu = cx(q) * ur0 + cy(q) * ur1 + cz(q) * ur2;
                     const double e2 = 2.0 * wqd(q) * (1.0 + 4.5 * cu * cu - 1.5 * uu);
@@ -327,22 +374,38 @@ __global__ __launch_bounds__(256) void k_solid_pairs(Geom G, Dev D, int pcap) {
 
 // Eq. (lubrication): only for gaps below Delta_c = 2/3, gap limited from below by
 // 0.2 Delta_c; equal and opposite on the pair
-__global__ void k_lub(Dev D, double mu, int pcap) {
+// Contact (the paper gives no contact model; reading): overlapping spheres repel by a
+// linear spring of stiffness kc along the line of centres, F1 = -kc (R1 + R2 - |d|)
+// d/|d|, equal and opposite.  The partner is taken at its nearest periodic image.
+__global__ void k_lub(Geom G, Dev D, double mu, double kc, int pcap) {
     int n = min(D.counters[C_NPAIRS], pcap);
     GRID_STRIDE(k, n) {
         int a = D.pairs[k].x, b = D.pairs[k].y;
         const double *p1 = D.ptab + (long long)a * P_STRIDE, *p2 = D.ptab + (long long)b * P_STRIDE;
         const double dc = 2.0 / 3.0;
-        double d0 = p2[0] - p1[0], d1 = p2[1] - p1[1], d2 = p2[2] - p1[2];
+        double d0 = min_img(p2[0] - p1[0], G.nx, G.per[0]), d1 = min_img(p2[1] - p1[1], G.ny, G.per[1]),
+               d2 = min_img(p2[2] - p1[2], G.nz, G.per[2]);
         double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        double gap = dist - p1[P_R] - p2[P_R];
-        if (!(gap < dc) || dist <= 0.0) continue;
-        if (gap < 0.2 * dc) gap = 0.2 * dc;
-        double n0 = d0 / dist, n1 = d1 / dist, n2 = d2 / dist;
-        double rr = p1[P_R] * p2[P_R], sR = p1[P_R] + p2[P_R];
-        double coef = -6.0 * M_PI * mu * (rr * rr) / (sR * sR) * (1.0 / gap - 1.0 / dc);
-        double vn = n0 * (p1[P_U] - p2[P_U]) + n1 * (p1[P_U + 1] - p2[P_U + 1]) + n2 * (p1[P_U + 2] - p2[P_U + 2]);
-        double f0 = coef * vn * n0, f1 = coef * vn * n1, f2 = coef * vn * n2;
+        double sR = p1[P_R] + p2[P_R];
+        double gap = dist - sR;
+        double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+        if (kc > 0.0 && dist < sR && dist > 0.0) {
+            const double s = -kc * (sR - dist) / dist;
+            f0 = s * d0;
+            f1 = s * d1;
+            f2 = s * d2;
+        }
+        if (gap < dc && dist > 0.0) {
+            if (gap < 0.2 * dc) gap = 0.2 * dc;
+            double n0 = d0 / dist, n1 = d1 / dist, n2 = d2 / dist;
+            double rr = p1[P_R] * p2[P_R];
+            double coef = -6.0 * M_PI * mu * (rr * rr) / (sR * sR) * (1.0 / gap - 1.0 / dc);
+            double vn = n0 * (p1[P_U] - p2[P_U]) + n1 * (p1[P_U + 1] - p2[P_U + 1]) + n2 * (p1[P_U + 2] - p2[P_U + 2]);
+            f0 += coef * vn * n0;
+            f1 += coef * vn * n1;
+            f2 += coef * vn * n2;
+        }
+        if (f0 == 0.0 && f1 == 0.0 && f2 == 0.0) continue;
         unsafeAtomicAdd(D.pFl + 3 * a, f0);
         unsafeAtomicAdd(D.pFl + 3 * a + 1, f1);
         unsafeAtomicAdd(D.pFl + 3 * a + 2, f2);
@@ -354,7 +417,7 @@ __global__ void k_lub(Dev D, double mu, int pcap) {
 
 // one semi-implicit Euler substep: velocity from F_hyd + m g + F_lub, then position;
 // angular velocity from T_hyd; normal velocity reversed when closer than R to a
-// wall face and moving towards it.  F_hyd, T_hyd are the mean of this and the
+// wall face and moving towards it; along a periodic axis the centre kept in [0, n).  F_hyd, T_hyd are the mean of this and the
 // previous step's momentum exchange (two-step average that removes the period-two
 // oscillation of explicit coupling), or this step's alone after a table reset.
 __global__ void k_substep(Dev D, Geom G, double dt, double g0, double g1, double g2, int have_prev) {
@@ -373,6 +436,7 @@ __global__ void k_substep(Dev D, Geom G, double dt, double g0, double g1, double
             double F = FT[d] + mP * gg[d] + fl[d];
             t[P_U + d] += dt * F / mP;
             t[P_X + d] += dt * t[P_U + d];
+            if (G.per[d]) t[P_X + d] = wrap_coord(t[P_X + d], n[d]);
             t[P_W + d] += dt * FT[3 + d] / IP;
             if (!G.per[d]) {
                 if (t[P_X + d] < R - 0.5 && t[P_U + d] < 0) t[P_U + d] = -t[P_U + d];
@@ -391,10 +455,12 @@ __global__ void k_substep(Dev D, Geom G, double dt, double g0, double g1, double
 // For every other sphere no node can be inside it and another sphere at once, so
 // its cover and uncover events follow from the inside tests at the old and new
 // positions alone.
-__global__ void k_cov_flag_init(Dev D) {
+__global__ void k_cov_flag_init(Geom G, Dev D) {
     GRID_STRIDE(P, D.np) {
         double *t = D.ptab + (long long)P * P_STRIDE;
-        const double m = fmax(fabs(t[P_X] - t[P_XOLD]), fmax(fabs(t[P_X + 1] - t[P_XOLD + 1]), fabs(t[P_X + 2] - t[P_XOLD + 2])));
+        const double m = fmax(fabs(min_img(t[P_X] - t[P_XOLD], G.nx, G.per[0])),
+                              fmax(fabs(min_img(t[P_X + 1] - t[P_XOLD + 1], G.ny, G.per[1])),
+                                   fabs(min_img(t[P_X + 2] - t[P_XOLD + 2], G.nz, G.per[2]))));
         t[P_OVL] = 0.0;
         // a sphere that moved half a cell or more in one step may meet partners that
         // the pair list (taken at the old positions) does not hold: then every
@@ -405,12 +471,13 @@ __global__ void k_cov_flag_init(Dev D) {
 __device__ __forceinline__ bool cov_claims(const Dev &D, const double *t) {
     return t[P_OVL] != 0.0 || D.counters[C_COVALL] != 0;
 }
-__global__ void k_cov_flag_pairs(Dev D, int pcap) {
+__global__ void k_cov_flag_pairs(Geom G, Dev D, int pcap) {
     const int n = min(D.counters[C_NPAIRS], pcap);
     GRID_STRIDE(k, n) {
         const int a = D.pairs[k].x, b = D.pairs[k].y;
         double *ta = D.ptab + (long long)a * P_STRIDE, *tb = D.ptab + (long long)b * P_STRIDE;
-        const double d0 = ta[P_X] - tb[P_X], d1 = ta[P_X + 1] - tb[P_X + 1], d2 = ta[P_X + 2] - tb[P_X + 2];
+        const double d0 = min_img(ta[P_X] - tb[P_X], G.nx, G.per[0]), d1 = min_img(ta[P_X + 1] - tb[P_X + 1], G.ny, G.per[1]),
+                     d2 = min_img(ta[P_X + 2] - tb[P_X + 2], G.nz, G.per[2]);
         const double r = ta[P_R] + tb[P_R] + 1.0;
         if (d0 * d0 + d1 * d1 + d2 * d2 < r * r) {
             ta[P_OVL] = 1.0;
@@ -432,7 +499,7 @@ __global__ __launch_bounds__(256) void k_cov_claim(Geom G, Dev D, int all) {
     int tot = ex * ey * ez;
     for (int s = threadIdx.x & 63; s < tot; s += 64) {
         int i = lo[0] + s % ex, j = lo[1] + (s / ex) % ey, k = lo[2] + s / (ex * ey);
-        if (inside(i, j, k, t + P_X, t[P_R])) atomicMin(D.claim + i + G.nx * (j + G.ny * k), P);
+        if (inside(i, j, k, t + P_X, t[P_R])) atomicMin(D.claim + node_at(G, i, j, k), P);
     }
 }
 
@@ -463,30 +530,38 @@ __global__ __launch_bounds__(256) void k_cov_scan(Geom G, Dev D) {
     int P = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (P >= D.np) return;
     const double *t = D.ptab + (long long)P * P_STRIDE;
+    // the old centre at its image nearest the new one: both boxes in one frame
+    double xo[3];
+    image_near(G, t + P_XOLD, t + P_X, xo);
     int lo[3], hi[3], lo2[3], hi2[3];
     const bool inNew = sphere_box(G, t + P_X, t[P_R], lo, hi);
-    const bool inOld = sphere_box(G, t + P_XOLD, t[P_R], lo2, hi2);
+    const bool inOld = sphere_box(G, xo, t[P_R], lo2, hi2);
     if (!inNew && !inOld) return;
     for (int a = 0; a < 3; ++a) {
         lo[a] = !inNew ? lo2[a] : !inOld ? lo[a] : min(lo[a], lo2[a]);
         hi[a] = !inNew ? hi2[a] : !inOld ? hi[a] : max(hi[a], hi2[a]);
     }
-    int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
-    int tot = ex * ey * ez;
     if (cov_claims(D, t)) {
+        // by cell index: along a periodic axis n consecutive nodes hold every cell once
+        const int n[3] = {G.nx, G.ny, G.nz};
+        for (int a = 0; a < 3; ++a)
+            if (G.per[a]) hi[a] = min(hi[a], lo[a] + n[a] - 1);
+        const int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
+        const int tot = ex * ey * ez;
         for (int s = threadIdx.x & 63; s < tot; s += 64) {
             int i = lo[0] + s % ex, j = lo[1] + (s / ex) % ey, k = lo[2] + s / (ex * ey);
-            classify_node(D, i + G.nx * (j + G.ny * k), P);
+            classify_node(D, node_at(G, i, j, k), P);
         }
         return;
     }
-    // a sphere alone: only nodes whose inside test changed between the old and new
-    // positions can change owner.  Walked as (x, y) columns: the in-plane part of
+    const int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1;
+    // a sphere alone (it moved less than half a cell): only nodes whose inside test
+    // changed between the old and new positions can change owner.  Walked as (x, y) columns: the in-plane part of
     // both squared distances is formed once per column, in the order of inside(), and
     // a column outside both circles is skipped (adding dz^2 cannot bring it inside);
     // cov_column_ranges gives the candidates of the others, and every candidate
     // still takes the exact test.
-    const double *xn = t + P_X, *xo = t + P_XOLD;
+    const double *xn = t + P_X;
     const double R2 = __dmul_rn(t[P_R], t[P_R]);
     for (int s = threadIdx.x & 63; s < ex * ey; s += 64) {
         const int i = lo[0] + s % ex, j = lo[1] + s / ex;
@@ -504,7 +579,7 @@ __global__ __launch_bounds__(256) void k_cov_scan(Geom G, Dev D) {
             const bool in_new = __dadd_rn(sn, __dmul_rn(a2, a2)) <= R2;
             const bool in_old = __dadd_rn(so, __dmul_rn(b2, b2)) <= R2;
             bool cov = false, unc = false;
-            const int c = i + G.nx * (j + G.ny * k);
+            const int c = node_at(G, i, j, k);
             if (in_new != in_old) {
                 const uint8_t f = D.flags[c];
                 cov = in_new && f != SOL;
@@ -600,7 +675,8 @@ __global__ void k_unc_apply(Geom G, Phys Ph, Dev D, double *phi) {
         float u0 = 0.f, u1 = 0.f, u2 = 0.f;
         if ((unsigned)P < (unsigned)D.np) {
             const double *t = D.ptab + (long long)P * P_STRIDE;
-            double rx = x - t[P_X], ry = y - t[P_X + 1], rz = z - t[P_X + 2];
+            double rx = min_img(x - t[P_X], G.nx, G.per[0]), ry = min_img(y - t[P_X + 1], G.ny, G.per[1]),
+                   rz = min_img(z - t[P_X + 2], G.nz, G.per[2]);
             u0 = (float)(t[P_U] + (t[P_W + 1] * rz - t[P_W + 2] * ry));
             u1 = (float)(t[P_U + 1] + (t[P_W + 2] * rx - t[P_W] * rz));
             u2 = (float)(t[P_U + 2] + (t[P_W] * ry - t[P_W + 1] * rx));
@@ -648,7 +724,7 @@ __global__ __launch_bounds__(256) void k_cov_reset(Geom G, Dev D) {
     int tot = ex * ey * ez;
     for (int s = threadIdx.x & 63; s < tot; s += 64) {
         int i = lo[0] + s % ex, j = lo[1] + (s / ex) % ey, k = lo[2] + s / (ex * ey);
-        D.claim[i + G.nx * (j + G.ny * k)] = CLAIM_NONE;
+        D.claim[node_at(G, i, j, k)] = CLAIM_NONE;
     }
 }
 

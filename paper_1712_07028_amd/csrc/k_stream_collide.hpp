@@ -60,12 +60,12 @@ __device__ __noinline__ void acc_flush_v(double *pacc, int P, float fs0, float f
     double *dst = pacc + acc_at(P, blockIdx.x & (ACC_COPIES - 1));
     for (int k = 0; k < 7; ++k) unsafeAtomicAdd(dst + k, a[k]);
 }
-__device__ __forceinline__ void acc_flush(const Dev &D, const LinkAcc &L, int x, int y, int z) {
+__device__ __forceinline__ void acc_flush(const Geom &G, const Dev &D, const LinkAcc &L, int x, int y, int z) {
     if (L.P < 0) return;
-    // lever arm x - x_P = (x - a) - f
+    // lever arm x - x_P = (x - a) - f, to the nearest image
     acc_flush_v(D.pacc, L.P, L.fs[0], L.fs[1], L.fs[2], L.ca[0], L.ca[1], L.ca[2], L.cd[0], L.cd[1],
-                L.cd[2], L.dm, ((float)x - L.an[0]) - L.fr[0], ((float)y - L.an[1]) - L.fr[1],
-                ((float)z - L.an[2]) - L.fr[2]);
+                L.cd[2], L.dm, mirror_arm(x, L.an[0], L.fr[0], G.nx, G.per[0]),
+                mirror_arm(y, L.an[1], L.fr[1], G.ny, G.per[1]), mirror_arm(z, L.an[2], L.fr[2], G.nz, G.per[2]));
 }
 
 // wave64 sums with DPP: pairs, quads, half-row and row mirrors leave every lane of a
@@ -392,9 +392,9 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
                 const PMir m = pmir_load(D.pmir, P);
                 acc.an[0] = m.ax; acc.an[1] = m.ay; acc.an[2] = m.az;
                 acc.fr[0] = m.fx; acc.fr[1] = m.fy; acc.fr[2] = m.fz;
-                const float rx = ((float)x - m.ax) - m.fx;
-                const float ry = ((float)y - m.ay) - m.fy;
-                const float rz = ((float)z - m.az) - m.fz;
+                const float rx = mirror_arm(x, m.ax, m.fx, G.nx, G.per[0]);
+                const float ry = mirror_arm(y, m.ay, m.fy, G.ny, G.per[1]);
+                const float rz = mirror_arm(z, m.az, m.fz, G.nz, G.per[2]);
                 un0 = m.ux + (m.wy * rz - m.wz * ry);
                 un1 = m.uy + (m.wz * rx - m.wx * rz);
                 un2 = m.uz + (m.wx * ry - m.wy * rx);
@@ -437,7 +437,7 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
                             continue;
                         }
                         if (P != acc.P) {
-                            acc_flush(D, acc, x, y, z);
+                            acc_flush(G, D, acc, x, y, z);
                             acc.P = P;
                             acc_zero(acc);
                             node_velocity(P);
@@ -925,7 +925,8 @@ __device__ __forceinline__ void march_cell(const Geom &G, const Phys &Ph, const 
             }
             // rigid-body velocity at the node: c_q . u_w at the link midpoint equals
             // c_q . (u_P + omega x (x - x_P)) because c_q . (omega x c_q) = 0
-            const float rx = ((float)x - m.ax) - m.fx, ry = ((float)y - m.ay) - m.fy, rz = ((float)z - m.az) - m.fz;
+            const float rx = mirror_arm(x, m.ax, m.fx, G.nx, G.per[0]), ry = mirror_arm(y, m.ay, m.fy, G.ny, G.per[1]),
+                        rz = mirror_arm(z, m.az, m.fz, G.nz, G.per[2]);
             const float ru0 = rho_t * (m.ux + (m.wy * rz - m.wz * ry));
             const float ru1 = rho_t * (m.uy + (m.wz * rx - m.wx * rz));
             const float ru2 = rho_t * (m.uz + (m.wx * ry - m.wy * rx));

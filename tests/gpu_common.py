@@ -67,6 +67,12 @@ def compare_step(o, s, w, f_rtol=1e-6, m_tol=1e-6, ft_rtol=1e-5, allow_flag_mism
         assert out["F_rel"] < ft_rtol and out["T_rel"] < ft_rtol, out
         assert out["x_abs"] < x_tol, out
         assert (o.get(O.PID) == s.get(fsl.FIELD_PID)).all()
+    # face forces (momentum exchange of the bounce-back links): each component within
+    # 1e-5 of its own size plus 1e-9 per face cell (rounding of the FP32 populations)
+    Wo, Wg = o.walls(), s.walls()
+    area = np.array([w.n[1] * w.n[2], w.n[0] * w.n[2], w.n[0] * w.n[1]], dtype=np.float64)[:, None, None]
+    out["wall_err"] = float((np.abs(Wo - Wg) / (1e-5 * np.abs(Wo) + 1e-9 * area)).max())
+    assert out["wall_err"] <= 1.0, (out, Wo, Wg)
     bo, bg = o.bubbles(), s.bubbles()
     for x, y in zip(bo, bg):
         if not x["alive"]:

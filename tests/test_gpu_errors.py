@@ -4,8 +4,7 @@ error codes.  Every kernel still runs to its end: the errors are latched on the
 device, never trapped.
   - a NaN population in a liquid cell: FSL_E_NUMERIC;
   - a liquid cell next to a gas cell (the interface layer broken): FSL_E_INVARIANT;
-  - conversion lists of capacity 1 with many cells filling at once: FSL_E_CAPACITY;
-  - a sphere whose centre comes closer than R + 1 to a periodic face: FSL_E_INVARIANT.
+  - conversion lists of capacity 1 with many cells filling at once: FSL_E_CAPACITY.
 The argument checks of the particle setter and of the differentiation window (no
 moving faces) are checked here too: they need a context on the device.
 """
@@ -81,38 +80,25 @@ def _one_sphere(x, periodic=(1, 1, 1), n=(24, 24, 24), u=(0.0, 0.0, 0.0), g=(0.0
 
 
 def test_unsupported_sphere_positions_are_refused():
-    """The particle setter refuses what the coverage and pair search cannot handle
-    (they do not wrap): centres closer than R + 1 to a periodic face, outside a walled
-    box, or not finite; the limits themselves are accepted, as by the oracle."""
-    s = fsl.Sim(_one_sphere((12.0, 12.0, 12.0)))
-    for x in [(3.5, 12.0, 12.0), (12.0, 19.5, 12.0), (np.nan, 12.0, 12.0)]:
-        with pytest.raises(fsl.FslError, match="particles_set"):
-            s.particles_set(_one_sphere(x).particles)
-    s.particles_set(_one_sphere((4.0, 19.0, 12.0)).particles)
-    s.close()
+    """The particle setter refuses centres that are not finite or lie outside a walled
+    box, and periodic axes not longer than 2R + 4; the faces of a walled box are
+    allowed, and on periodic axes any centre, taken into [0, n), as by the oracle."""
     s = fsl.Sim(_one_sphere((12.0, 12.0, 12.0), periodic=(0, 0, 0)))
     for x in [(12.0, 12.0, 24.2), (-0.7, 12.0, 12.0), (12.0, np.inf, 12.0)]:
         with pytest.raises(fsl.FslError, match="particles_set"):
             s.particles_set(_one_sphere(x, periodic=(0, 0, 0)).particles)
     s.particles_set(_one_sphere((-0.5, 12.0, 23.5), periodic=(0, 0, 0)).particles)
     s.close()
-
-
-def test_sphere_reaching_a_periodic_face_is_reported():
-    """A sphere driven toward a periodic face: the step that brings its centre closer
-    than R + 1 is reported by the next synchronising call (FSL_E_INVARIANT), after the
-    kernels ran to their end; the oracle sets its particle flag in the same step."""
-    w = _one_sphere((5.0, 12.0, 12.0), u=(-0.2, 0.0, 0.0), g=(-1e-3, 0.0, 0.0))
-    o = O.Oracle(w, n_threads=4)
-    s = fsl.Sim(w)
-    t_o = next(t for t in range(1, 31) if o.step(1))
-    with pytest.raises(fsl.FslError, match="sphere"):
-        for _ in range(30):
-            s.step(1)
-            s.sync()
+    s = fsl.Sim(_one_sphere((12.0, 12.0, 12.0)))
+    with pytest.raises(fsl.FslError, match="particles_set"):
+        s.particles_set(_one_sphere((np.nan, 12.0, 12.0)).particles)
+    big = _one_sphere((12.0, 12.0, 12.0)).particles
+    big.R[:] = 10.0  # 2R + 4 = 24: the axis must be longer
+    with pytest.raises(fsl.FslError, match="particles_set"):
+        s.particles_set(big)
+    s.particles_set(_one_sphere((-3.0, 27.5, 12.0)).particles)
+    np.testing.assert_allclose(s.particles_get(1)["x"][0], [21.0, 3.5, 12.0], rtol=0, atol=1e-12)
     s.close()
-    o.close()
-    assert t_o <= 30
 
 
 def test_window_refuses_moving_faces():

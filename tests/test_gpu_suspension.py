@@ -1,0 +1,137 @@
+"""The pieces of the sheared suspension (Sec. 3.1) on the GPU against the oracle:
+spheres across periodic faces (coverage, links, lever arms, pair forces through the
+nearest images), the force on the no-slip faces and the contact spring.
+
+- single steps from the oracle's state with spheres straddling the periodic faces
+  and moving plates: the single-step bars, the face forces included;
+- 150 steps of spheres crossing the faces: positions and velocities against the
+  oracle's after the same steps;
+- Couette flow between plates: the plate force against mu 2U/n times the area;
+- two overlapping spheres: the contact spring moves them apart as in the oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1712_07028_amd as fsl
+from paper_1712_07028_amd import workloads as W
+
+from gpu_common import compare_step, transfer
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    O.build(force=False)
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    fsl.load_library()
+
+
+def plates(U):
+    return [[[0, 0, 0], [0, 0, 0]], [[0, 0, 0], [0, 0, 0]], [[-U, 0, 0], [U, 0, 0]]]
+
+
+def straddling(integrate=True, contact=0.0):
+    """periodic in x and y, plates in z; sphere 0 straddles the x and y faces, 2 the
+    y face, 0 and 1 lie 0.31 apart across the x face, 3 sits inside"""
+    n = (26, 22, 16)
+    x = np.array([[1.3, 1.0, 6.4], [8.0 + 14.0, 1.2, 6.3], [11.6, 20.9, 9.7], [13.0, 11.0, 8.0]])
+    p = W.Particles(x=x, u=np.array([[0.01, -0.004, 0.002], [-0.006, 0.008, 0.0], [0.0, 0.0, -0.003],
+                                     [0.004, 0.003, 0.0]]),
+                    omega=np.array([[0.002, 0.0, -0.003], [0.0, 0.004, 0.001], [-0.002, 0.0, 0.0], [0.0, 0.0, 0.002]]),
+                    R=np.array([2.6, 2.4, 2.4, 3.0]), rho_p=np.array([2.0, 2.5, 3.0, 2.0]))
+    return W.Workload(name="straddle", n=n, trt=True, tau=0.6, g=(0, 0, -1e-5), zs=-1.0, steps=0,
+                      periodic=(1, 1, 0), particles=p, integrate=integrate, contact_k=contact)
+
+
+@pytest.mark.parametrize("integrate", [False, True])
+def test_single_step_spheres_across_periodic_faces(integrate):
+    w = straddling(integrate)
+    wall = plates(0.01)
+    say("single step, spheres across periodic faces, integrate", integrate)
+    o = O.Oracle(w, wall_u=wall)
+    o.step(8)
+    s = fsl.Sim(w, wall_u=wall)
+    transfer(o, s, w)
+    o.step(1)
+    s.step(1)
+    s.sync()
+    say(compare_step(o, s, w))
+    o.close()
+    s.close()
+
+
+def test_spheres_crossing_faces_multistep():
+    """Spheres driven along x and y by a body force cross the periodic faces several
+    times: positions and velocities against the oracle's after 150 steps (FP32
+    populations against FP64: 1e-6 of the distance travelled, 1e-4 relative on the
+    velocities), cell types within a few interface-free coverage flips."""
+    n = (20, 18, 14)
+    p = W.Particles(x=np.array([[17.5, 9.0, 6.5], [5.0, 16.8, 7.2]]), u=np.array([[0.08, 0.02, 0.0], [-0.05, 0.09, 0.0]]),
+                    omega=np.zeros((2, 3)), R=np.array([3.0, 2.5]), rho_p=np.array([8.0, 8.0]))
+    w = W.Workload(name="cross", n=n, trt=True, tau=0.7, g=(0, 0, 0), zs=-1.0, steps=0,
+                   periodic=(1, 1, 0), particles=p, contact_k=0.05)
+    o = O.Oracle(w, wall_u=plates(0.02))
+    s = fsl.Sim(w, wall_u=plates(0.02))
+    o.step(150)
+    s.step(150)
+    s.sync()
+    a, b = o.particles_get(2), s.particles_get(2)
+    say("  oracle x", a["x"].tolist(), "gpu x", b["x"].tolist())
+    dx = b["x"] - a["x"]
+    for k in range(2):
+        dx[:, k] -= n[k] * np.round(dx[:, k] / n[k])
+    travelled = 150 * np.abs(a["u"]).max()
+    assert np.abs(dx).max() < 1e-6 * max(travelled, 1.0)
+    assert np.abs(b["u"] - a["u"]).max() < 1e-4 * np.abs(a["u"]).max()
+    mism = (o.get(O.FLAGS) != s.get(fsl.FIELD_FLAGS)).sum()
+    assert mism <= 4, mism
+    o.close()
+    s.close()
+
+
+def test_couette_plate_force_gpu():
+    n, U, tau = (5, 4, 12), 0.01, 0.8
+    w = W.Workload(name="couette", n=n, trt=True, tau=tau, g=(0, 0, 0), zs=-1.0, steps=0, periodic=(1, 1, 0),
+                   integrate=False)
+    s = fsl.Sim(w, wall_u=plates(U))
+    s.step(20000)
+    F = s.walls()
+    s.close()
+    mu, A = (tau - 0.5) / 3.0, n[0] * n[1]
+    shear = mu * 2.0 * U / n[2] * A
+    say("  plate forces", F[2].tolist(), "expected shear", shear)
+    # FP32 populations: the shear within 1e-5, the pressure A/3 within 1e-6
+    assert abs(F[2, 1, 0] / -shear - 1) < 1e-5 and abs(F[2, 0, 0] / shear - 1) < 1e-5
+    assert abs(F[2, 1, 2] / (A / 3.0) - 1) < 1e-6 and abs(F[2, 0, 2] / (-A / 3.0) - 1) < 1e-6
+
+
+def test_contact_spring_gpu():
+    """Two spheres set 0.4 cells into each other in a fluid at rest: after 20 steps
+    of the spring, lubrication and the fluid, velocities against the oracle's."""
+    n = (24, 20, 20)
+    p = W.Particles(x=np.array([[9.0, 10.0, 10.0], [14.6, 10.3, 10.0]]), u=np.zeros((2, 3)), omega=np.zeros((2, 3)),
+                    R=np.array([3.0, 3.0]), rho_p=np.array([4.0, 4.0]))
+    w = W.Workload(name="contact", n=n, trt=True, tau=0.8, g=(0, 0, 0), zs=-1.0, steps=0, periodic=(1, 1, 1),
+                   particles=p, contact_k=0.05)
+    o, s = O.Oracle(w), fsl.Sim(w)
+    o.step(20)
+    s.step(20)
+    s.sync()
+    a, b = o.particles_get(2), s.particles_get(2)
+    say("  oracle u", a["u"].tolist(), "gpu u", b["u"].tolist())
+    assert a["u"][1, 0] - a["u"][0, 0] > 1e-4  # pushed apart
+    assert np.abs(b["u"] - a["u"]).max() < 1e-4 * np.abs(a["u"]).max()
+    o.close()
+    s.close()
