@@ -257,6 +257,56 @@ def ceiling_bandwidth(torch, n=(512, 512, 256), reps=5):
     return round(152.0 * N / (ms / 1e3) / 1e9, 1)
 
 
+def suspension(fsl, W, torch, phis, re_p, warm, steps, every):
+    """The sheared suspension of Sec. 3.1 on the paper's box: for each volume fraction
+    the plate force F_x (the mean of the two plates' x forces, bottom minus top) is
+    sampled every `every` steps over `steps` steps after `warm` steps of start-up,
+    mu_s = <F_x> / (A gamma), against Eq. Eilers."""
+    out = {}
+    for phi in phis:
+        w, wall = W.sheared_suspension(phi, re_p=re_p)
+        n = w.n
+        U = wall[2][1][0]
+        gamma, A, mu = 2.0 * U / n[2], n[0] * n[1], (w.tau - 0.5) / 3.0
+        s = fsl.Sim(w, wall_u=wall)
+        log(f"suspension phi {phi}: {w.particles.n if w.particles is not None else 0} spheres, tau {w.tau:.4f}, "
+            f"{warm} + {steps} steps")
+        t0 = time.perf_counter()
+        done = 0
+        while done < warm:
+            k = min(50000, warm - done)
+            s.step(k)
+            s.sync()
+            done += k
+            log(f"  start-up {done}/{warm}, {time.perf_counter() - t0:.0f} s")
+        samples = []
+        done = 0
+        while done < steps:
+            s.step(every)
+            Wf = s.walls()
+            samples.append(0.5 * (Wf[2, 0, 0] - Wf[2, 1, 0]))
+            done += every
+            if done % 50000 < every:
+                log(f"  averaging {done}/{steps}, mu_s/mu so far {np.mean(samples) / (A * gamma) / mu:.4f}, "
+                    f"{time.perf_counter() - t0:.0f} s")
+        wall_s = time.perf_counter() - t0
+        s.close()
+        f = np.array(samples)
+        half = len(f) // 2
+        rel = f.mean() / (A * gamma) / mu
+        out[f"{phi:g}"] = {
+            "workload": w.name, "spheres": w.particles.n if w.particles is not None else 0, "tau": w.tau,
+            "re_p": re_p, "gamma_T": gamma * steps, "startup_steps": warm, "steps": steps, "sample_every": every,
+            "mu_s_over_mu": round(float(rel), 4),
+            # the two halves of the averaging window, as a check that the mean has settled
+            "halves": [round(float(f[:half].mean() / (A * gamma) / mu), 4),
+                       round(float(f[half:].mean() / (A * gamma) / mu), 4)],
+            "eilers": round(float(W.eilers(phi)), 4), "mlups": round(w.cells * (warm + steps) / wall_s / 1e6, 1),
+        }
+        log(f"  phi {phi}: mu_s/mu = {rel:.4f}, Eilers {W.eilers(phi):.4f}")
+    return out
+
+
 def host_threads():
     """Threads the host grants this job: OMP_NUM_THREADS when the job scheduler sets
     it, else the CPUs in the process's affinity mask."""
@@ -321,6 +371,12 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--regimes-only", action="store_true",
                     help="only the single rising bubbles of the bubble-regime table")
+    ap.add_argument("--suspension", default="",
+                    help="only the sheared suspension: comma-separated volume fractions")
+    ap.add_argument("--susp-re", type=float, default=0.1, help="particle Reynolds number of the suspension")
+    ap.add_argument("--susp-warm", type=int, default=150000, help="start-up steps of the suspension")
+    ap.add_argument("--susp-steps", type=int, default=900000, help="averaging steps (gamma T = 100 at 900,000)")
+    ap.add_argument("--susp-every", type=int, default=50, help="steps between plate-force samples")
     ap.add_argument("--traffic", default=TRAFFIC_FILE,
                     help="JSON file with measured HBM bytes per stream-collide launch")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
@@ -341,6 +397,14 @@ def main():
         print("no HIP device", file=sys.stderr)
         sys.exit(1)
     fsl.load_library()
+
+    if args.suspension:
+        from paper_1712_07028_amd import workloads as W
+
+        phis = [float(v) for v in args.suspension.split(",")]
+        res = suspension(fsl, W, torch, phis, args.susp_re, args.susp_warm, args.susp_steps, args.susp_every)
+        print(json.dumps({"sheared_suspension": res}), flush=True)
+        return
 
     if args.regimes_only:
         from paper_1712_07028_amd import workloads as W

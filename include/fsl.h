@@ -168,7 +168,12 @@ int fsl_init_static(const fsl_config *cfg, void *d_state, size_t *bytes, void *h
  * carries its root id, so merged ids are free again.  A bubble whose gas volume
  * vanishes no longer exists (its gas mass leaves).  A split that needs more live
  * bubbles than max_bubbles, or a state with more than 1024 separate gas parts, is
- * reported as FSL_E_CAPACITY by the next synchronising call. */
+ * reported as FSL_E_CAPACITY by the next synchronising call.
+ * For n >= 8 on a stream other than the null stream, once the stored densities
+ * are valid and the particle update is past its first step (and profiling is
+ * off), the steps are replayed from a HIP graph of two captured steps: the same
+ * kernels in the same order, without the per-launch cost.  Every setter, the
+ * window calls and fsl_profile_enable drop the graph. */
 int fsl_step(fsl_ctx *ctx, int n);
 
 /* Replace the particle table with n spheres (Sec. 2.3; arrays n x 3: centres in

@@ -142,13 +142,16 @@ def make_config(w, max_particles=None, list_capacity=0, window=(0, 0), wall_u=No
 class Sim:
     """One simulation state on the current HIP device.
 
-    The workspace is a torch uint8 tensor; the library runs on torch's current
-    stream.  ``w`` is a workloads.Workload.  With ``static=True`` the context comes
-    from fsl_init_static: the tensor holds the state only and the working memory is
-    the library's own array on the device."""
+    The workspace is a torch uint8 tensor.  The library runs on ``stream`` (a
+    torch.cuda.Stream), by default a stream of its own at default priority (steps
+    replay from a HIP graph only off the null stream).  ``w`` is a
+    workloads.Workload.  With ``static=True`` the context comes from
+    fsl_init_static: the tensor holds the state only and the working memory is the
+    library's own array on the device, shared by every such context on it (give them
+    one stream)."""
 
     def __init__(self, w, device="cuda", max_particles=None, list_capacity=0, window=(0, 0),
-                 set_particles=True, wall_u=None, max_bubbles=0, static=False):
+                 set_particles=True, wall_u=None, max_bubbles=0, static=False, stream=None):
         import torch
 
         self.L = load_library()
@@ -168,7 +171,7 @@ class Sim:
             if rc:
                 raise FslError(f"fsl_init_static failed ({rc}): {self.L.fsl_error_string(None).decode()}")
             self.workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
-            self.stream = torch.cuda.current_stream(self.workspace.device)
+            self.stream = stream if stream is not None else torch.cuda.Stream(device=self.workspace.device)
             rc = self.L.fsl_init_static(ctypes.byref(self.cfg), ctypes.c_void_p(self.workspace.data_ptr()),
                                         ctypes.byref(nb), ctypes.c_void_p(self.stream.cuda_stream),
                                         ctypes.byref(self.ctx))
@@ -179,7 +182,7 @@ class Sim:
             if nbytes == 0:
                 raise FslError("invalid configuration")
             self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
-            self.stream = torch.cuda.current_stream(self.workspace.device)
+            self.stream = stream if stream is not None else torch.cuda.Stream(device=self.workspace.device)
             rc = self.L.fsl_init(ctypes.byref(self.cfg), ctypes.c_void_p(self.workspace.data_ptr()),
                                  ctypes.c_size_t(nbytes), ctypes.c_void_p(self.stream.cuda_stream),
                                  ctypes.byref(self.ctx))

@@ -191,6 +191,12 @@ struct fsl_ctx {
     int have_prev;  // a previous step's hydrodynamic force exists (particle update)
     int stamp;      // stamp of the next stream-collide launch (>= 1)
     int rhow_ok;    // the density words of stamp - 1 hold the densities of the populations in A
+    // two steps captured as a HIP graph from a steady state (stored densities valid, the
+    // particle update past its first step): fsl_step replays it while lattice A is the
+    // buffer it was captured with; any setter drops it
+    hipGraphExec_t gexec;
+    void *gfA;
+    int gstate;  // 0 usable, -1 capture failed on this context (eager steps only)
     std::vector<hipEvent_t> evpool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> evlog;
     double prof_ms[NPROF];
@@ -295,10 +301,15 @@ void set_phys(fsl_ctx *c) {
 template <int ST, bool MW>
 void launch_stream_collide_mw(fsl_ctx *c, const Dev &Dv) {
     int *glist = (int *)(c->xs + c->L.glist), *ngen = Dv.counters + C_NGEN;
-    const int nChunks = (c->G.nz + NZC - 1) / NZC;
+    // planes per block: NZC, fewer on small boxes so that the launch still fills the
+    // device (at least 2,048 blocks)
+    const long long cols = (long long)c->tilesX * c->tilesY;
+    int nzc = NZC;
+    while (nzc > 2 && cols * ((c->G.nz + nzc - 1) / nzc) < 2048) nzc /= 2;
+    const int nChunks = (c->G.nz + nzc - 1) / nzc;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->st, ngen, 1LL, 0);
     hipLaunchKernelGGL((k_stream_collide<ST, MW>), dim3(c->tilesX * c->tilesY * nChunks), dim3(256), 0, c->st,
-                       c->G, c->Ph, Dv, c->tilesX, c->tilesY, nChunks, glist, ngen);
+                       c->G, c->Ph, Dv, c->tilesX, c->tilesY, nChunks, nzc, glist, ngen);
     hipLaunchKernelGGL((k_general<ST, MW>), dim3(std::min(c->nTiles, 4096)), dim3(256), 0, c->st, c->G, c->Ph, Dv,
                        c->tilesX, c->tilesY, (const int *)glist, (const int *)ngen);
 }
@@ -424,11 +435,16 @@ int enqueue_integration(fsl_ctx *c) {
     ProfScope ps(c, 4);
     const int ns = c->cfg.n_sub > 0 ? c->cfg.n_sub : 10;
     const double mu = (c->cfg.tau - 0.5) / 3.0;
-    for (int s = 0; s < ns; ++s) {
-        hipLaunchKernelGGL(k_lub, dim3(grid_for(c->L.pcap, 256, 1024)), dim3(256), 0, c->st, c->G, D, mu,
-                           c->cfg.contact_k, c->L.pcap);
-        hipLaunchKernelGGL(k_substep, dim3(grid_for(np)), dim3(256), 0, c->st, D, c->G, 1.0 / ns,
-                           c->cfg.g[0], c->cfg.g[1], c->cfg.g[2], c->have_prev);
+    if (np <= INT_BLOCK_MAX) {  // small tables: every substep in one block
+        hipLaunchKernelGGL(k_integrate_block, dim3(1), dim3(1024), 0, c->st, c->G, D, ns, mu, c->cfg.contact_k,
+                           c->L.pcap, c->cfg.g[0], c->cfg.g[1], c->cfg.g[2], c->have_prev);
+    } else {
+        for (int s = 0; s < ns; ++s) {
+            hipLaunchKernelGGL(k_lub, dim3(grid_for(c->L.pcap, 256, 1024)), dim3(256), 0, c->st, c->G, D, mu,
+                               c->cfg.contact_k, c->L.pcap);
+            hipLaunchKernelGGL(k_substep, dim3(grid_for(np)), dim3(256), 0, c->st, D, c->G, 1.0 / ns,
+                               c->cfg.g[0], c->cfg.g[1], c->cfg.g[2], c->have_prev);
+        }
     }
     c->have_prev = 1;
     LAUNCHCHK(c);
@@ -945,9 +961,70 @@ int fsl_init_static(const fsl_config *cfg, void *d_state, size_t *bytes, void *h
     return init_ctx(cfg, L, (char *)d_state, work, hip_stream, out);
 }
 
+}  // extern "C"
+
+// Steps as a HIP graph: launch-bound small boxes issue about 60 kernels per step.  Two
+// steps are captured (lattice and fill-level buffers swap back, and the stored-density
+// parities alternate as in eager steps); the host state that the capture advanced is
+// restored, and each replay advances it by two steps.
+template <int ST>
+static int capture_pair(fsl_ctx *c) {
+    const Dev D0 = c->D;
+    const int stamp0 = c->stamp, rhow0 = c->rhow_ok, prev0 = c->have_prev;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(c->st, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        c->gstate = -1;
+        (void)hipGetLastError();
+        return FSL_OK;
+    }
+    const int rc = enqueue_steps<ST>(c, 2);
+    const hipError_t e = hipStreamEndCapture(c->st, &g);
+    c->D = D0;
+    c->stamp = stamp0;
+    c->rhow_ok = rhow0;
+    c->have_prev = prev0;
+    if (rc != FSL_OK || e != hipSuccess || !g || hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+        c->gexec = nullptr;
+        c->gstate = -1;
+        (void)hipGetLastError();
+    } else {
+        c->gfA = c->D.fA;
+    }
+    if (g) (void)hipGraphDestroy(g);
+    return FSL_OK;
+}
+
+static void drop_graph(fsl_ctx *c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+}
+
+extern "C" {
+
 int fsl_step(fsl_ctx *c, int n) {
     if (!c || n < 0) return FSL_E_ARG;
-    return by_storage(c, [&](auto st) { return enqueue_steps<decltype(st)::value>(c, n); });
+    return by_storage(c, [&](auto st) -> int {
+        constexpr int ST = decltype(st)::value;
+        while (n > 0) {
+            const bool steady = n >= 8 && c->gstate == 0 && c->st != nullptr && !c->profiling && c->rhow_ok &&
+                                (c->D.np == 0 || !c->cfg.integrate || c->have_prev) && c->stamp < (1 << 29);
+            if (steady && !c->gexec) {
+                const int rc = capture_pair<ST>(c);
+                if (rc) return rc;
+            }
+            if (steady && c->gexec && c->D.fA == c->gfA) {
+                const int k = n / 2;
+                for (int i = 0; i < k; ++i) HIPCHK(c, hipGraphLaunch(c->gexec, c->st));
+                c->stamp += 2 * k;
+                n -= 2 * k;
+                continue;
+            }
+            const int rc = enqueue_steps<ST>(c, 1);
+            if (rc) return rc;
+            --n;
+        }
+        return FSL_OK;
+    });
 }
 
 int fsl_particles_set(fsl_ctx *c, int n, const double *x, const double *u, const double *omega,
@@ -955,6 +1032,7 @@ int fsl_particles_set(fsl_ctx *c, int n, const double *x, const double *u, const
     if (!c || n < 0 || n > c->cfg.max_particles || (n > 0 && (!x || !R || !rho_p)))
         return fail(c, FSL_E_ARG, "particles_set: bad arguments");
     c->rhow_ok = 0;  // the stored densities may not match the populations any more
+    drop_graph(c);
     c->adj.ready = 0;
     std::vector<double> tab((size_t)std::max(n, 1) * P_STRIDE, 0.0);
     double Rmax = 0;
@@ -1071,6 +1149,7 @@ int fsl_bubbles_get(fsl_ctx *c, fsl_bubble *out, int cap, int *n) {
 int fsl_bubbles_set(fsl_ctx *c, int n, const double *M, const int *root, const int *alive) {
     if (!c || n < 1 || n > c->L.maxB || !M || !root || !alive) return fail(c, FSL_E_ARG, "bubbles_set: bad arguments");
     c->rhow_ok = 0;  // the stored densities may not match the populations any more
+    drop_graph(c);
     for (int b = 0; b < n; ++b)
         if (root[b] < 0 || root[b] >= n) return fail(c, FSL_E_ARG, "bubbles_set: bad root");
     // ids from n on become unused: no mass, their own root, not alive
@@ -1162,6 +1241,7 @@ int fsl_fields_get(fsl_ctx *c, int field, void *host) {
 int fsl_fields_set(fsl_ctx *c, int field, const void *host) {
     if (!c || !host) return FSL_E_ARG;
     c->rhow_ok = 0;  // the stored densities may not match the populations any more
+    drop_graph(c);
     c->adj.ready = 0;
     const long long N = c->G.N;
     Dev &D = c->D;
@@ -1234,6 +1314,7 @@ const char *fsl_error_string(const fsl_ctx *c) {
 void fsl_destroy(fsl_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->st);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     for (auto &e : c->evlog) {
         (void)hipEventDestroy(e.second.first);
         (void)hipEventDestroy(e.second.second);
@@ -1244,6 +1325,7 @@ void fsl_destroy(fsl_ctx *c) {
 
 int fsl_profile_enable(fsl_ctx *c, int on) {
     if (!c) return FSL_E_ARG;
+    drop_graph(c);
     c->profiling = on ? 1 : 0;
     return FSL_OK;
 }
@@ -1273,18 +1355,21 @@ int fsl_profile_get(fsl_ctx *c, double *ms, long long *count, int n) {
 int fsl_window_forward(fsl_ctx *c, int T, int k, double *J) {
     if (!c) return FSL_E_ARG;
     c->rhow_ok = 0;  // the stored densities may not match the populations any more
+    drop_graph(c);
     return window_forward(c, T, k, J);
 }
 
 int fsl_window_backward(fsl_ctx *c, double dJ, double *dJ_dtau, double dJ_dg[3]) {
     if (!c) return FSL_E_ARG;
     c->rhow_ok = 0;  // the stored densities may not match the populations any more
+    drop_graph(c);
     return window_backward(c, dJ, dJ_dtau, dJ_dg);
 }
 
 int fsl_params_set(fsl_ctx *c, double tau, const double g[3]) {
     if (!c || !(tau > 0.5) || !g) return fail(c, FSL_E_ARG, "params_set: tau must exceed 1/2");
     c->rhow_ok = 0;  // the stored densities may not match the populations any more
+    drop_graph(c);
     if (c->cfg.collision == FSL_TRT && !(tau != 0.5)) return fail(c, FSL_E_ARG, "params_set: bad tau");
     c->cfg.tau = tau;
     for (int a = 0; a < 3; ++a) c->cfg.g[a] = g[a];

@@ -372,79 +372,142 @@ __global__ __launch_bounds__(256) void k_solid_pairs(Geom G, Dev D, int pcap) {
     }
 }
 
-// Eq. (lubrication): only for gaps below Delta_c = 2/3, gap limited from below by
-// 0.2 Delta_c; equal and opposite on the pair
-// Contact (the paper gives no contact model; reading): overlapping spheres repel by a
-// linear spring of stiffness kc along the line of centres, F1 = -kc (R1 + R2 - |d|)
-// d/|d|, equal and opposite.  The partner is taken at its nearest periodic image.
+// Pair force of one candidate pair (x, u of each sphere; f: force on sphere 1, sphere 2
+// takes -f).  Contact (the paper gives no contact model; reading): overlapping spheres
+// repel by a linear spring of stiffness kc along the line of centres, -kc (R1 + R2 -
+// |d|) d/|d|.  Eq. (lubrication): only for gaps below Delta_c = 2/3, the gap limited
+// from below by 0.2 Delta_c.  The partner is taken at its nearest periodic image.
+// Returns false when there is no force.
+__device__ __forceinline__ bool pair_force(const Geom &G, const double *x1, const double *u1, double R1,
+                                           const double *x2, const double *u2, double R2, double mu, double kc,
+                                           double f[3]) {
+    const double dc = 2.0 / 3.0;
+    const double d0 = min_img(x2[0] - x1[0], G.nx, G.per[0]), d1 = min_img(x2[1] - x1[1], G.ny, G.per[1]),
+                 d2 = min_img(x2[2] - x1[2], G.nz, G.per[2]);
+    const double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    const double sR = R1 + R2;
+    double gap = dist - sR;
+    f[0] = f[1] = f[2] = 0.0;
+    if (kc > 0.0 && dist < sR && dist > 0.0) {
+        const double s = -kc * (sR - dist) / dist;
+        f[0] = s * d0;
+        f[1] = s * d1;
+        f[2] = s * d2;
+    }
+    if (gap < dc && dist > 0.0) {
+        if (gap < 0.2 * dc) gap = 0.2 * dc;
+        const double n0 = d0 / dist, n1 = d1 / dist, n2 = d2 / dist;
+        const double rr = R1 * R2;
+        const double coef = -6.0 * M_PI * mu * (rr * rr) / (sR * sR) * (1.0 / gap - 1.0 / dc);
+        const double vn = n0 * (u1[0] - u2[0]) + n1 * (u1[1] - u2[1]) + n2 * (u1[2] - u2[2]);
+        f[0] += coef * vn * n0;
+        f[1] += coef * vn * n1;
+        f[2] += coef * vn * n2;
+    }
+    return f[0] != 0.0 || f[1] != 0.0 || f[2] != 0.0;
+}
+
 __global__ void k_lub(Geom G, Dev D, double mu, double kc, int pcap) {
     int n = min(D.counters[C_NPAIRS], pcap);
     GRID_STRIDE(k, n) {
-        int a = D.pairs[k].x, b = D.pairs[k].y;
+        const int a = D.pairs[k].x, b = D.pairs[k].y;
         const double *p1 = D.ptab + (long long)a * P_STRIDE, *p2 = D.ptab + (long long)b * P_STRIDE;
-        const double dc = 2.0 / 3.0;
-        double d0 = min_img(p2[0] - p1[0], G.nx, G.per[0]), d1 = min_img(p2[1] - p1[1], G.ny, G.per[1]),
-               d2 = min_img(p2[2] - p1[2], G.nz, G.per[2]);
-        double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        double sR = p1[P_R] + p2[P_R];
-        double gap = dist - sR;
-        double f0 = 0.0, f1 = 0.0, f2 = 0.0;
-        if (kc > 0.0 && dist < sR && dist > 0.0) {
-            const double s = -kc * (sR - dist) / dist;
-            f0 = s * d0;
-            f1 = s * d1;
-            f2 = s * d2;
-        }
-        if (gap < dc && dist > 0.0) {
-            if (gap < 0.2 * dc) gap = 0.2 * dc;
-            double n0 = d0 / dist, n1 = d1 / dist, n2 = d2 / dist;
-            double rr = p1[P_R] * p2[P_R];
-            double coef = -6.0 * M_PI * mu * (rr * rr) / (sR * sR) * (1.0 / gap - 1.0 / dc);
-            double vn = n0 * (p1[P_U] - p2[P_U]) + n1 * (p1[P_U + 1] - p2[P_U + 1]) + n2 * (p1[P_U + 2] - p2[P_U + 2]);
-            f0 += coef * vn * n0;
-            f1 += coef * vn * n1;
-            f2 += coef * vn * n2;
-        }
-        if (f0 == 0.0 && f1 == 0.0 && f2 == 0.0) continue;
-        unsafeAtomicAdd(D.pFl + 3 * a, f0);
-        unsafeAtomicAdd(D.pFl + 3 * a + 1, f1);
-        unsafeAtomicAdd(D.pFl + 3 * a + 2, f2);
-        unsafeAtomicAdd(D.pFl + 3 * b, -f0);
-        unsafeAtomicAdd(D.pFl + 3 * b + 1, -f1);
-        unsafeAtomicAdd(D.pFl + 3 * b + 2, -f2);
+        double f[3];
+        if (!pair_force(G, p1 + P_X, p1 + P_U, p1[P_R], p2 + P_X, p2 + P_U, p2[P_R], mu, kc, f)) continue;
+        unsafeAtomicAdd(D.pFl + 3 * a, f[0]);
+        unsafeAtomicAdd(D.pFl + 3 * a + 1, f[1]);
+        unsafeAtomicAdd(D.pFl + 3 * a + 2, f[2]);
+        unsafeAtomicAdd(D.pFl + 3 * b, -f[0]);
+        unsafeAtomicAdd(D.pFl + 3 * b + 1, -f[1]);
+        unsafeAtomicAdd(D.pFl + 3 * b + 2, -f[2]);
     }
 }
 
-// one semi-implicit Euler substep: velocity from F_hyd + m g + F_lub, then position;
-// angular velocity from T_hyd; normal velocity reversed when closer than R to a
-// wall face and moving towards it; along a periodic axis the centre kept in [0, n).  F_hyd, T_hyd are the mean of this and the
-// previous step's momentum exchange (two-step average that removes the period-two
-// oscillation of explicit coupling), or this step's alone after a table reset.
+// one semi-implicit Euler substep of particle t (x, u, omega may live elsewhere than
+// the table): velocity from F_hyd + m g + F_pair, then position; angular velocity from
+// T_hyd; normal velocity reversed when closer than R to a wall face and moving towards
+// it; along a periodic axis the centre kept in [0, n).  F_hyd, T_hyd are the mean of
+// this and the previous step's momentum exchange (two-step average that removes the
+// period-two oscillation of explicit coupling), or this step's alone after a reset.
+__device__ __forceinline__ void substep_one(const Geom &G, const Dev &D, int P, double *x, double *u, double *w,
+                                            double *fl, double dt, const double gg[3], int have_prev) {
+    const double *t = D.ptab + (long long)P * P_STRIDE;
+    const double *FTn = D.pFT + (long long)P * 6, *FTp = D.pFTp + (long long)P * 6;
+    const double R = t[P_R];
+    const double mP = t[P_RHO] * (4.0 / 3.0) * M_PI * R * R * R;
+    const double IP = 0.4 * mP * R * R;
+    const int n[3] = {G.nx, G.ny, G.nz};
+    for (int d = 0; d < 3; ++d) {
+        const double Fh = have_prev ? 0.5 * (FTn[d] + FTp[d]) : FTn[d];
+        const double Th = have_prev ? 0.5 * (FTn[3 + d] + FTp[3 + d]) : FTn[3 + d];
+        const double F = Fh + mP * gg[d] + fl[d];
+        u[d] += dt * F / mP;
+        x[d] += dt * u[d];
+        if (G.per[d]) x[d] = wrap_coord(x[d], n[d]);
+        w[d] += dt * Th / IP;
+        if (!G.per[d]) {
+            if (x[d] < R - 0.5 && u[d] < 0) u[d] = -u[d];
+            if (x[d] > n[d] - 0.5 - R && u[d] > 0) u[d] = -u[d];
+        }
+        fl[d] = 0.0;
+    }
+}
+
 __global__ void k_substep(Dev D, Geom G, double dt, double g0, double g1, double g2, int have_prev) {
     GRID_STRIDE(P, D.np) {
         double *t = D.ptab + (long long)P * P_STRIDE;
-        const double *FTn = D.pFT + (long long)P * 6, *FTp = D.pFTp + (long long)P * 6;
-        double FT[6];
-        for (int k = 0; k < 6; ++k) FT[k] = have_prev ? 0.5 * (FTn[k] + FTp[k]) : FTn[k];
-        double *fl = D.pFl + (long long)P * 3;
-        const double R = t[P_R];
-        const double mP = t[P_RHO] * (4.0 / 3.0) * M_PI * R * R * R;
-        const double IP = 0.4 * mP * R * R;
         const double gg[3] = {g0, g1, g2};
+        substep_one(G, D, P, t + P_X, t + P_U, t + P_W, D.pFl + (long long)P * 3, dt, gg, have_prev);
         const int n[3] = {G.nx, G.ny, G.nz};
+        if (!sphere_supported(t + P_X, t[P_R], n, G.per)) atomicOr(D.err, ERR_PART);
+    }
+}
+
+// All ns substeps in one block for small tables (np <= INT_BLOCK_MAX): centres,
+// velocities and pair forces in LDS, so that a substep's pair phase sees the
+// previous substep's update after a barrier; the same arithmetic as k_lub and
+// k_substep, which take one launch each per substep.
+constexpr int INT_BLOCK_MAX = 512;
+__global__ __launch_bounds__(1024) void k_integrate_block(Geom G, Dev D, int ns, double mu, double kc, int pcap,
+                                                          double g0, double g1, double g2, int have_prev) {
+    __shared__ double sx[INT_BLOCK_MAX][3], su[INT_BLOCK_MAX][3], sf[INT_BLOCK_MAX][3];
+    const int np = D.np, npair = min(D.counters[C_NPAIRS], pcap);
+    for (int P = threadIdx.x; P < np; P += blockDim.x) {
+        const double *t = D.ptab + (long long)P * P_STRIDE;
         for (int d = 0; d < 3; ++d) {
-            double F = FT[d] + mP * gg[d] + fl[d];
-            t[P_U + d] += dt * F / mP;
-            t[P_X + d] += dt * t[P_U + d];
-            if (G.per[d]) t[P_X + d] = wrap_coord(t[P_X + d], n[d]);
-            t[P_W + d] += dt * FT[3 + d] / IP;
-            if (!G.per[d]) {
-                if (t[P_X + d] < R - 0.5 && t[P_U + d] < 0) t[P_U + d] = -t[P_U + d];
-                if (t[P_X + d] > n[d] - 0.5 - R && t[P_U + d] > 0) t[P_U + d] = -t[P_U + d];
-            }
-            fl[d] = 0.0;
+            sx[P][d] = t[P_X + d];
+            su[P][d] = t[P_U + d];
+            sf[P][d] = D.pFl[3 * P + d];
         }
-        if (!sphere_supported(t + P_X, R, n, G.per)) atomicOr(D.err, ERR_PART);
+    }
+    __syncthreads();
+    const double dt = 1.0 / ns, gg[3] = {g0, g1, g2};
+    for (int s = 0; s < ns; ++s) {
+        for (int k = threadIdx.x; k < npair; k += blockDim.x) {
+            const int a = D.pairs[k].x, b = D.pairs[k].y;
+            double f[3];
+            if (!pair_force(G, sx[a], su[a], D.ptab[(long long)a * P_STRIDE + P_R], sx[b], su[b],
+                            D.ptab[(long long)b * P_STRIDE + P_R], mu, kc, f))
+                continue;
+            for (int d = 0; d < 3; ++d) {
+                atomicAdd(&sf[a][d], f[d]);
+                atomicAdd(&sf[b][d], -f[d]);
+            }
+        }
+        __syncthreads();
+        for (int P = threadIdx.x; P < np; P += blockDim.x)
+            substep_one(G, D, P, sx[P], su[P], D.ptab + (long long)P * P_STRIDE + P_W, sf[P], dt, gg, have_prev);
+        __syncthreads();
+    }
+    for (int P = threadIdx.x; P < np; P += blockDim.x) {
+        double *t = D.ptab + (long long)P * P_STRIDE;
+        for (int d = 0; d < 3; ++d) {
+            t[P_X + d] = sx[P][d];
+            t[P_U + d] = su[P][d];
+            D.pFl[3 * P + d] = 0.0;
+        }
+        const int n[3] = {G.nx, G.ny, G.nz};
+        if (!sphere_supported(t + P_X, t[P_R], n, G.per)) atomicOr(D.err, ERR_PART);
     }
 }
 

@@ -585,7 +585,8 @@ __device__ __forceinline__ int kconst(int q) {
 }
 
 // ---- the marching kernel ------------------------------------------------------------
-// A block takes a 64 x 4 column of cells through NZC consecutive planes.  Each wave
+// A block takes a 64 x 4 column of cells through nzc consecutive planes (NZC, fewer on
+// small boxes).  Each wave
 // takes one row of the column; each lane one x.  The cell types and the particle ids
 // of the particle nodes of four planes (z-1 .. z+2) stay in LDS rings, refilled one
 // plane ahead from loads issued a plane earlier, so that a plane costs one barrier.
@@ -1008,7 +1009,7 @@ __device__ __forceinline__ void march_cell(const Geom &G, const Phys &Ph, const 
 }
 
 // tiles of the march: blocks go to the eight XCDs round-robin; each XCD takes whole
-// chunks of NZC planes (every eighth chunk), all tile columns of a chunk in turn
+// chunks of planes (every eighth chunk), all tile columns of a chunk in turn
 __device__ __forceinline__ void march_of_block(int b, int nCols, int nChunks, int &col, int &chunk) {
     if (nChunks % 8 == 0) {
         const int i = b >> 3;
@@ -1021,17 +1022,17 @@ __device__ __forceinline__ void march_of_block(int b, int nCols, int nChunks, in
 }
 
 // The fused step (Eqs. LBE1, LBE2, bbrule, netforce, torque, momentum_transfer) for the
-// liquid cells of a 64 x 4 column through NZC planes.  Interface cells and liquid
+// liquid cells of a 64 x 4 column through nzc planes.  Interface cells and liquid
 // cells next to gas or a moving or slipping face are left to k_general: each plane of
 // the column that holds one is appended to the list gen.
 template <int ST, bool MW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE_MARCH))) void k_stream_collide(
-    Geom G, Phys Ph, Dev D, int tilesX, int tilesY, int nChunks, int *gen, int *ngen) {
+    Geom G, Phys Ph, Dev D, int tilesX, int tilesY, int nChunks, int nzc, int *gen, int *ngen) {
     __shared__ MarchLds L;
     int col, chunk;
     march_of_block(blockIdx.x, tilesX * tilesY, nChunks, col, chunk);
     const int x0 = (col % tilesX) * TX, y0 = (col / tilesX) * TY;
-    const int zs = chunk * NZC, ze = min(zs + NZC, G.nz);
+    const int zs = chunk * nzc, ze = min(zs + nzc, G.nz);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int lx = lane, ly = wv;
     const int x = x0 + lx, y = y0 + ly;

@@ -191,6 +191,76 @@ def layers_of(w: Workload, z0: int, z1: int, spin_seed: int | None = None,
                      gas_spheres=gas)
 
 
+def periodic_rsa(n_target, R, box, seed=0, gap=0.2, z_margin=1.0, max_draws=None, batch=2048):
+    """Random sequential addition of equal spheres in a box periodic along x and y
+    and walled along z: candidate centres uniform in [0, n) along x and y and in
+    [R + z_margin - 1/2, nz - 1/2 - R - z_margin] along z, rejected when the surface
+    gap to an accepted sphere, through the nearest periodic image, is below gap.
+    Candidates are drawn in batches from numpy.random.Generator(PCG64(seed)) and
+    tested in draw order, so the result equals a one-by-one addition."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    L = np.array(box[:2], dtype=np.float64)
+    zlo, zhi = R + z_margin - 0.5, box[2] - 0.5 - R - z_margin
+    dmin2 = (2 * R + gap) ** 2
+    acc = np.empty((0, 3))
+    max_draws = max_draws or 20000 * n_target + 100000
+    draws = 0
+
+    def sep2(a, b):
+        d = a[:, None, :] - b[None, :, :]
+        d[..., :2] -= L * np.round(d[..., :2] / L)
+        return (d * d).sum(axis=2)
+
+    while acc.shape[0] < n_target and draws < max_draws:
+        u = rng.random((batch, 3))
+        cand = np.column_stack([u[:, 0] * L[0], u[:, 1] * L[1], zlo + (zhi - zlo) * u[:, 2]])
+        draws += batch
+        ok = np.ones(batch, dtype=bool) if acc.shape[0] == 0 else (sep2(cand, acc) >= dmin2).all(axis=1)
+        sub = cand[ok]
+        if sub.shape[0] == 0:
+            continue
+        clash = sep2(sub, sub) < dmin2
+        keep = []
+        for k in range(sub.shape[0]):
+            if len(keep) == n_target - acc.shape[0]:
+                break
+            if not any(clash[k, j] for j in keep):
+                keep.append(k)
+        acc = np.vstack([acc, sub[keep]])
+    if acc.shape[0] < n_target:
+        raise ValueError(f"placed only {acc.shape[0]} of {n_target} spheres")
+    return acc
+
+
+def sheared_suspension(phi, re_p=0.1, n=(114, 116, 180), R=8.0, rho_s=8.0, U=0.01, seed=11, contact_k=0.5):
+    """The sheared suspension of Sec. 3.1 (validation of the particle suspension
+    model): a box periodic along x and y between plates at z = -1/2 and nz - 1/2
+    moving along x with -U and +U, flow and spheres initially at rest, no gravity,
+    N = phi V / V_P spheres of radius R and specific density rho_s at random
+    non-overlapping positions.  The particle Reynolds number Re_P = gamma (2R)^2 / mu,
+    gamma = 2U / nz, fixes tau (mu = (tau - 1/2) / 3).  Returns the workload and
+    the face velocities."""
+    V = n[0] * n[1] * n[2]
+    VP = 4.0 / 3.0 * np.pi * R ** 3
+    N = int(round(phi * V / VP))
+    gamma = 2.0 * U / n[2]
+    mu = gamma * (2 * R) ** 2 / re_p
+    tau = 0.5 + 3.0 * mu
+    x = periodic_rsa(N, R, n, seed=seed) if N else np.zeros((0, 3))
+    p = Particles(x=x, u=np.zeros_like(x), omega=np.zeros_like(x), R=np.full(N, float(R)),
+                  rho_p=np.full(N, float(rho_s))) if N else None
+    w = Workload(name=f"suspension{n[0]}x{n[1]}x{n[2]}_phi{phi:g}_re{re_p:g}", n=tuple(n), trt=True,
+                 tau=float(tau), g=(0.0, 0.0, 0.0), zs=-1.0, steps=0, periodic=(1, 1, 0), particles=p,
+                 contact_k=contact_k if N else 0.0)
+    wall = [[[0.0] * 3, [0.0] * 3], [[0.0] * 3, [0.0] * 3], [[-U, 0.0, 0.0], [U, 0.0, 0.0]]]
+    return w, wall
+
+
+def eilers(phi, phi_max=0.63):
+    """Eq. Eilers: relative viscosity of a suspension of spheres at volume fraction phi."""
+    return (1.0 + 1.25 * phi / (1.0 - phi / phi_max)) ** 2
+
+
 def adjoint_window(n=64, n_particles=20):
     """Fully liquid periodic n^3 window, 20 spheres R=4 moving with U(-0.01,0.01)^3."""
     parts = particle_bed(n_particles, 4.0, (n, n, n), -1.0, None, seed=5, vel_range=0.01)

@@ -135,3 +135,28 @@ def test_contact_spring_gpu():
     assert np.abs(b["u"] - a["u"]).max() < 1e-4 * np.abs(a["u"]).max()
     o.close()
     s.close()
+
+
+def test_reduced_sheared_suspension_plate_force():
+    """The sheared suspension on a reduced box (40 x 36 x 32, 26 spheres of R = 4 at
+    Phi = 0.15, plates at +-0.01, Re_P = 0.5, contact on): the plate force of every
+    step over 500 steps against the oracle's, and its mean over the last 250 steps
+    (the quantity mu_s = F_x / (A gamma) is taken from) within 1e-4."""
+    w, wall = W.sheared_suspension(0.15, re_p=0.5, n=(40, 36, 32), R=4.0, seed=3)
+    assert w.particles.n == 26
+    o, s = O.Oracle(w, wall_u=wall), fsl.Sim(w, wall_u=wall)
+    fo, fg = [], []
+    for t in range(500):
+        o.step(1)
+        s.step(1)
+        Wo, Wg = o.walls(), s.walls()
+        fo.append(0.5 * (Wo[2, 0, 0] - Wo[2, 1, 0]))
+        fg.append(0.5 * (Wg[2, 0, 0] - Wg[2, 1, 0]))
+    fo, fg = np.array(fo), np.array(fg)
+    say("  plate force, oracle mean", fo[250:].mean(), "gpu mean", fg[250:].mean(),
+        "max step difference", np.abs(fo - fg).max())
+    assert np.abs(fo - fg).max() < 1e-4 * np.abs(fo).max()
+    assert abs(fg[250:].mean() / fo[250:].mean() - 1) < 1e-4
+    np.testing.assert_array_equal(o.get(O.FLAGS), s.get(fsl.FIELD_FLAGS))
+    o.close()
+    s.close()

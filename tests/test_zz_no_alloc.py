@@ -54,9 +54,12 @@ def compare(a, b, tol):
 def test_static_contexts_match_full_workspace():
     wa, wb = bed(), W.bubble_column_small()
     assert wb.cells < wa.cells  # the second context is the smaller input
+    import torch
+
     ref_a, ref_b = fsl.Sim(wa), fsl.Sim(wb)
-    st_a = fsl.Sim(wa, static=True)
-    st_b = fsl.Sim(wb, static=True)
+    shared = torch.cuda.Stream()  # calls on contexts that share the array must not overlap
+    st_a = fsl.Sim(wa, static=True, stream=shared)
+    st_b = fsl.Sim(wb, static=True, stream=shared)
     assert st_a.workspace.numel() < ref_a.workspace.numel()
     for _ in range(3):
         for ref, st in ((ref_a, st_a), (ref_b, st_b)):
