@@ -298,7 +298,7 @@ void set_phys(fsl_ctx *c) {
 // one lattice update of every cell: the marching pass over the liquid cells, then the
 // general path over the tiles it listed (interface cells, liquid cells next to gas or
 // a moving or slipping face)
-template <int ST, bool MW>
+template <int ST, bool MW, bool PER>
 void launch_stream_collide_mw(fsl_ctx *c, const Dev &Dv) {
     int *glist = (int *)(c->xs + c->L.glist), *ngen = Dv.counters + C_NGEN;
     // planes per block: NZC, fewer on small boxes so that the launch still fills the
@@ -308,15 +308,23 @@ void launch_stream_collide_mw(fsl_ctx *c, const Dev &Dv) {
     while (nzc > 2 && cols * ((c->G.nz + nzc - 1) / nzc) < 2048) nzc /= 2;
     const int nChunks = (c->G.nz + nzc - 1) / nzc;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->st, ngen, 1LL, 0);
-    hipLaunchKernelGGL((k_stream_collide<ST, MW>), dim3(c->tilesX * c->tilesY * nChunks), dim3(256), 0, c->st,
+    hipLaunchKernelGGL((k_stream_collide<ST, MW, PER>), dim3(c->tilesX * c->tilesY * nChunks), dim3(256), 0, c->st,
                        c->G, c->Ph, Dv, c->tilesX, c->tilesY, nChunks, nzc, glist, ngen);
     hipLaunchKernelGGL((k_general<ST, MW>), dim3(std::min(c->nTiles, 4096)), dim3(256), 0, c->st, c->G, c->Ph, Dv,
                        c->tilesX, c->tilesY, (const int *)glist, (const int *)ngen);
 }
 template <int ST>
 void launch_stream_collide(fsl_ctx *c, const Dev &Dv) {
-    if (c->Ph.moving_walls) launch_stream_collide_mw<ST, true>(c, Dv);
-    else launch_stream_collide_mw<ST, false>(c, Dv);
+    // the lever arms of particle links take nearest images only on boxes with a
+    // periodic axis
+    const bool per = c->G.per[0] || c->G.per[1] || c->G.per[2];
+    if (c->Ph.moving_walls) {
+        if (per) launch_stream_collide_mw<ST, true, true>(c, Dv);
+        else launch_stream_collide_mw<ST, true, false>(c, Dv);
+    } else {
+        if (per) launch_stream_collide_mw<ST, false, true>(c, Dv);
+        else launch_stream_collide_mw<ST, false, false>(c, Dv);
+    }
 }
 
 template <int ST> int enqueue_steps(fsl_ctx *c, int n, int split = 1);

@@ -817,7 +817,7 @@ __device__ __forceinline__ int step_to(int v, int d, int n, int per, int stride)
 // store set and act clear (gas and particle nodes of the row) write values that no
 // rule reads, so that every row of every population is written whole and once;
 // interface cells and lanes outside the box leave their words to the general path.
-template <int ST>
+template <int ST, bool PER>
 __device__ __forceinline__ void march_cell(const Geom &G, const Phys &Ph, const Dev &D, MarchLds &L,
                                            int sm1, int s0, int sp1, int lx, int ly, int x, int y, int z, int c,
                                            const SrcOff &so, bool act, bool store, bool nbnf, const void *Av,
@@ -926,8 +926,10 @@ __device__ __forceinline__ void march_cell(const Geom &G, const Phys &Ph, const 
             }
             // rigid-body velocity at the node: c_q . u_w at the link midpoint equals
             // c_q . (u_P + omega x (x - x_P)) because c_q . (omega x c_q) = 0
-            const float rx = mirror_arm(x, m.ax, m.fx, G.nx, G.per[0]), ry = mirror_arm(y, m.ay, m.fy, G.ny, G.per[1]),
-                        rz = mirror_arm(z, m.az, m.fz, G.nz, G.per[2]);
+            // nearest image only when the box has periodic axes (a compile-time case)
+            const float rx = mirror_arm(x, m.ax, m.fx, G.nx, PER && G.per[0]),
+                        ry = mirror_arm(y, m.ay, m.fy, G.ny, PER && G.per[1]),
+                        rz = mirror_arm(z, m.az, m.fz, G.nz, PER && G.per[2]);
             const float ru0 = rho_t * (m.ux + (m.wy * rz - m.wz * ry));
             const float ru1 = rho_t * (m.uy + (m.wz * rx - m.wx * rz));
             const float ru2 = rho_t * (m.uz + (m.wx * ry - m.wy * rx));
@@ -1025,7 +1027,7 @@ __device__ __forceinline__ void march_of_block(int b, int nCols, int nChunks, in
 // liquid cells of a 64 x 4 column through nzc planes.  Interface cells and liquid
 // cells next to gas or a moving or slipping face are left to k_general: each plane of
 // the column that holds one is appended to the list gen.
-template <int ST, bool MW>
+template <int ST, bool MW, bool PER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE_MARCH))) void k_stream_collide(
     Geom G, Phys Ph, Dev D, int tilesX, int tilesY, int nChunks, int nzc, int *gen, int *ngen) {
     __shared__ MarchLds L;
@@ -1086,7 +1088,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE_MARCH))
             so.zm = step_to(z, -1, G.nz, G.per[2], nxy);
             so.zp = step_to(z, 1, G.nz, G.per[2], nxy);
             const int c = xc + G.nx * yc + nxy * z;
-            march_cell<ST>(G, Ph, D, L, sm1, s0, sp1, lx, ly, xl, yl, z, c, so, act, inb && !gen_c, nbnf, Av, Bv, Sl,
+            march_cell<ST, PER>(G, Ph, D, L, sm1, s0, sp1, lx, ly, xl, yl, z, c, so, act, inb && !gen_c, nbnf, Av, Bv, Sl,
                            SI, R, zo2, curP);
         } else {
             pre_pids(D.pid, SI, R, zo2);
