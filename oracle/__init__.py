@@ -100,6 +100,8 @@ def lib():
                                       ctypes.c_double, dp]
         L.orc_contact.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
         L.orc_walls_get.argtypes = [P, dp]
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.orc_face_force.argtypes = [ip, ip, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
         L.orc_lambda_minus.restype = ctypes.c_double
         L.orc_lambda_minus.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int]
         _lib = L
@@ -129,6 +131,19 @@ def contact(x1, x2, R1, R2, k):
     F = np.zeros(3)
     applied = lib().orc_contact(*[_dp(v) for v in a], float(R1), float(R2), float(k), _dp(F))
     return F, bool(applied)
+
+
+def face_force(n, noslip, x, u, R, mu, k):
+    """Force of the no-slip faces on one sphere (lubrication limit and contact
+    spring); returns (F, number of faces that acted)."""
+    ni = np.ascontiguousarray(n, dtype=np.int32)
+    ns = np.ascontiguousarray(noslip, dtype=np.int32)
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (x, u)]
+    F = np.zeros(3)
+    ip = ctypes.POINTER(ctypes.c_int)
+    hits = lib().orc_face_force(ni.ctypes.data_as(ip), ns.ctypes.data_as(ip), *[_dp(v) for v in a],
+                                float(R), float(mu), float(k), _dp(F))
+    return F, int(hits)
 
 
 def lambda_minus(tau, magic=3.0 / 16.0, trt=True):

@@ -82,6 +82,7 @@ struct orc_ctx {
     double *px, *pu, *pw, *pR, *prho, *pF, *pT, *pFp, *pTp;
     int have_prev;          /* a previous step's force exists */
     double wallF[18];       /* force on each no-slip face [2 axis + side][comp], last step */
+    double wallP[18];       /* the part of it from links into particle nodes (force_pass) */
     /* bubbles */
     int nb;
     double *bM, *bV, *bV0, *bcent, *brho;
@@ -855,6 +856,44 @@ int orc_lubrication(const double x1[3], const double x2[3], const double u1[3],
     return 1;
 }
 
+/* A sphere at a no-slip face (axes a with noslip[a], faces at -1/2 and n[a] - 1/2).
+ * The paper states Eq. (lubrication) and needs a contact rule only for pairs of
+ * particles; reading: a face acts as a resting sphere of infinite radius touching the
+ * face plane.  Then (R1 R2)^2 / (R1 + R2)^2 tends to R^2, the line of centres is the
+ * face normal and the gap is h - R (h: distance of the centre from the face), so for
+ * gaps below Delta_c = 2/3, limited from below by 0.2 Delta_c, the sphere takes
+ * -6 pi mu R^2 (1/gap - 1/Delta_c) times its velocity component normal to the face,
+ * along that normal; with k > 0 an overlapping sphere (h < R) is pushed off the face
+ * by k (R - h).  Adds to F; returns the number of faces that applied a force. */
+int orc_face_force(const int n[3], const int noslip[3], const double x[3], const double u[3],
+                   double R, double mu, double k, double F[3])
+{
+    const double dc = 2.0 / 3.0;
+    int hits = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (!noslip[a]) continue;
+        for (int side = 0; side < 2; ++side) {
+            /* distance from the face and the direction pointing away from it */
+            double h = side ? (n[a] - 0.5) - x[a] : x[a] + 0.5;
+            double away = side ? -1.0 : 1.0;
+            int hit = 0;
+            if (k > 0.0 && h < R) {
+                F[a] += away * k * (R - h);
+                hit = 1;
+            }
+            double gap = h - R;
+            if (gap < dc) {
+                if (gap < 0.2 * dc) gap = 0.2 * dc;
+                /* normal n = -away e_a towards the face: -c (n.u) n = -c u_a e_a */
+                F[a] -= 6.0 * M_PI * mu * R * R * (1.0 / gap - 1.0 / dc) * u[a];
+                hit = 1;
+            }
+            hits += hit;
+        }
+    }
+    return hits;
+}
+
 /* Semi-implicit Euler with n_sub substeps (Sec. 2.3, "up to 10" read as a fixed
  * count; the paper does not give the scheme).  The hydrodynamic force and torque
  * are held constant over the substeps and are the mean of the momentum-exchange
@@ -864,8 +903,9 @@ int orc_lubrication(const double x1[3], const double x2[3], const double u1[3],
  * 2.5); right after the particle table is set, this step's value alone.  The
  * lubrication force is recomputed every substep, gravity m_P g (buoyancy comes
  * through the fluid pressure), m_P = rho_P 4/3 pi R^3, I = 2/5 m_P R^2.  The pair
- * forces (lubrication, contact) take the nearest periodic image of the partner.
- * Velocity is updated before position; along a periodic axis the position is kept
+ * forces (lubrication, contact) take the nearest periodic image of the partner;
+ * the no-slip faces act on each sphere as in orc_face_force, at the position and
+ * velocity the substep starts from.  Velocity is updated before position; along a periodic axis the position is kept
  * in [0, n).  A sphere closer than R to a wall face while moving towards it has
  * that velocity component reversed. */
 static void particles_integrate(orc_ctx *c)
@@ -873,6 +913,8 @@ static void particles_integrate(orc_ctx *c)
     const int np = c->np, ns = c->cfg.n_sub;
     const double dt = 1.0 / ns;
     const double mu = (c->cfg.tau - 0.5) / 3.0;
+    int noslip[3];
+    for (int a = 0; a < 3; ++a) noslip[a] = !c->cfg.periodic[a] && !c->cfg.freeslip[a];
     double *Fl = (double *)calloc((size_t)3 * np + 3, sizeof(double));
     for (int s = 0; s < ns; ++s) {
         memset(Fl, 0, sizeof(double) * 3 * np);
@@ -895,6 +937,9 @@ static void particles_integrate(orc_ctx *c)
                     }
                 }
             }
+        for (int P = 0; P < np; ++P)
+            orc_face_force(c->cfg.n, noslip, c->px + 3 * P, c->pu + 3 * P, c->pR[P], mu, c->cfg.contact_k,
+                           Fl + 3 * P);
         for (int P = 0; P < np; ++P) {
             double R = c->pR[P];
             double mP = c->prho[P] * (4.0 / 3.0) * M_PI * R * R * R;
@@ -937,11 +982,19 @@ static void particles_integrate(orc_ctx *c)
  * c_qbar f_qbar(x,t+1) with f_qbar(x,t+1) from Eq. (bbrule); the torque arm is the
  * node x.  A solid node of another particle P' with a link into P contributes
  * with equilibrium populations at rho = 1 and the rigid velocity of P' at that
- * node: Delta j = 2 c_q e^+_q(1, u_P'(x)).  Walls and gas contribute nothing.  The
- * torque arm runs from the nearest image of the centre. */
+ * node: Delta j = 2 c_q e^+_q(1, u_P'(x)).  Reading for the faces of the box, which
+ * the paper does not treat: a link into P from beyond a non-periodic face is taken
+ * the same way, with the velocity of the first no-slip face it crosses (at rest when
+ * it crosses free-slip faces only), and that no-slip face takes -Delta j.  The
+ * constant parts 2 w_q c_q of the links into a closed node set cancel exactly; without
+ * the face links a sphere that covers nodes of a face layer would miss them over the
+ * cut and be pulled into the face by the lattice pressure 1/3.  Gas contributes
+ * nothing.  The torque arm runs from the nearest image of the centre to the far end
+ * of the link. */
 static void force_pass(orc_ctx *c)
 {
     const size_t N = (size_t)c->N;
+    for (int a = 0; a < 18; ++a) c->wallP[a] = 0.0;
     for (int P = 0; P < c->np; ++P)
         for (int a = 0; a < 3; ++a) c->pF[3 * P + a] = c->pT[3 * P + a] = 0;
     if (c->np == 0) return;
@@ -978,6 +1031,35 @@ static void force_pass(orc_ctx *c)
             }
         } else if (fl == SOL) {
             int Pp = c->pid[x];
+            if (Pp >= 0)
+                for (int q = 1; q < 19; ++q) {
+                    /* a link into this node of Pp from beyond the faces of the box */
+                    if (nbr(c, i, j, k, -CX[q], -CY[q], -CZ[q], NULL) >= 0) continue;
+                    int slip = 0;
+                    const int cross = crossed_axes(c, i, j, k, -CX[q], -CY[q], -CZ[q], &slip);
+                    double uw[3] = {0.0, 0.0, 0.0};
+                    int face = -1;
+                    if (!slip) {
+                        int a = 0;
+                        while (!((cross >> a) & 1) || c->cfg.freeslip[a]) ++a;
+                        const int v = a == 0 ? i - CX[q] : (a == 1 ? j - CY[q] : k - CZ[q]);
+                        face = 2 * a + (v < 0 ? 0 : 1);
+                        for (int d = 0; d < 3; ++d) uw[d] = c->cfg.wall_u[a][v < 0 ? 0 : 1][d];
+                    }
+                    double ep = 2.0 * eq_plus(q, 1.0, uw);
+                    double dj[3] = {CX[q] * ep, CY[q] * ep, CZ[q] * ep};
+                    double r[3] = {min_image(c, 0, i - CX[q] - c->px[3 * Pp]),
+                                   min_image(c, 1, j - CY[q] - c->px[3 * Pp + 1]),
+                                   min_image(c, 2, k - CZ[q] - c->px[3 * Pp + 2])};
+                    c->pF[3 * Pp] += dj[0];
+                    c->pF[3 * Pp + 1] += dj[1];
+                    c->pF[3 * Pp + 2] += dj[2];
+                    c->pT[3 * Pp] += r[1] * dj[2] - r[2] * dj[1];
+                    c->pT[3 * Pp + 1] += r[2] * dj[0] - r[0] * dj[2];
+                    c->pT[3 * Pp + 2] += r[0] * dj[1] - r[1] * dj[0];
+                    if (face >= 0)
+                        for (int d = 0; d < 3; ++d) c->wallP[3 * face + d] -= dj[d];
+                }
             for (int q = 1; q < 19; ++q) {
                 int n = nbr(c, i, j, k, CX[q], CY[q], CZ[q], NULL);
                 if (n < 0 || c->flag[n] != SOL) continue;
@@ -1120,7 +1202,7 @@ static void stream_collide(orc_ctx *c)
     const double *g = c->cfg.g;
     int nerr = 0;
     double wf[18];
-    for (int a = 0; a < 18; ++a) wf[a] = 0.0;
+    for (int a = 0; a < 18; ++a) wf[a] = c->wallP[a];  /* links into particle nodes */
 #ifdef _OPENMP
 #pragma omp parallel for schedule(static) reduction(| : nerr) reduction(+ : wf[:18]) num_threads(c->cfg.n_threads > 0 ? c->cfg.n_threads : omp_get_max_threads())
 #endif

@@ -107,6 +107,8 @@ void orc_equilibrium(double rho, const double u[3], double e[19]);
 int orc_lubrication(const double x1[3], const double x2[3], const double u1[3],
                     const double u2[3], double R1, double R2, double mu, double F1[3]);
 int orc_contact(const double x1[3], const double x2[3], double R1, double R2, double k, double F1[3]);
+int orc_face_force(const int n[3], const int noslip[3], const double x[3], const double u[3],
+                   double R, double mu, double k, double F[3]);
 double orc_lambda_minus(double tau, double magic, int trt);
 
 #ifdef __cplusplus

@@ -431,6 +431,8 @@ int enqueue_pair_forces(fsl_ctx *c) {
     hipLaunchKernelGGL(k_grid_fill, dim3(grid_for(np)), dim3(256), 0, c->st, D, c->PG);
     hipLaunchKernelGGL(k_pairs, dim3(grid_for((long long)np * 27, 256, 2048)), dim3(256), 0, c->st, D, c->PG, c->L.pcap);
     hipLaunchKernelGGL(k_solid_pairs, dim3(grid_for(c->L.pcap, 4, 8192)), dim3(256), 0, c->st, c->G, D, c->L.pcap);
+    if (!c->G.per[0] || !c->G.per[1] || !c->G.per[2])
+        hipLaunchKernelGGL(k_face_links, dim3((np + 3) / 4), dim3(256), 0, c->st, c->G, c->Ph, D);
     hipLaunchKernelGGL(k_part_forces, dim3((np + 255) / 256), dim3(256), 0, c->st, D, c->cfg.integrate);
     LAUNCHCHK(c);
     return FSL_OK;
@@ -443,15 +445,18 @@ int enqueue_integration(fsl_ctx *c) {
     ProfScope ps(c, 4);
     const int ns = c->cfg.n_sub > 0 ? c->cfg.n_sub : 10;
     const double mu = (c->cfg.tau - 0.5) / 3.0;
+    int wmask = 0;  // axes whose faces are no-slip walls
+    for (int a = 0; a < 3; ++a)
+        if (c->cfg.boundary[a] == FSL_NOSLIP) wmask |= 1 << a;
     if (np <= INT_BLOCK_MAX) {  // small tables: every substep in one block
         hipLaunchKernelGGL(k_integrate_block, dim3(1), dim3(1024), 0, c->st, c->G, D, ns, mu, c->cfg.contact_k,
-                           c->L.pcap, c->cfg.g[0], c->cfg.g[1], c->cfg.g[2], c->have_prev);
+                           c->L.pcap, c->cfg.g[0], c->cfg.g[1], c->cfg.g[2], c->have_prev, wmask);
     } else {
         for (int s = 0; s < ns; ++s) {
             hipLaunchKernelGGL(k_lub, dim3(grid_for(c->L.pcap, 256, 1024)), dim3(256), 0, c->st, c->G, D, mu,
                                c->cfg.contact_k, c->L.pcap);
             hipLaunchKernelGGL(k_substep, dim3(grid_for(np)), dim3(256), 0, c->st, D, c->G, 1.0 / ns,
-                               c->cfg.g[0], c->cfg.g[1], c->cfg.g[2], c->have_prev);
+                               c->cfg.g[0], c->cfg.g[1], c->cfg.g[2], c->have_prev, mu, c->cfg.contact_k, wmask);
         }
     }
     c->have_prev = 1;

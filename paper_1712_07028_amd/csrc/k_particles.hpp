@@ -372,6 +372,81 @@ __global__ __launch_bounds__(256) void k_solid_pairs(Geom G, Dev D, int pcap) {
     }
 }
 
+// Links into a particle's nodes from beyond the faces of the box (Eq. momentum_transfer).
+// Reading: the far end is taken as a node inside another particle is, with
+// equilibrium populations at rho = 1, here at the velocity of the first no-slip face
+// the link crosses (at rest when it crosses free-slip faces only): Delta j = 2 c_q
+// e^+_q(1, u_w), and that no-slip face takes -Delta j.  The constant parts 2 w_q c_q
+// of the links into a closed node set cancel exactly; without these links a sphere
+// that covers nodes of a face layer would miss them over the cut and be pulled into
+// the face by the lattice pressure 1/3.  One wave per particle; the torque arm runs
+// from the centre to the far end of the link.
+__global__ __launch_bounds__(256) void k_face_links(Geom G, Phys Ph, Dev D) {
+    const int P = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (P >= D.np) return;
+    const int lane = threadIdx.x & 63;
+    const double *t = D.ptab + (long long)P * P_STRIDE;
+    const int n[3] = {G.nx, G.ny, G.nz};
+    int lo[3], hi[3];
+    sphere_box(G, t + P_X, t[P_R], lo, hi);
+    bool touch = false;
+    for (int a = 0; a < 3; ++a)
+        if (!G.per[a] && (lo[a] == 0 || hi[a] == n[a] - 1)) touch = true;
+    if (!touch) return;
+    const int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
+    const int tot = ex * ey * ez;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int s = lane; s < tot; s += 64) {
+        const int p[3] = {lo[0] + s % ex, lo[1] + (s / ex) % ey, lo[2] + s / (ex * ey)};
+        bool face = false;
+        for (int a = 0; a < 3; ++a)
+            if (!G.per[a] && (p[a] == 0 || p[a] == n[a] - 1)) face = true;
+        if (!face || !inside(p[0], p[1], p[2], t + P_X, t[P_R])) continue;
+        const int c = node_at(G, p[0], p[1], p[2]);
+        if (D.flags[c] != SOL || D.pid[c] != P) continue;
+        for (int q = 1; q < Q; ++q) {
+            const int f[3] = {p[0] - cx(q), p[1] - cy(q), p[2] - cz(q)};  // far end
+            int fa = -1;
+            bool crossed = false;
+            for (int a = 0; a < 3; ++a) {
+                if (G.per[a] || (f[a] >= 0 && f[a] < n[a])) continue;
+                crossed = true;
+                if (fa < 0 && !Ph.slip[a]) fa = a;
+            }
+            if (!crossed) continue;
+            const int sd = fa >= 0 && f[fa] >= 0 ? 1 : 0;
+            double u0 = 0.0, u1 = 0.0, u2 = 0.0;
+            if (fa >= 0) {
+                const float *uw = D.wallu + (fa * 2 + sd) * 3;
+                u0 = uw[0];
+                u1 = uw[1];
+                u2 = uw[2];
+            }
+            const double cu = cx(q) * u0 + cy(q) * u1 + cz(q) * u2;
+            const double e2 = 2.0 * wqd(q) * (1.0 + 4.5 * cu * cu - 1.5 * (u0 * u0 + u1 * u1 + u2 * u2));
+            const double j0 = cx(q) * e2, j1 = cy(q) * e2, j2 = cz(q) * e2;
+            const double r0 = f[0] - t[P_X], r1 = f[1] - t[P_X + 1], r2 = f[2] - t[P_X + 2];
+            acc[0] += j0;
+            acc[1] += j1;
+            acc[2] += j2;
+            acc[3] += r1 * j2 - r2 * j1;
+            acc[4] += r2 * j0 - r0 * j2;
+            acc[5] += r0 * j1 - r1 * j0;
+            if (fa >= 0) {
+                double *w = D.wallF + 3 * (2 * fa + sd);
+                if (j0 != 0.0) unsafeAtomicAdd(w, -j0);
+                if (j1 != 0.0) unsafeAtomicAdd(w + 1, -j1);
+                if (j2 != 0.0) unsafeAtomicAdd(w + 2, -j2);
+            }
+        }
+    }
+    double *dst = D.pacc + acc_at(P, P & (ACC_COPIES - 1));
+    for (int a = 0; a < 6; ++a) {
+        const double v = wave_sum(acc[a]);
+        if (lane == 0 && v != 0.0) unsafeAtomicAdd(dst + a, v);
+    }
+}
+
 // Pair force of one candidate pair (x, u of each sphere; f: force on sphere 1, sphere 2
 // takes -f).  Contact (the paper gives no contact model; reading): overlapping spheres
 // repel by a linear spring of stiffness kc along the line of centres, -kc (R1 + R2 -
@@ -407,6 +482,32 @@ __device__ __forceinline__ bool pair_force(const Geom &G, const double *x1, cons
     return f[0] != 0.0 || f[1] != 0.0 || f[2] != 0.0;
 }
 
+// Force of the no-slip faces (axes with bit a of wmask; faces at -1/2 and n - 1/2) on
+// one sphere, added to f.  Eq. (lubrication) and contact are stated for particle
+// pairs; reading: a face is a resting sphere of infinite radius touching the face
+// plane, so (R1 R2)^2/(R1 + R2)^2 becomes R^2, the pair normal the face normal and
+// the gap h - R (h: distance of the centre from the face).  For a gap below Delta_c,
+// limited from below by 0.2 Delta_c, that leaves a drag -6 pi mu R^2 (1/gap -
+// 1/Delta_c) on the velocity component normal to the face, whichever the side; an
+// overlapping sphere (h < R) is pushed off the face by kc (R - h).
+__device__ __forceinline__ void face_force(const Geom &G, int wmask, const double *x, const double *u, double R,
+                                           double mu, double kc, double f[3]) {
+    const double dc = 2.0 / 3.0;
+    const int n[3] = {G.nx, G.ny, G.nz};
+    for (int a = 0; a < 3; ++a) {
+        if (!((wmask >> a) & 1)) continue;
+        const double hl = x[a] + 0.5, hh = (n[a] - 0.5) - x[a];
+        if (kc > 0.0) {
+            if (hl < R) f[a] += kc * (R - hl);
+            if (hh < R) f[a] -= kc * (R - hh);
+        }
+        const double c = 6.0 * M_PI * mu * R * R;
+        double gl = hl - R, gh = hh - R;
+        if (gl < dc) f[a] -= c * (1.0 / fmax(gl, 0.2 * dc) - 1.0 / dc) * u[a];
+        if (gh < dc) f[a] -= c * (1.0 / fmax(gh, 0.2 * dc) - 1.0 / dc) * u[a];
+    }
+}
+
 __global__ void k_lub(Geom G, Dev D, double mu, double kc, int pcap) {
     int n = min(D.counters[C_NPAIRS], pcap);
     GRID_STRIDE(k, n) {
@@ -425,15 +526,18 @@ __global__ void k_lub(Geom G, Dev D, double mu, double kc, int pcap) {
 
 // one semi-implicit Euler substep of particle t (x, u, omega may live elsewhere than
 // the table): velocity from F_hyd + m g + F_pair, then position; angular velocity from
-// T_hyd; normal velocity reversed when closer than R to a wall face and moving towards
-// it; along a periodic axis the centre kept in [0, n).  F_hyd, T_hyd are the mean of
+// T_hyd; the no-slip faces act through face_force at the position and velocity the
+// substep starts from; normal velocity reversed when closer than R to a wall face and
+// moving towards it; along a periodic axis the centre kept in [0, n).  F_hyd, T_hyd are the mean of
 // this and the previous step's momentum exchange (two-step average that removes the
 // period-two oscillation of explicit coupling), or this step's alone after a reset.
 __device__ __forceinline__ void substep_one(const Geom &G, const Dev &D, int P, double *x, double *u, double *w,
-                                            double *fl, double dt, const double gg[3], int have_prev) {
+                                            double *fl, double dt, const double gg[3], int have_prev, double mu,
+                                            double kc, int wmask) {
     const double *t = D.ptab + (long long)P * P_STRIDE;
     const double *FTn = D.pFT + (long long)P * 6, *FTp = D.pFTp + (long long)P * 6;
     const double R = t[P_R];
+    if (wmask) face_force(G, wmask, x, u, R, mu, kc, fl);
     const double mP = t[P_RHO] * (4.0 / 3.0) * M_PI * R * R * R;
     const double IP = 0.4 * mP * R * R;
     const int n[3] = {G.nx, G.ny, G.nz};
@@ -453,11 +557,13 @@ __device__ __forceinline__ void substep_one(const Geom &G, const Dev &D, int P, 
     }
 }
 
-__global__ void k_substep(Dev D, Geom G, double dt, double g0, double g1, double g2, int have_prev) {
+__global__ void k_substep(Dev D, Geom G, double dt, double g0, double g1, double g2, int have_prev, double mu,
+                          double kc, int wmask) {
     GRID_STRIDE(P, D.np) {
         double *t = D.ptab + (long long)P * P_STRIDE;
         const double gg[3] = {g0, g1, g2};
-        substep_one(G, D, P, t + P_X, t + P_U, t + P_W, D.pFl + (long long)P * 3, dt, gg, have_prev);
+        substep_one(G, D, P, t + P_X, t + P_U, t + P_W, D.pFl + (long long)P * 3, dt, gg, have_prev, mu, kc,
+                    wmask);
         const int n[3] = {G.nx, G.ny, G.nz};
         if (!sphere_supported(t + P_X, t[P_R], n, G.per)) atomicOr(D.err, ERR_PART);
     }
@@ -469,7 +575,8 @@ __global__ void k_substep(Dev D, Geom G, double dt, double g0, double g1, double
 // k_substep, which take one launch each per substep.
 constexpr int INT_BLOCK_MAX = 512;
 __global__ __launch_bounds__(1024) void k_integrate_block(Geom G, Dev D, int ns, double mu, double kc, int pcap,
-                                                          double g0, double g1, double g2, int have_prev) {
+                                                          double g0, double g1, double g2, int have_prev,
+                                                          int wmask) {
     __shared__ double sx[INT_BLOCK_MAX][3], su[INT_BLOCK_MAX][3], sf[INT_BLOCK_MAX][3];
     const int np = D.np, npair = min(D.counters[C_NPAIRS], pcap);
     for (int P = threadIdx.x; P < np; P += blockDim.x) {
@@ -496,7 +603,8 @@ __global__ __launch_bounds__(1024) void k_integrate_block(Geom G, Dev D, int ns,
         }
         __syncthreads();
         for (int P = threadIdx.x; P < np; P += blockDim.x)
-            substep_one(G, D, P, sx[P], su[P], D.ptab + (long long)P * P_STRIDE + P_W, sf[P], dt, gg, have_prev);
+            substep_one(G, D, P, sx[P], su[P], D.ptab + (long long)P * P_STRIDE + P_W, sf[P], dt, gg, have_prev, mu,
+                        kc, wmask);
         __syncthreads();
     }
     for (int P = threadIdx.x; P < np; P += blockDim.x) {

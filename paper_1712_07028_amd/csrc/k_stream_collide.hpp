@@ -110,11 +110,24 @@ __device__ __forceinline__ void unpack2(int p, int &hi, int &lo) {
 
 // wave-level reduction of the lanes' accumulators, segmented by particle id:
 // one FP64 atomic per (wave, particle, component).  Lanes must be converged.
-__device__ __forceinline__ void acc_reduce_wave(const Dev &D, const LinkAcc &L, int x, int y, int z) {
+// integer arm x - a along one axis, to the nearest image along a periodic axis (the
+// nodes next to a sphere lie within R + 2 of its centre, less than n/2)
+__device__ __forceinline__ int anchor_arm(int x, float anchor, int n, int per) {
+    int d = x - (int)anchor;
+    if (per) {
+        if (2 * d > n) d -= n;
+        else if (2 * d < -n) d += n;
+    }
+    return d;
+}
+
+__device__ __forceinline__ void acc_reduce_wave(const Geom &G, const Dev &D, const LinkAcc &L, int x, int y,
+                                                int z) {
     int key = L.P;
     if (!__ballot(key >= 0)) return;
     // lane parts: forces, torques about the anchor, mass
-    const int dx = x - (int)L.an[0], dy = y - (int)L.an[1], dz = z - (int)L.an[2];
+    const int dx = anchor_arm(x, L.an[0], G.nx, G.per[0]), dy = anchor_arm(y, L.an[1], G.ny, G.per[1]),
+              dz = anchor_arm(z, L.an[2], G.nz, G.per[2]);
     const float ts0 = dy * L.fs[2] - dz * L.fs[1], ts1 = dz * L.fs[0] - dx * L.fs[2], ts2 = dx * L.fs[1] - dy * L.fs[0];
     const int ta0 = dy * L.ca[2] - dz * L.ca[1], ta1 = dz * L.ca[0] - dx * L.ca[2], ta2 = dx * L.ca[1] - dy * L.ca[0];
     const int td0 = dy * L.cd[2] - dz * L.cd[1], td1 = dz * L.cd[0] - dx * L.cd[2], td2 = dx * L.cd[1] - dy * L.cd[0];
@@ -521,7 +534,7 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
 
     wave_append(isF, c, D.lF, D.counters + C_NF, D.cap, D.err);
     wave_append(isE, c, D.lE0, D.counters + C_NE0, D.cap, D.err);
-    if (D.np > 0) acc_reduce_wave(D, acc, x, y, z);
+    if (D.np > 0) acc_reduce_wave(G, D, acc, x, y, z);
 }
 
 // Cell types of a 64 x 4 x 1 tile and its one-cell halo (WALL outside a

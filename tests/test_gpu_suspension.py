@@ -160,3 +160,82 @@ def test_reduced_sheared_suspension_plate_force():
     np.testing.assert_array_equal(o.get(O.FLAGS), s.get(fsl.FIELD_FLAGS))
     o.close()
     s.close()
+
+
+def cut_by_plates(integrate=True, depth=0.6):
+    """spheres reaching beyond both plates, one of them also across the periodic x face,
+    one sliding towards the low plate"""
+    n = (24, 20, 22)
+    R = np.array([4.0, 3.5, 3.0])
+    x = np.array([[1.2, 9.3, -0.5 + 4.0 - depth], [12.4, 10.2, 21.5 - 3.5 + depth], [12.0, 4.0, 3.4]])
+    p = W.Particles(x=x, u=np.array([[0.004, -0.002, -0.003], [0.0, 0.003, 0.002], [0.002, 0.0, -0.02]]),
+                    omega=np.array([[0.0, 0.002, 0.0], [0.001, 0.0, -0.002], [0.0, 0.0, 0.0]]),
+                    R=R, rho_p=np.array([3.0, 3.0, 3.0]))
+    return W.Workload(name="cut", n=n, trt=True, tau=0.7, g=(0, 0, 0), zs=-1.0, steps=0,
+                      periodic=(1, 1, 0), particles=p, integrate=integrate, contact_k=0.05)
+
+
+@pytest.mark.parametrize("integrate", [False, True])
+def test_single_step_spheres_cut_by_moving_plates(integrate):
+    """Links into sphere nodes from beyond the plates and the face lubrication and
+    spring: one step from the oracle's state, the single-step bars (face forces
+    included)."""
+    w = cut_by_plates(integrate)
+    wall = plates(0.01)
+    say("single step, spheres cut by moving plates, integrate", integrate)
+    o = O.Oracle(w, wall_u=wall)
+    o.step(6)
+    fo = o.get(O.FLAGS).reshape(w.n[2], w.n[1], w.n[0])
+    assert (fo[0] == O.SOL).sum() > 0 and (fo[-1] == O.SOL).sum() > 0
+    s = fsl.Sim(w, wall_u=wall)
+    transfer(o, s, w)
+    o.step(1)
+    s.step(1)
+    s.sync()
+    say(compare_step(o, s, w))
+    o.close()
+    s.close()
+
+
+def test_resting_spheres_cut_by_plates_gpu():
+    """Fluid at rest, resting plates, resting spheres cut by the plates: no force or
+    torque on the spheres and the pressure 1/3 over each plate's whole area."""
+    w = cut_by_plates(False, depth=1.1)
+    p = w.particles
+    w = w.replace(particles=W.Particles(x=p.x, u=0 * p.u, omega=0 * p.omega, R=p.R, rho_p=p.rho_p))
+    s = fsl.Sim(w)
+    s.step(3)
+    s.sync()
+    q = s.particles_get(3)
+    say("  F", q["F"].tolist(), "T", q["T"].tolist())
+    np.testing.assert_allclose(q["F"], 0.0, atol=1e-12)
+    # the lever arms are FP32 (x - x_P rounded to 2^-24 relative at |x - x_P| <= R + 2):
+    # about a thousand links of 1/9 or 1/18 leave at most a few 1e-5 (missing face
+    # links would leave about 1/3 per cut node at an arm of R)
+    np.testing.assert_allclose(q["T"], 0.0, atol=1e-5)
+    F = s.walls()
+    A = w.n[0] * w.n[1]
+    np.testing.assert_allclose(F[2, 0], [0, 0, -A / 3.0], rtol=0, atol=1e-9 * A)
+    np.testing.assert_allclose(F[2, 1], [0, 0, A / 3.0], rtol=0, atol=1e-9 * A)
+    s.close()
+
+
+def test_spheres_at_moving_plates_multistep():
+    """120 steps of spheres at the moving plates (one driven into the low plate): the
+    positions and velocities against the oracle's."""
+    w = cut_by_plates(True)
+    wall = plates(0.02)
+    o, s = O.Oracle(w, wall_u=wall), fsl.Sim(w, wall_u=wall)
+    o.step(120)
+    s.step(120)
+    s.sync()
+    a, b = o.particles_get(3), s.particles_get(3)
+    say("  oracle x", a["x"].tolist(), "gpu x", b["x"].tolist())
+    dx = b["x"] - a["x"]
+    for k in range(2):
+        dx[:, k] -= w.n[k] * np.round(dx[:, k] / w.n[k])
+    assert np.abs(dx).max() < 1e-6
+    assert np.abs(b["u"] - a["u"]).max() < 1e-4 * np.abs(a["u"]).max()
+    assert a["x"][2, 2] - 3.0 > -0.5  # held off the low plate
+    o.close()
+    s.close()

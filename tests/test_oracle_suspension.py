@@ -12,6 +12,12 @@ across periodic faces (nearest images) and the contact spring.
   periodic axes (spheres straddling the faces in one, not in the other) gives the
   shifted fields, positions, velocities, forces and torques to rounding.
 - Contact: the spring law's closed form, equal and opposite, zero without overlap.
+- No-slip faces on a sphere: the pair forms (Eq. lubrication, the contact spring)
+  for a resting partner of radius 2^30 whose surface is the face plane, for every
+  axis and both faces; nothing on periodic or free-slip axes, nothing beyond the
+  cut-off, nothing for motion along the face, the gap clamp at 0.2 Delta_c.
+- A sphere driven at a plate stops short of it (the face lubrication) and an
+  overlapping one is pushed back out (the face spring).
 """
 import numpy as np
 import pytest
@@ -136,3 +142,115 @@ def test_contact_law(orc):
     np.testing.assert_allclose(F2, -F, rtol=0, atol=1e-18)
     assert not orc.contact(x1, x2, 2.0, 2.9, 0.2)[1]  # gap 0.1
     assert not orc.contact(x1, x2, 3.0, 2.5, 0.0)[1]  # switched off
+
+
+FACE_N = (20, 24, 28)
+
+
+def big_partner(x, axis, side, R2):
+    """centre of a sphere of radius R2 whose surface lies on the face plane"""
+    xb = np.array(x, dtype=np.float64)
+    xb[axis] = -0.5 - R2 if side == 0 else (FACE_N[axis] - 0.5) + R2
+    return xb
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("side", [0, 1])
+@pytest.mark.parametrize("h", [8.5, 8.25, 8.0625])  # gaps 0.5, 0.25 and 0.0625 (clamped)
+def test_face_force_is_the_large_sphere_limit(orc, axis, side, h):
+    R, mu, R2 = 8.0, 0.037, 2.0 ** 30
+    x = np.array([9.0, 11.0, 13.0])
+    x[axis] = h - 0.5 if side == 0 else (FACE_N[axis] - 0.5) - h
+    u = np.array([0.003, -0.002, 0.004])
+    noslip = [0, 0, 0]
+    noslip[axis] = 1
+    F, hits = orc.face_force(FACE_N, noslip, x, u, R, mu, 0.0)
+    Fp, on = orc.lubrication(x, big_partner(x, axis, side, R2), u, np.zeros(3), R, R2, mu)
+    assert hits == 1 and on
+    # (R R2)^2/(R + R2)^2 = R^2 (1 - 2^-27)^2; the partner's centre rounds within 2^-22
+    np.testing.assert_allclose(F, Fp, rtol=1e-5, atol=1e-18)
+    assert F[axis] * u[axis] < 0 and np.count_nonzero(F) == 1
+    # the closed form
+    gap = max(h - R, 0.2 * 2.0 / 3.0)
+    assert abs(F[axis] / (-6 * np.pi * mu * R * R * (1 / gap - 1.5) * u[axis]) - 1) < 1e-14
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+@pytest.mark.parametrize("side", [0, 1])
+def test_face_contact_is_the_large_sphere_limit(orc, axis, side):
+    R, k, R2 = 6.0, 0.3, 2.0 ** 30
+    x = np.array([9.0, 11.0, 13.0])
+    h = 5.75  # 0.25 into the face
+    x[axis] = h - 0.5 if side == 0 else (FACE_N[axis] - 0.5) - h
+    noslip = [0, 0, 0]
+    noslip[axis] = 1
+    F, hits = orc.face_force(FACE_N, noslip, x, np.zeros(3), R, 0.0, k)
+    Fp, on = orc.contact(x, big_partner(x, axis, side, R2), R, R2, k)
+    assert hits == 1 and on
+    np.testing.assert_allclose(F, Fp, rtol=1e-5, atol=1e-18)
+    assert F[axis] == pytest.approx((1 if side == 0 else -1) * k * 0.25, rel=1e-14)
+
+
+def test_face_force_only_at_no_slip_faces_within_reach(orc):
+    R, mu, k = 4.0, 0.05, 0.2
+    u = np.array([0.01, 0.02, -0.03])
+    x = np.array([3.6, 3.6, 3.6])  # 0.1 from every low face: gaps 0.1 (clamped)
+    assert orc.face_force(FACE_N, [0, 0, 0], x, u, R, mu, k)[1] == 0  # periodic or free-slip axes
+    F, hits = orc.face_force(FACE_N, [1, 1, 1], x, u, R, mu, k)
+    assert hits == 3
+    c = 6 * np.pi * mu * R * R * (1 / (0.4 / 3.0) - 1.5)
+    np.testing.assert_allclose(F, -c * u, rtol=1e-14)  # no overlap: no spring
+    # gap Delta_c and beyond: nothing; the far faces are far
+    x2 = np.array([4.5 + 2.0 / 3.0, 9.0, 10.0])
+    assert orc.face_force(FACE_N, [1, 1, 1], x2, u, R, mu, k)[1] == 0
+    # motion along the face takes no force from it
+    F, hits = orc.face_force(FACE_N, [0, 0, 1], np.array([9.0, 9.0, 3.7]), np.array([0.02, -0.01, 0.0]), R, mu, 0.0)
+    assert hits == 1 and np.all(F == 0)
+
+
+def test_sphere_held_off_and_pushed_out_of_plates(orc):
+    """Plates at rest: a sphere 0.3 from the low plate moving into it at 0.02 stops
+    short of the plate, and one 0.3 into the high plate is pushed back out."""
+    n = (20, 18, 24)
+    p = W.Particles(x=np.array([[9.0, 9.0, 4.5 + 0.3 - 0.5], [9.0, 9.0, 23.5 - 4.0 + 0.3]]),
+                    u=np.array([[0.0, 0.0, -0.02], [0.0, 0.0, 0.0]]), omega=np.zeros((2, 3)),
+                    R=np.array([4.0, 4.0]), rho_p=np.array([3.0, 3.0]))
+    w = W.Workload(name="plates", n=n, trt=True, tau=0.8, g=(0, 0, 0), zs=-1.0, steps=0, periodic=(1, 1, 0),
+                   particles=p, contact_k=0.05)
+    o = orc.Oracle(w)
+    zs = []
+    for _ in range(40):
+        o.step(1)
+        zs.append(o.particles_get(2)["x"][:, 2])
+    zs = np.array(zs)
+    assert zs[:, 0].min() - 4.0 > -0.5  # never reaches the low plate
+    assert zs[-1, 1] + 4.0 < zs[0, 1] + 4.0  # moved away from the high plate
+    o.close()
+
+
+@pytest.mark.parametrize("depth", [0.3, 1.2])
+def test_resting_sphere_cut_by_plates_feels_no_pressure(orc, depth):
+    """Fluid at rest (rho = 1, u = 0) between resting plates, a resting sphere reaching
+    `depth` beyond the low plate and one beyond the high plate: a uniform pressure
+    puts no net force or torque on a body, and the plate still takes the pressure
+    1/3 over its whole area.  The links from beyond the faces complete the node set;
+    without them each sphere would be pulled into its plate by 1/3 per cut node."""
+    n = (22, 20, 26)
+    R = 5.0
+    x = np.array([[7.3, 9.6, -0.5 + R - depth], [15.2, 9.1, 25.5 - R + depth]])
+    p = W.Particles(x=x, u=np.zeros((2, 3)), omega=np.zeros((2, 3)), R=np.array([R, R]), rho_p=np.array([2.0, 2.0]))
+    w = W.Workload(name="cut", n=n, trt=True, tau=0.7, g=(0, 0, 0), zs=-1.0, steps=0, periodic=(1, 1, 0),
+                   particles=p, integrate=False)
+    o = orc.Oracle(w)
+    flags = o.get(orc.FLAGS).reshape(n[2], n[1], n[0])
+    cut = [(flags[0] == orc.SOL).sum(), (flags[-1] == orc.SOL).sum()]
+    assert min(cut) >= 4
+    o.step(3)
+    q = o.particles_get(2)
+    np.testing.assert_allclose(q["F"], 0.0, atol=1e-13)
+    np.testing.assert_allclose(q["T"], 0.0, atol=1e-12)
+    F = o.walls()
+    A = n[0] * n[1]
+    np.testing.assert_allclose(F[2, 0], [0, 0, -A / 3.0], rtol=0, atol=1e-12 * A)
+    np.testing.assert_allclose(F[2, 1], [0, 0, A / 3.0], rtol=0, atol=1e-12 * A)
+    o.close()
