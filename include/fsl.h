@@ -199,20 +199,24 @@ int fsl_particles_get(fsl_ctx *ctx, int n, double *x, double *u, double *omega,
 /* Force of the fluid on each no-slip face of the box over the last completed step:
  * the momentum exchange (Eqs. netforce, momentum_transfer) of the face's half-way
  * bounce-back links, resting or moving (Eq. bbrule), as for particle links; the
- * plate force of the sheared suspension (Sec. 3.1, mu_s = F_x / (A gamma)).
+ * plate force of the sheared suspension (Sec. 3.1, mu_s = F_x / (A gamma)).  A
+ * sphere node on a face layer takes the links from beyond the face as links from
+ * inside another particle (Eq. momentum_transfer: equilibrium at rho = 1, here with
+ * the face's velocity); the face takes the opposite momentum of those too.
  * F[3 (2 axis + side) + component], side 0 the low face; a link whose source lies
  * beyond several faces counts for the first no-slip one; free-slip and periodic
  * faces read 0.  The normal components include the fluid pressure (rho c_s^2 per
  * unit area at rest).  Synchronises. */
 int fsl_walls_get(fsl_ctx *ctx, double F[18]);
 
-/* Copy up to cap bubble records to out; *n receives the number of ids in use
+/* Copy up to cap bubble records (the bubble model of Sec. 2.2: gas mass M, volume V
+ * from the fill levels, rho_g = M / V) to out; *n receives the number of ids in use
  * (splits add ids).  Synchronises. */
 int fsl_bubbles_get(fsl_ctx *ctx, fsl_bubble *out, int cap, int *n);
 
-/* Import the bubble table (gas masses, merge roots, alive flags) for n ids (the
- * others become unused), recompute volumes and gas densities from the current
- * fields and split bubbles whose gas is not connected. */
+/* Import the bubble table of Sec. 2.2 (gas masses, merge roots, alive flags) for
+ * n ids (the others become unused), recompute volumes and gas densities rho_g =
+ * M / V from the current fields and split bubbles whose gas is not connected. */
 int fsl_bubbles_set(fsl_ctx *ctx, int n, const double *M, const int *root, const int *alive);
 
 /* Field exchange for tests and checkpoints.  Host layouts:
