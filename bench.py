@@ -172,8 +172,8 @@ def split_pass_cost(fsl, torch, w, reps=3):
 def bubble_regimes(fsl, W, torch, steps=8000, every=50, z_stop=70.0):
     """Single rising bubbles in the regimes of Table tab:Annaland (free-slip sides,
     no-slip floor, pressure at the top): the bubble Reynolds number Re = u d / nu from
-    the centroid's rise velocity over the last third of the run, d the diameter of a
-    sphere of the bubble's volume, beside the paper's numbers."""
+    the rise velocity of the main bubble's centroid over the last third of the run, d
+    the diameter of a sphere of its volume, beside the paper's numbers."""
     out = {}
     for case, p in W.BUBBLE_REGIMES.items():
         w = W.bubble_regime(case)
@@ -183,12 +183,24 @@ def bubble_regimes(fsl, W, torch, steps=8000, every=50, z_stop=70.0):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         t = 0
+        full = None
         while t < steps:
             s.step(every)
             t += every
-            b = s.bubbles()
-            track.append((t, b[1]["centroid"][2], b[1]["V"], len([x for x in b if x["alive"]])))
-            if b[1]["centroid"][2] > z_stop:
+            try:
+                b = s.bubbles()
+            except fsl.FslError as e:
+                # the skirted bubble sheds tens of satellites, each holding an id of the
+                # 64-entry table until it vanishes: the run ends where the table is full
+                if "overflowed" not in str(e):
+                    raise
+                full = t
+                break
+            # the main bubble: the largest gas part other than the atmosphere (id 0); a
+            # split can leave id 1 to a fragment
+            m = max((x for x in b[1:] if x["alive"]), key=lambda x: x["V"])
+            track.append((t, m["centroid"][2], m["V"], len([x for x in b if x["alive"]])))
+            if m["centroid"][2] > z_stop:
                 break
         dt = time.perf_counter() - t0
         s.close()
@@ -197,8 +209,10 @@ def bubble_regimes(fsl, W, torch, steps=8000, every=50, z_stop=70.0):
         u = np.polyfit(tr[-k:, 0], tr[-k:, 1], 1)[0]
         d = (6.0 * tr[-k:, 2].mean() / np.pi) ** (1.0 / 3.0)
         out[case] = {"re": round(float(u * d / nu), 3), "re_paper": p["re_paper"], "re_fan": p["re_fan"],
-                     "u": float(u), "d": round(float(d), 3), "steps": int(t), "bubbles_alive": int(tr[-1, 3]),
+                     "u": float(u), "d": round(float(d), 3), "steps": int(tr[-1, 0]), "bubbles_alive": int(tr[-1, 3]),
                      "mlups": round(w.cells * t / dt / 1e6, 1)}
+        if full is not None:
+            out[case]["bubble_table_full_at_step"] = int(full)
     return out
 
 

@@ -228,9 +228,10 @@ class Sim:
         return dict(zip(("x", "u", "omega", "F", "T"), out))
 
     def bubbles(self):
-        buf = (FslBubble * 64)()
+        cap = max(64, int(self.cfg.max_bubbles))  # the table's capacity (0 = the default 64)
+        buf = (FslBubble * cap)()
         n = ctypes.c_int(0)
-        self._check(self.L.fsl_bubbles_get(self.ctx, buf, 64, ctypes.byref(n)), "fsl_bubbles_get")
+        self._check(self.L.fsl_bubbles_get(self.ctx, buf, cap, ctypes.byref(n)), "fsl_bubbles_get")
         return [dict(id=b.id, alive=b.alive, V=b.V, M=b.M, rho_g=b.rho_g, centroid=tuple(b.centroid),
                      V0=b.V0, n_gas=b.n_gas, n_iface=b.n_iface) for b in buf[: n.value]]
 
