@@ -239,3 +239,55 @@ def test_spheres_at_moving_plates_multistep():
     assert a["x"][2, 2] - 3.0 > -0.5  # held off the low plate
     o.close()
     s.close()
+
+
+def many_at_plates():
+    """600 spheres (above the one-block integration's 512): a layer of 441 cut by the
+    low plate on a 3-cell grid, 159 higher up, plates moving along x"""
+    n = (64, 64, 20)
+    g = np.arange(21) * 3.0 + 1.5
+    gx, gy = np.meshgrid(g, g, indexing="ij")
+    low = np.stack([gx.ravel(), gy.ravel(), np.full(gx.size, 0.5)], axis=1)  # h = 1.0 < R
+    rng = np.random.default_rng(4)
+    high = np.stack([gx.ravel(), gy.ravel(), np.full(gx.size, 10.0)], axis=1)[rng.permutation(gx.size)[:159]]
+    x = np.concatenate([low, high])
+    u = rng.uniform(-0.01, 0.01, size=x.shape)
+    u[:441, 2] = -np.abs(u[:441, 2])  # the low layer moves into the plate
+    p = W.Particles(x=x, u=u, omega=np.zeros_like(x), R=np.full(600, 1.2), rho_p=np.full(600, 3.0))
+    return W.Workload(name="many_at_plates", n=n, trt=True, tau=0.7, g=(0, 0, -1e-5), zs=-1.0, steps=0,
+                      periodic=(1, 1, 0), particles=p, contact_k=0.05)
+
+
+def test_many_spheres_at_plates_single_step_and_multistep():
+    """The per-substep launches (k_lub, k_substep with the face lubrication and spring)
+    and the face links with 600 spheres: one step from the oracle's state within the
+    single-step bars, then 30 steps from the start against the oracle's positions and
+    velocities."""
+    w = many_at_plates()
+    wall = plates(0.01)
+    o = O.Oracle(w, wall_u=wall)
+    o.step(3)
+    fo = o.get(O.FLAGS).reshape(w.n[2], w.n[1], w.n[0])
+    assert (fo[0] == O.SOL).sum() >= 441
+    s = fsl.Sim(w, wall_u=wall)
+    transfer(o, s, w)
+    o.step(1)
+    s.step(1)
+    s.sync()
+    say(compare_step(o, s, w))
+    o.close()
+    s.close()
+    o, s = O.Oracle(w, wall_u=wall), fsl.Sim(w, wall_u=wall)
+    o.step(30)
+    s.step(30)
+    s.sync()
+    a, b = o.particles_get(600), s.particles_get(600)
+    dx = b["x"] - a["x"]
+    for k in range(2):
+        dx[:, k] -= w.n[k] * np.round(dx[:, k] / w.n[k])
+    say("  max |dx|", np.abs(dx).max(), "max |du|", np.abs(b["u"] - a["u"]).max(), "of", np.abs(a["u"]).max())
+    assert np.abs(dx).max() < 1e-6
+    assert np.abs(b["u"] - a["u"]).max() < 1e-4 * np.abs(a["u"]).max()
+    assert a["x"][:441, 2].min() > -0.5  # no centre reached the plate
+    o.close()
+    s.close()
