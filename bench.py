@@ -198,12 +198,17 @@ def bubble_regimes(fsl, W, torch, steps=8000, every=50, z_stop=70.0):
                 break
             # the main bubble: the largest gas part other than the atmosphere (id 0); a
             # split can leave id 1 to a fragment
-            m = max((x for x in b[1:] if x["alive"]), key=lambda x: x["V"])
+            m = max((x for x in b[1:] if x["alive"]), key=lambda x: x["V"], default=None)
+            if m is None:  # the bubble has vanished
+                break
             track.append((t, m["centroid"][2], m["V"], len([x for x in b if x["alive"]])))
             if m["centroid"][2] > z_stop:
                 break
         dt = time.perf_counter() - t0
         s.close()
+        if len(track) < 2:
+            out[case] = {"re": None, "re_paper": p["re_paper"], "re_fan": p["re_fan"], "steps": int(t)}
+            continue
         tr = np.array(track)
         k = max(2, len(tr) // 3)
         u = np.polyfit(tr[-k:, 0], tr[-k:, 1], 1)[0]
