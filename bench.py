@@ -132,7 +132,7 @@ def adjoint_rate(fsl, W, torch, n, n_particles, T=200, k=20):
 def surface_tension_rate(fsl, torch, w, steps, sigma=0.005):
     """The column with surface tension: whole step and the curvature pass."""
     ws = w.replace(sigma=sigma)
-    s = fsl.Sim(ws)
+    s = fsl.Sim(ws, face_forces=False)
     s.step(5)
     s.sync()
     torch.cuda.synchronize()
@@ -155,7 +155,7 @@ def surface_tension_rate(fsl, torch, w, steps, sigma=0.005):
 def split_pass_cost(fsl, torch, w, reps=3):
     """The column's bubble-splitting labelling when it runs: a forced pass over the
     state after 5 steps (setting the bubble table labels every gas cell)."""
-    s = fsl.Sim(w)
+    s = fsl.Sim(w, face_forces=False)
     s.step(5)
     s.sync()
     b = s.bubbles()
@@ -446,7 +446,9 @@ def main():
 
     def run(storage, steps, warmup, profile):
         ww = w.replace(storage=storage)
-        sim = fsl.Sim(ww)
+        # the column's step without the face-force diagnostic (the plate force of the
+        # suspension experiment), which nothing here reads
+        sim = fsl.Sim(ww, face_forces=False)
         sim.step(warmup)
         sim.sync()
         flags = sim.get(fsl.FIELD_FLAGS)

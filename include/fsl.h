@@ -105,6 +105,10 @@ typedef struct {
                                    spheres, F = k (R1 + R2 - |d|) along the line of
                                    centres (0 = none; the paper gives no contact
                                    model, its lubrication force is cut off)          */
+    int no_face_forces;         /* 1: the force on each no-slip face (fsl_walls_get) is
+                                   not computed, which saves a pass over the face
+                                   layers per step; fsl_walls_get then fails with
+                                   FSL_E_ARG.  0 (the default): computed every step */
 } fsl_config;
 
 typedef struct {
@@ -206,7 +210,8 @@ int fsl_particles_get(fsl_ctx *ctx, int n, double *x, double *u, double *omega,
  * F[3 (2 axis + side) + component], side 0 the low face; a link whose source lies
  * beyond several faces counts for the first no-slip one; free-slip and periodic
  * faces read 0.  The normal components include the fluid pressure (rho c_s^2 per
- * unit area at rest).  Synchronises. */
+ * unit area at rest).  Synchronises.  FSL_E_ARG
+ * when the context was made with no_face_forces. */
 int fsl_walls_get(fsl_ctx *ctx, double F[18]);
 
 /* Copy up to cap bubble records (the bubble model of Sec. 2.2: gas mass M, volume V

@@ -40,6 +40,7 @@ class FslConfig(ctypes.Structure):
         ("wall_u", ((ctypes.c_double * 3) * 2) * 3),
         ("open_atmosphere", ctypes.c_int),
         ("contact_k", ctypes.c_double),
+        ("no_face_forces", ctypes.c_int),
     ]
 
 
@@ -102,7 +103,8 @@ def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def make_config(w, max_particles=None, list_capacity=0, window=(0, 0), wall_u=None, max_bubbles=0):
+def make_config(w, max_particles=None, list_capacity=0, window=(0, 0), wall_u=None, max_bubbles=0,
+                face_forces=True):
     """fsl_config from a workloads.Workload."""
     c = FslConfig()
     for a in range(3):
@@ -129,6 +131,7 @@ def make_config(w, max_particles=None, list_capacity=0, window=(0, 0), wall_u=No
     c.max_bubbles = int(max_bubbles)
     c.open_atmosphere = int(bool(getattr(w, "open_atmosphere", False)))
     c.contact_k = float(getattr(w, "contact_k", 0.0))
+    c.no_face_forces = 0 if face_forces else 1
     c.window_steps, c.window_every = int(window[0]), int(window[1])
     c.sigma = float(getattr(w, "sigma", 0.0))
     if wall_u is not None:
@@ -148,10 +151,11 @@ class Sim:
     workloads.Workload.  With ``static=True`` the context comes from
     fsl_init_static: the tensor holds the state only and the working memory is the
     library's own array on the device, shared by every such context on it (give them
-    one stream)."""
+    one stream).  ``face_forces=False`` leaves out the force on the no-slip faces
+    (``walls()`` then fails)."""
 
     def __init__(self, w, device="cuda", max_particles=None, list_capacity=0, window=(0, 0),
-                 set_particles=True, wall_u=None, max_bubbles=0, static=False, stream=None):
+                 set_particles=True, wall_u=None, max_bubbles=0, static=False, stream=None, face_forces=True):
         import torch
 
         self.L = load_library()
@@ -159,7 +163,7 @@ class Sim:
             raise FslError("no HIP device")
         self.w = w
         self.N = w.cells
-        self.cfg = make_config(w, max_particles, list_capacity, window, wall_u, max_bubbles)
+        self.cfg = make_config(w, max_particles, list_capacity, window, wall_u, max_bubbles, face_forces)
         self.ctx = ctypes.c_void_p()
         if static:
             dev = torch.device(device)

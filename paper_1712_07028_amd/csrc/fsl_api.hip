@@ -503,8 +503,8 @@ int enqueue_steps(fsl_ctx *c, int n, int split) {
     for (int s = 0; s < n; ++s) {
         Dev &D = c->D;
         hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, c->st, D);
-        hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, c->st, D.wallF, 18LL, 0.0);
-        if (c->FS.n > 0)  // face forces from the state at t
+        if (D.wallF) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, c->st, D.wallF, 18LL, 0.0);
+        if (c->FS.n > 0 && D.wallF)  // face forces from the state at t
             hipLaunchKernelGGL(k_wall_forces<ST>, dim3(grid_for(c->FS.start[c->FS.n], 256, 1024)), dim3(256), 0, c->st,
                                c->G, c->Ph, D, c->FS);
         if (D.kappa) {  // curvature of the interface at t for the Laplace jump
@@ -821,7 +821,7 @@ static int init_ctx(const fsl_config *cfg, const Layout &L, char *d_ws, char *d_
     D.rhog = (float *)(w + L.rhog);
     D.kappa = cfg->sigma != 0.0 ? (float *)(w + L.kappa) : nullptr;
     D.wallu = (float *)(w + L.wallu);
-    D.wallF = (double *)(w + L.wallF);
+    D.wallF = cfg->no_face_forces ? nullptr : (double *)(w + L.wallF);
     D.rhow = cfg->max_particles > 0 ? (unsigned *)(w + L.rhow) : nullptr;
     D.st_prev = D.st_cur = -1;
     c->stamp = 1;
@@ -878,7 +878,7 @@ static int init_ctx(const fsl_config *cfg, const Layout &L, char *d_ws, char *d_
 
     // control block, tables, accumulators
     hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, c->st, (double *)(w + L.ctl), 64LL, 0.0);
-    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, c->st, D.wallF, 18LL, 0.0);
+    if (D.wallF) hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, c->st, D.wallF, 18LL, 0.0);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, c->st, D.counters, 64LL, 0);
     {
         const int used = cfg->n_gas_spheres + 1;  // bubble ids in use: atmosphere and gas spheres
@@ -1104,6 +1104,7 @@ int fsl_particles_set(fsl_ctx *c, int n, const double *x, const double *u, const
 
 int fsl_walls_get(fsl_ctx *c, double F[18]) {
     if (!c || !F) return FSL_E_ARG;
+    if (!c->D.wallF) return fail(c, FSL_E_ARG, "walls_get: the context was made with no_face_forces");
     HIPCHK(c, hipMemcpyAsync(F, c->D.wallF, 18 * sizeof(double), hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
     return read_error(c);

@@ -432,7 +432,7 @@ __global__ __launch_bounds__(256) void k_face_links(Geom G, Phys Ph, Dev D) {
             acc[3] += r1 * j2 - r2 * j1;
             acc[4] += r2 * j0 - r0 * j2;
             acc[5] += r0 * j1 - r1 * j0;
-            if (fa >= 0) {
+            if (fa >= 0 && D.wallF) {
                 double *w = D.wallF + 3 * (2 * fa + sd);
                 if (j0 != 0.0) unsafeAtomicAdd(w, -j0);
                 if (j1 != 0.0) unsafeAtomicAdd(w + 1, -j1);

@@ -291,3 +291,33 @@ def test_many_spheres_at_plates_single_step_and_multistep():
     assert a["x"][:441, 2].min() > -0.5  # no centre reached the plate
     o.close()
     s.close()
+
+
+def test_face_forces_off_changes_nothing_else():
+    """A context made without the face forces: walls() fails, and after 20 steps at
+    moving plates its cell types and particle owners equal those of a context that
+    computes them, its populations and sphere states to rounding (the FP64 force sums
+    take no fixed order, as between any two runs): the face forces are a diagnostic,
+    never fed back."""
+    w = cut_by_plates(True)
+    wall = plates(0.01)
+    a, b = fsl.Sim(w, wall_u=wall), fsl.Sim(w, wall_u=wall, face_forces=False)
+    a.step(20)
+    b.step(20)
+    a.sync()
+    b.sync()
+    with pytest.raises(fsl.FslError, match="no_face_forces"):
+        b.walls()
+    assert np.abs(a.walls()).max() > 0
+    for k in (fsl.FIELD_FLAGS, fsl.FIELD_PID):
+        np.testing.assert_array_equal(a.get(k), b.get(k))
+    fl = a.get(fsl.FIELD_FLAGS)
+    act = (fl == fsl.LIQ) | (fl == fsl.IFC)
+    fa, fb = a.get(fsl.FIELD_F)[:, act], b.get(fsl.FIELD_F)[:, act]
+    assert np.abs(fa - fb).max() <= 1e-9 * np.abs(fa).max()
+    pa, pb = a.particles_get(3), b.particles_get(3)
+    assert np.abs(pa["x"] - pb["x"]).max() < 1e-9
+    for k in ("u", "omega", "F", "T"):
+        assert np.abs(pa[k] - pb[k]).max() <= 1e-6 * np.abs(pa[k]).max(), k
+    a.close()
+    b.close()
