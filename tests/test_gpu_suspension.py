@@ -321,3 +321,39 @@ def test_face_forces_off_changes_nothing_else():
         assert np.abs(pa[k] - pb[k]).max() <= 1e-6 * np.abs(pa[k]).max(), k
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("slip", [False, True])
+def test_spheres_cut_by_edges_and_corners(slip):
+    """A walled box (no-slip, the low x face moving along y; or free-slip x and y faces
+    with a no-slip floor): spheres cut by two or three faces at once, whose links
+    from beyond an edge or a corner take the first no-slip face they cross (or rest
+    when they cross free-slip faces only).  One step from the oracle's state within
+    the single-step bars, face forces included."""
+    n = (22, 20, 18)
+    R = np.array([3.0, 2.5, 3.5, 2.0])
+    x = np.array([[2.0, 1.9, 8.0],      # cut by the low x and low y faces
+                  [19.6, 10.0, 1.6],    # high x and low z
+                  [2.6, 17.0, 14.2],    # low x, high y, high z
+                  [11.0, 9.0, 1.2]])    # the floor alone
+    p = W.Particles(x=x, u=np.array([[0.003, -0.002, 0.0], [0.002, 0.001, -0.003], [0.0, 0.002, 0.001],
+                                     [0.001, 0.0, -0.004]]),
+                    omega=np.array([[0.0, 0.0, 0.003], [0.002, 0.0, 0.0], [0.0, -0.002, 0.0], [0.0, 0.0, 0.0]]),
+                    R=R, rho_p=np.full(4, 3.0))
+    w = W.Workload(name="corners", n=n, trt=True, tau=0.7, g=(0, 0, -1e-5), zs=-1.0, steps=0, periodic=(0, 0, 0),
+                   particles=p, contact_k=0.05, freeslip=(1, 1, 0) if slip else (0, 0, 0))
+    wall = [[[0.0] * 3, [0.0] * 3] for _ in range(3)]
+    if not slip:
+        wall[0][0][1] = 0.01  # the low x face moves along y
+    o = O.Oracle(w, wall_u=wall)
+    o.step(4)
+    fo = o.get(O.FLAGS).reshape(n[2], n[1], n[0])
+    assert (fo[:, :, 0] == O.SOL).any() and (fo[:, 0, :] == O.SOL).any() and (fo[0] == O.SOL).any()
+    s = fsl.Sim(w, wall_u=wall)
+    transfer(o, s, w)
+    o.step(1)
+    s.step(1)
+    s.sync()
+    say(compare_step(o, s, w))
+    o.close()
+    s.close()
