@@ -309,8 +309,9 @@ __device__ __noinline__ float slip_link(const Geom &G, const Phys &Ph, const Dev
 // then take the moving-wall form of Eq. bbrule).
 template <int ST, bool INTERIOR, bool MW>
 __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev &D,
-                                        const uint8_t (&tile)[3][TY + 2][TX + 2], int lx, int ly,
-                                        int x, int y, int z, bool inb) {
+                                        const uint8_t (&tile)[3][TY + 2][TX + 2],
+                                        const double (&ph)[3][TY + 2][TX + 2], int lx, int ly, int x, int y,
+                                        int z, bool inb) {
     using SS = Store<ST>;
     using T = typename SS::T;
     const int nx = G.nx, ny = G.ny, nz = G.nz, nxy = nx * ny;
@@ -488,14 +489,14 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
         const double drho_d = M.drho;
         if (fl == IFC) {
             // Eqs. (massExchange, massExchangeb), mass form, FP64
-            const double phx = D.phi_cur[c];
+            const double phx = ph[1][ly + 1][lx + 1];
             double dm = 0.0;
 #pragma unroll
             for (int q = 1; q < Q; ++q) {
                 const uint8_t nf = tile[1 + cz(q)][ly + 1 + cy(q)][lx + 1 + cx(q)];
                 if (nf == LIQ || nf == IFC) {
                     double d = (double)fi[opp(q)] - (double)fo(q);
-                    if (nf == IFC) d *= 0.5 * (D.phi_cur[nbr(q)] + phx);
+                    if (nf == IFC) d *= 0.5 * (ph[1 + cz(q)][ly + 1 + cy(q)][lx + 1 + cx(q)] + phx);
                     dm += d;
                 } else if (MW && !INTERIOR && nf == WALL) {
                     // across free-slip faces the partner is the cell beside this one
@@ -509,10 +510,7 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
                         const uint8_t pf = tile[1 + dz][ly + 1 + dy][lx + 1 + dx];
                         if (pf == LIQ || pf == IFC) {
                             double d = (double)fi[opp(q)] - (double)fo(q);
-                            if (pf == IFC) {
-                                const int pc = wrapc(x + dx, nx) + nx * wrapc(y + dy, ny) + nxy * wrapc(z + dz, nz);
-                                d *= 0.5 * (D.phi_cur[pc] + phx);
-                            }
+                            if (pf == IFC) d *= 0.5 * (ph[1 + dz][ly + 1 + dy][lx + 1 + dx] + phx);
                             dm += d;
                         }
                     }
@@ -1136,6 +1134,34 @@ __device__ __forceinline__ void build_bad_masks(const uint8_t (&tile)[3][TY + 2]
     }
 }
 
+// Fill levels of the staged tile's interface cells, with the tile's one-cell halo:
+// Eqs. (massExchange, massExchangeb) weight a link to an interface neighbour by the
+// mean of the two fill levels, so each level is read once per tile into LDS rather
+// than once per link.  Reads the staged cell types; other entries are left 0.
+__device__ __forceinline__ void stage_phi_tile(const Geom &G, const double *phi,
+                                               const uint8_t (&tile)[3][TY + 2][TX + 2],
+                                               double (&ph)[3][TY + 2][TX + 2], int x0, int y0, int z,
+                                               bool interior) {
+    constexpr int NE = 3 * (TY + 2) * (TX + 2);
+    const int nx = G.nx, ny = G.ny, nz = G.nz;
+    const uint8_t *ft = &tile[0][0][0];
+    double *fp = &ph[0][0][0];
+    for (int e = threadIdx.x; e < NE; e += 256) {
+        double v = 0.0;
+        if (ft[e] == IFC) {
+            const int lx = e % (TX + 2), r = e / (TX + 2);
+            int gx = x0 + lx - 1, gy = y0 + r % (TY + 2) - 1, gz = z + r / (TY + 2) - 1;
+            if (!interior) {  // beyond a face only along a periodic axis (a wall stages WALL)
+                gx = wrapc(gx, nx);
+                gy = wrapc(gy, ny);
+                gz = wrapc(gz, nz);
+            }
+            v = phi[gx + (long long)nx * (gy + (long long)ny * gz)];
+        }
+        fp[e] = v;
+    }
+}
+
 // The general path: interface cells and liquid cells next to gas or a moving or
 // slipping face, for the tiles (64 x 4 of one plane) that k_stream_collide listed.
 // A tile's cells are compacted and handled by as few waves as they fill (sc_cell).
@@ -1143,6 +1169,7 @@ template <int ST, bool MW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MW ? 1 : 5))) void k_general(
     Geom G, Phys Ph, Dev D, int tilesX, int tilesY, const int *gen, const int *ngen) {
     __shared__ uint8_t tile[3][TY + 2][TX + 2];
+    __shared__ double ph[3][TY + 2][TX + 2];
     __shared__ unsigned long long b3[3 * (TY + 2)], b1[3 * (TY + 2)];
     __shared__ uint8_t list[TX * TY];
     __shared__ int wcount[4];
@@ -1159,6 +1186,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MW ? 1 : 5)
         stage_flag_tile(G, D.flags, tile, x0, y0, z, interior);
         __syncthreads();
         build_bad_masks(tile, b3, b1, MW);
+        stage_phi_tile(G, (const double *)D.phi_cur, tile, ph, x0, y0, z, interior);
         __syncthreads();
         const int lx = lane, ly = wv;
         const bool inb = x0 + lx < G.nx && y0 + ly < G.ny;
@@ -1184,8 +1212,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MW ? 1 : 5)
             const bool has = (int)threadIdx.x < total;
             const int e = has ? list[threadIdx.x] : 0;
             const int ex = e & (TX - 1), ey = e >> 6;
-            if (interior) sc_cell<ST, true, MW>(G, Ph, D, tile, ex, ey, x0 + ex, y0 + ey, z, has);
-            else sc_cell<ST, false, MW>(G, Ph, D, tile, ex, ey, x0 + ex, y0 + ey, z, has);
+            if (interior) sc_cell<ST, true, MW>(G, Ph, D, tile, ph, ex, ey, x0 + ex, y0 + ey, z, has);
+            else sc_cell<ST, false, MW>(G, Ph, D, tile, ph, ex, ey, x0 + ex, y0 + ey, z, has);
         }
         __syncthreads();
     }
