@@ -379,8 +379,9 @@ __global__ __launch_bounds__(256) void k_solid_pairs(Geom G, Dev D, int pcap) {
 // e^+_q(1, u_w), and that no-slip face takes -Delta j.  The constant parts 2 w_q c_q
 // of the links into a closed node set cancel exactly; without these links a sphere
 // that covers nodes of a face layer would miss them over the cut and be pulled into
-// the face by the lattice pressure 1/3.  One wave per particle; the torque arm runs
-// from the centre to the far end of the link.
+// the face by the lattice pressure 1/3.  One wave per particle walks the face-layer
+// nodes of its node box; the torque arm runs from the centre to the far end of the
+// link.
 __global__ __launch_bounds__(256) void k_face_links(Geom G, Phys Ph, Dev D) {
     const int P = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (P >= D.np) return;
@@ -391,52 +392,64 @@ __global__ __launch_bounds__(256) void k_face_links(Geom G, Phys Ph, Dev D) {
     sphere_box(G, t + P_X, t[P_R], lo, hi);
     bool touch = false;
     for (int a = 0; a < 3; ++a)
-        if (!G.per[a] && (lo[a] == 0 || hi[a] == n[a] - 1)) touch = true;
-    if (!touch) return;
-    const int ex = hi[0] - lo[0] + 1, ey = hi[1] - lo[1] + 1, ez = hi[2] - lo[2] + 1;
-    const int tot = ex * ey * ez;
+        if (!G.per[a] && lo[a] <= hi[a] && (lo[a] == 0 || hi[a] == n[a] - 1)) touch = true;
+    if (!touch) return;  // the whole wave: no face layer in reach
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int s = lane; s < tot; s += 64) {
-        const int p[3] = {lo[0] + s % ex, lo[1] + (s / ex) % ey, lo[2] + s / (ex * ey)};
-        bool face = false;
-        for (int a = 0; a < 3; ++a)
-            if (!G.per[a] && (p[a] == 0 || p[a] == n[a] - 1)) face = true;
-        if (!face || !inside(p[0], p[1], p[2], t + P_X, t[P_R])) continue;
-        const int c = node_at(G, p[0], p[1], p[2]);
-        if (D.flags[c] != SOL || D.pid[c] != P) continue;
-        for (int q = 1; q < Q; ++q) {
-            const int f[3] = {p[0] - cx(q), p[1] - cy(q), p[2] - cz(q)};  // far end
-            int fa = -1;
-            bool crossed = false;
-            for (int a = 0; a < 3; ++a) {
-                if (G.per[a] || (f[a] >= 0 && f[a] < n[a])) continue;
-                crossed = true;
-                if (fa < 0 && !Ph.slip[a]) fa = a;
-            }
-            if (!crossed) continue;
-            const int sd = fa >= 0 && f[fa] >= 0 ? 1 : 0;
-            double u0 = 0.0, u1 = 0.0, u2 = 0.0;
-            if (fa >= 0) {
-                const float *uw = D.wallu + (fa * 2 + sd) * 3;
-                u0 = uw[0];
-                u1 = uw[1];
-                u2 = uw[2];
-            }
-            const double cu = cx(q) * u0 + cy(q) * u1 + cz(q) * u2;
-            const double e2 = 2.0 * wqd(q) * (1.0 + 4.5 * cu * cu - 1.5 * (u0 * u0 + u1 * u1 + u2 * u2));
-            const double j0 = cx(q) * e2, j1 = cy(q) * e2, j2 = cz(q) * e2;
-            const double r0 = f[0] - t[P_X], r1 = f[1] - t[P_X + 1], r2 = f[2] - t[P_X + 2];
-            acc[0] += j0;
-            acc[1] += j1;
-            acc[2] += j2;
-            acc[3] += r1 * j2 - r2 * j1;
-            acc[4] += r2 * j0 - r0 * j2;
-            acc[5] += r0 * j1 - r1 * j0;
-            if (fa >= 0 && D.wallF) {
-                double *w = D.wallF + 3 * (2 * fa + sd);
-                if (j0 != 0.0) unsafeAtomicAdd(w, -j0);
-                if (j1 != 0.0) unsafeAtomicAdd(w + 1, -j1);
-                if (j2 != 0.0) unsafeAtomicAdd(w + 2, -j2);
+    // the face layers of the walled axes that the node box reaches; a node on the
+    // layers of two axes is taken with the lower axis
+    for (int a = 0; a < 3; ++a) {
+        if (G.per[a]) continue;
+        const int b = a == 0 ? 1 : 0, d = a == 2 ? 1 : 2;  // the other two axes
+        const int eb = hi[b] - lo[b] + 1, ed = hi[d] - lo[d] + 1;
+        for (int side = 0; side < 2; ++side) {
+            const int layer = side ? n[a] - 1 : 0;
+            if (layer < lo[a] || layer > hi[a] || (side && n[a] == 1)) continue;
+            for (int s = lane; s < eb * ed; s += 64) {
+                int p[3];
+                p[a] = layer;
+                p[b] = lo[b] + s % eb;
+                p[d] = lo[d] + s / eb;
+                bool lower = false;
+                for (int k = 0; k < a; ++k)
+                    if (!G.per[k] && (p[k] == 0 || p[k] == n[k] - 1)) lower = true;
+                if (lower || !inside(p[0], p[1], p[2], t + P_X, t[P_R])) continue;
+                const int c = node_at(G, p[0], p[1], p[2]);
+                if (D.flags[c] != SOL || D.pid[c] != P) continue;
+                for (int q = 1; q < Q; ++q) {
+                    const int f[3] = {p[0] - cx(q), p[1] - cy(q), p[2] - cz(q)};  // far end
+                    int fa = -1;
+                    bool crossed = false;
+                    for (int k = 0; k < 3; ++k) {
+                        if (G.per[k] || (f[k] >= 0 && f[k] < n[k])) continue;
+                        crossed = true;
+                        if (fa < 0 && !Ph.slip[k]) fa = k;
+                    }
+                    if (!crossed) continue;
+                    const int sd = fa >= 0 && f[fa] >= 0 ? 1 : 0;
+                    double u0 = 0.0, u1 = 0.0, u2 = 0.0;
+                    if (fa >= 0) {
+                        const float *uw = D.wallu + (fa * 2 + sd) * 3;
+                        u0 = uw[0];
+                        u1 = uw[1];
+                        u2 = uw[2];
+                    }
+                    const double cu = cx(q) * u0 + cy(q) * u1 + cz(q) * u2;
+                    const double e2 = 2.0 * wqd(q) * (1.0 + 4.5 * cu * cu - 1.5 * (u0 * u0 + u1 * u1 + u2 * u2));
+                    const double j0 = cx(q) * e2, j1 = cy(q) * e2, j2 = cz(q) * e2;
+                    const double r0 = f[0] - t[P_X], r1 = f[1] - t[P_X + 1], r2 = f[2] - t[P_X + 2];
+                    acc[0] += j0;
+                    acc[1] += j1;
+                    acc[2] += j2;
+                    acc[3] += r1 * j2 - r2 * j1;
+                    acc[4] += r2 * j0 - r0 * j2;
+                    acc[5] += r0 * j1 - r1 * j0;
+                    if (fa >= 0 && D.wallF) {
+                        double *w = D.wallF + 3 * (2 * fa + sd);
+                        if (j0 != 0.0) unsafeAtomicAdd(w, -j0);
+                        if (j1 != 0.0) unsafeAtomicAdd(w + 1, -j1);
+                        if (j2 != 0.0) unsafeAtomicAdd(w + 2, -j2);
+                    }
+                }
             }
         }
     }

@@ -326,11 +326,6 @@ __device__ __forceinline__ void sc_cell(const Geom &G, const Phys &Ph, const Dev
         const int sx = wrapc(x - cx(q), nx), sy = wrapc(y - cy(q), ny), sz = wrapc(z - cz(q), nz);
         return sx + nx * sy + nxy * sz;
     };
-    auto nbr = [&](int q) -> int {
-        if (INTERIOR) return c + (cx(q) + cy(q) * nx + cz(q) * nxy);
-        const int sx = wrapc(x + cx(q), nx), sy = wrapc(y + cy(q), ny), sz = wrapc(z + cz(q), nz);
-        return sx + nx * sy + nxy * sz;
-    };
 
     LinkAcc acc;
     acc.P = -1;
