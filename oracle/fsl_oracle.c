@@ -11,7 +11,9 @@
  *      half-way bounce-back at box walls, by the moving-wall bounce-back rule
  *      Eq. (bbrule) at particle links and by the free-surface condition Eq. (fsk)
  *      at gas links; momentum exchange Eqs. (netforce), (torque),
- *      (momentum_transfer) at particle links;
+ *      (momentum_transfer) at particle links, at links from nodes of another
+ *      particle and (a reading) at links from beyond the box faces, and at the
+ *      no-slip faces themselves (the plate force);
  *   2. moments (Sec. 2.1), with the Guo half-force shift of the velocity;
  *   3. interface mass exchange Eqs. (massExchange), (massExchangeb);
  *   4. TRT collision Eq. (LBE2) with the equilibrium Eq. (equilibrium) and the
@@ -19,8 +21,10 @@
  *   5. cell conversions of Fig. (cellConversions) with the closure of the
  *      interface layer, equilibrium initialisation of new interface cells and
  *      excess-mass redistribution;
- *   6. particle update: lubrication correction Eq. (lubrication) and up to ten
- *      substeps per lattice step (Sec. 2.3), then the obstacle-coverage update;
+ *   6. particle update: lubrication correction Eq. (lubrication) between
+ *      spheres and (a reading) at no-slip faces, a contact spring (a reading),
+ *      and up to ten substeps per lattice step (Sec. 2.3), then the
+ *      obstacle-coverage update;
  *   7. bubble model (end of Sec. 2.2): per-bubble volume, constant gas mass,
  *      gas density = mass / volume; a bubble whose gas falls apart splits.
  * Where the paper is silent the reading used is stated at the place it is used.
