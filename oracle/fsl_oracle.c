@@ -30,8 +30,9 @@
  * Where the paper is silent the reading used is stated at the place it is used.
  * Parity-pinned parts are listed in the tests; the conversion rules (reading
  * of the fill thresholds, conflict rule, G->I initial state, excess split), the
- * bubble merge and the cover/uncover bookkeeping are "parity unpinned" beyond
- * conservation and the invariants checked in the tests.
+ * bubble merge and the cover/uncover bookkeeping next to gas are "parity
+ * unpinned" beyond conservation and the invariants checked in the tests (the
+ * cover/uncover bookkeeping in liquid is pinned on a closed form).
  *
  * Build: cc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no intrinsics).
  */
