@@ -117,3 +117,31 @@ def test_helper_libraries_export_their_headers(lib_name, header, expected):
     L = ctypes.CDLL(path)
     for n in names:
         assert hasattr(L, n), n
+
+
+@pytest.mark.parametrize("cname,pyname", [("fsl_config", "FslConfig"), ("fsl_bubble", "FslBubble")])
+def test_binding_structs_match_header_layout(tmp_path, cname, pyname):
+    """The ctypes structures of the binding have the size and the member offsets that
+    a C compiler gives the header's structs (a member added on one side only, or in
+    another order, would otherwise shift every later field without an error)."""
+    import shutil
+    import subprocess
+
+    import paper_1712_07028_amd as fsl
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    py = getattr(fsl, pyname)
+    names = [f[0] for f in py._fields_]
+    body = "\n".join(f'    printf("{n} %zu\\n", offsetof({cname}, {n}));' for n in names)
+    src = tmp_path / "layout.c"
+    src.write_text(f'#include <stddef.h>\n#include <stdio.h>\n#include "fsl.h"\nint main(void) {{\n'
+                   f'    printf("sizeof %zu\\n", sizeof({cname}));\n{body}\n    return 0;\n}}\n')
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                         text=True).stdout.splitlines())
+    assert int(out["sizeof"]) == ctypes.sizeof(py)
+    for n in names:
+        assert int(out[n]) == getattr(py, n).offset, n
