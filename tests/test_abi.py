@@ -119,27 +119,34 @@ def test_helper_libraries_export_their_headers(lib_name, header, expected):
         assert hasattr(L, n), n
 
 
-@pytest.mark.parametrize("cname,pyname", [("fsl_config", "FslConfig"), ("fsl_bubble", "FslBubble")])
-def test_binding_structs_match_header_layout(tmp_path, cname, pyname):
-    """The ctypes structures of the binding have the size and the member offsets that
-    a C compiler gives the header's structs (a member added on one side only, or in
-    another order, would otherwise shift every later field without an error)."""
+@pytest.mark.parametrize("module,header,cname,pyname", [
+    ("paper_1712_07028_amd", "include/fsl.h", "fsl_config", "FslConfig"),
+    ("paper_1712_07028_amd", "include/fsl.h", "fsl_bubble", "FslBubble"),
+    ("oracle", "oracle/fsl_oracle.h", "orc_config", "OrcConfig"),
+    ("oracle", "oracle/fsl_oracle.h", "orc_bubble", "OrcBubble"),
+])
+def test_binding_structs_match_header_layout(tmp_path, module, header, cname, pyname):
+    """The ctypes structures of the library's binding (and of the oracle's) have the
+    size and the member offsets that a C compiler gives the header's structs (a
+    member added on one side only, or in another order, would otherwise shift every
+    later field without an error)."""
+    import importlib
     import shutil
     import subprocess
-
-    import paper_1712_07028_amd as fsl
 
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
-    py = getattr(fsl, pyname)
+    py = getattr(importlib.import_module(module), pyname)
     names = [f[0] for f in py._fields_]
     body = "\n".join(f'    printf("{n} %zu\\n", offsetof({cname}, {n}));' for n in names)
     src = tmp_path / "layout.c"
-    src.write_text(f'#include <stddef.h>\n#include <stdio.h>\n#include "fsl.h"\nint main(void) {{\n'
+    src.write_text(f'#include <stddef.h>\n#include <stdint.h>\n#include <stdio.h>\n'
+                   f'#include "{os.path.basename(header)}"\nint main(void) {{\n'
                    f'    printf("sizeof %zu\\n", sizeof({cname}));\n{body}\n    return 0;\n}}\n')
     exe = tmp_path / "layout"
-    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    inc = os.path.join(ROOT, os.path.dirname(header))
+    subprocess.run([cc, "-std=c99", "-I", inc, "-o", str(exe), str(src)], check=True)
     out = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
                                                          text=True).stdout.splitlines())
     assert int(out["sizeof"]) == ctypes.sizeof(py)
