@@ -552,7 +552,7 @@ def main():
         "config": {"workload": w.name, "box": list(w.n),
                    "particles": w.particles.n if w.particles is not None else 0,
                    "collision": "TRT" if w.trt else "SRT", "tau": w.tau,
-                   "storage": args.storage, "step_ms_breakdown": breakdown},
+                   "storage": args.storage, "face_forces": False, "step_ms_breakdown": breakdown},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
